@@ -1,0 +1,183 @@
+"""Plain FP64 CPU oracle for the lattice-Boltzmann phase-field scheme of
+Cartalade, Younsi & Plapp (arXiv:1602.07483).
+
+TEST INFRASTRUCTURE ONLY: imported by the tests, by the package smoke check and
+by the CPU-baseline leg of the benchmark.  The product library never imports
+it.  The arithmetic lives in ``lbpf_oracle.c``; this module only marshals
+numpy arrays through ctypes.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "liblbpf_oracle.so")
+
+WALL_NOFLUX = 0
+WALL_SYMMETRY = 1
+ANISO_CUBIC = 0
+ANISO_K41K61 = 1
+
+R_SOLID, R_MASS, R_ENTHALPY, R_TIPX, R_TIPY, R_TIPZ, R_PHIMIN, R_PHIMAX, \
+    R_NONFINITE, R_SUMU, R_SUMPHI, R_COUNT = range(12)
+
+
+class OrcParams(ctypes.Structure):
+    _fields_ = [
+        ("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
+        ("lattice", ctypes.c_int32), ("wall", ctypes.c_int32 * 6),
+        ("dx", ctypes.c_double), ("dt", ctypes.c_double),
+        ("W0", ctypes.c_double), ("tau0", ctypes.c_double),
+        ("lam", ctypes.c_double), ("Mcinf", ctypes.c_double),
+        ("k", ctypes.c_double), ("D", ctypes.c_double), ("kappa", ctypes.c_double),
+        ("aniso", ctypes.c_int32), ("eps", ctypes.c_double), ("delta", ctypes.c_double),
+    ]
+
+
+_lib = None
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB_PATH):
+        from . import build as _b
+        _b.build()
+    lib = ctypes.CDLL(_LIB_PATH)
+    P = ctypes.POINTER
+    dp = P(ctypes.c_double)
+    lib.orc_create.restype = ctypes.c_void_p
+    lib.orc_create.argtypes = [P(OrcParams)]
+    lib.orc_destroy.argtypes = [ctypes.c_void_p]
+    lib.orc_init.argtypes = [ctypes.c_void_p, dp, dp, dp]
+    lib.orc_step.argtypes = [ctypes.c_void_p, ctypes.c_int64]
+    lib.orc_stream_only.argtypes = [ctypes.c_void_p, ctypes.c_int64]
+    lib.orc_fields.argtypes = [ctypes.c_void_p, dp, dp, dp]
+    lib.orc_get_pops.argtypes = [ctypes.c_void_p, ctypes.c_int, dp]
+    lib.orc_set_pops.argtypes = [ctypes.c_void_p, ctypes.c_int, dp]
+    lib.orc_reduce.argtypes = [ctypes.c_void_p, dp, dp]
+    lib.orc_step_count.restype = ctypes.c_int64
+    lib.orc_step_count.argtypes = [ctypes.c_void_p]
+    lib.orc_lattice.argtypes = [ctypes.c_int, P(ctypes.c_int32), dp, dp, dp, dp]
+    lib.orc_anisotropy.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_double,
+                                   dp, dp, dp]
+    lib.orc_geq.argtypes = [ctypes.c_int, ctypes.c_double, dp, ctypes.c_double, dp]
+    lib.orc_heq.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_double, dp,
+                            ctypes.c_double, dp]
+    _lib = lib
+    return lib
+
+
+def _dptr(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def lattice(q):
+    """(e [q,3] int, w, A, B, e2) as typed in the oracle."""
+    lib = _load()
+    e = np.zeros((q, 3), dtype=np.int32)
+    w = np.zeros(q); A = np.zeros(q); B = np.zeros(q); e2 = ctypes.c_double()
+    rc = lib.orc_lattice(q, e.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                         _dptr(w), _dptr(A), _dptr(B), ctypes.byref(e2))
+    if rc:
+        raise ValueError("unsupported lattice %r" % q)
+    return e, w, A, B, e2.value
+
+
+def anisotropy(p, aniso=ANISO_CUBIC, eps=0.05, delta=0.0):
+    """a_s and the vector N for the gradient p (3 doubles)."""
+    lib = _load()
+    p = _f64(p)
+    a = ctypes.c_double()
+    N = np.zeros(3)
+    lib.orc_anisotropy(aniso, eps, delta, _dptr(p), ctypes.byref(a), _dptr(N))
+    return a.value, N
+
+
+def geq(q, phi, N, cphi):
+    lib = _load()
+    out = np.zeros(q)
+    lib.orc_geq(q, float(phi), _dptr(_f64(N)), float(cphi), _dptr(out))
+    return out
+
+
+def heq(q, U, r, J, dt_over_dx):
+    lib = _load()
+    out = np.zeros(q)
+    lib.orc_heq(q, float(U), float(r), _dptr(_f64(J)), float(dt_over_dx), _dptr(out))
+    return out
+
+
+class Oracle:
+    """One domain advanced by the FP64 oracle.  Fields are numpy arrays of
+    shape (nz, ny, nx); populations (Q, nz, ny, nx)."""
+
+    def __init__(self, nx, ny, nz, lattice=19, walls=(0,) * 6, dx=1.0, dt=1.0,
+                 W0=1.0, tau0=1.0, lam=3.2, Mcinf=1.0, k=0.15, D=2.0, kappa=20.0,
+                 aniso=ANISO_CUBIC, eps=0.05, delta=0.0):
+        lib = _load()
+        p = OrcParams()
+        p.nx, p.ny, p.nz = int(nx), int(ny), int(nz)
+        p.lattice = int(lattice)
+        for i, wv in enumerate(walls):
+            p.wall[i] = int(wv)
+        p.dx, p.dt, p.W0, p.tau0 = dx, dt, W0, tau0
+        p.lam, p.Mcinf, p.k, p.D, p.kappa = lam, Mcinf, k, D, kappa
+        p.aniso, p.eps, p.delta = int(aniso), eps, delta
+        self.params = p
+        self.shape = (int(nz), int(ny), int(nx))
+        self.q = int(lattice)
+        self._h = lib.orc_create(ctypes.byref(p))
+        if not self._h:
+            raise ValueError("oracle rejected the parameters")
+        self._lib = lib
+
+    def close(self):
+        if self._h:
+            self._lib.orc_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def init(self, phi, U, theta):
+        a = [_f64(v).reshape(self.shape) for v in (phi, U, theta)]
+        self._lib.orc_init(self._h, _dptr(a[0]), _dptr(a[1]), _dptr(a[2]))
+
+    def step(self, n=1):
+        self._lib.orc_step(self._h, int(n))
+
+    def stream_only(self, n=1):
+        self._lib.orc_stream_only(self._h, int(n))
+
+    @property
+    def steps(self):
+        return self._lib.orc_step_count(self._h)
+
+    def fields(self):
+        out = [np.zeros(self.shape) for _ in range(3)]
+        self._lib.orc_fields(self._h, _dptr(out[0]), _dptr(out[1]), _dptr(out[2]))
+        return out
+
+    def pops(self, field):
+        out = np.zeros((self.q,) + self.shape)
+        self._lib.orc_get_pops(self._h, int(field), _dptr(out))
+        return out
+
+    def set_pops(self, field, arr):
+        a = _f64(arr).reshape((self.q,) + self.shape)
+        self._lib.orc_set_pops(self._h, int(field), _dptr(a))
+
+    def reduce(self, centre=(0.0, 0.0, 0.0)):
+        out = np.zeros(R_COUNT)
+        self._lib.orc_reduce(self._h, _dptr(_f64(centre)), _dptr(out))
+        return out

@@ -1,0 +1,150 @@
+"""Seeded synthetic inputs: initial fields and the workload definitions.
+
+This module holds no lattice-Boltzmann arithmetic.  It builds the initial
+condition of Sec. 4 of Cartalade, Younsi & Plapp (arXiv:1602.07483): diffuse
+spherical nuclei phi = tanh((R - d)/(sqrt(2) W0)) in an undercooled melt with
+constant U0 and theta0, optionally with seeded uniform noise on U.  The same
+arrays feed the GPU library and the FP64 oracle.
+
+Noise: u = SplitMix64(seed, linear node index) mapped to a double in [0, 1),
+the published SplitMix64 finaliser (Steele, Lea & Flood, OOPSLA 2014).
+"""
+from dataclasses import dataclass, field, asdict
+from typing import List, Sequence, Tuple
+
+import numpy as np
+
+NOFLUX = 0
+SYMMETRY = 1
+
+_M64 = np.uint64(0xFFFFFFFFFFFFFFFF)
+
+
+def splitmix64(seed: int, index: np.ndarray) -> np.ndarray:
+    """SplitMix64 output for state seed + (index+1) * golden gamma."""
+    with np.errstate(over="ignore"):
+        z = (np.uint64(seed) + (index.astype(np.uint64) + np.uint64(1))
+             * np.uint64(0x9E3779B97F4A7C15))
+        z = (z ^ (z >> np.uint64(30))) * np.uint64(0xBF58476D1CE4E5B9)
+        z = (z ^ (z >> np.uint64(27))) * np.uint64(0x94D049BB133111EB)
+        z = z ^ (z >> np.uint64(31))
+    return z
+
+
+def uniform01(seed: int, n: int) -> np.ndarray:
+    """n doubles in [0, 1) from the top 53 bits of SplitMix64."""
+    z = splitmix64(seed, np.arange(n, dtype=np.uint64))
+    return (z >> np.uint64(11)).astype(np.float64) * (1.0 / 9007199254740992.0)
+
+
+def sphere_field(shape: Tuple[int, int, int], centres: Sequence[Sequence[float]],
+                 radius: float, W0: float = 1.0, dx: float = 1.0) -> np.ndarray:
+    """phi0 = max over seeds of tanh((R - d)/(sqrt(2) W0)), d the distance to
+    the seed centre; centres and R in node-index (lattice) units; shape is
+    (nz, ny, nx)."""
+    nz, ny, nx = shape
+    z, y, x = np.meshgrid(np.arange(nz, dtype=np.float64), np.arange(ny, dtype=np.float64),
+                          np.arange(nx, dtype=np.float64), indexing="ij")
+    phi = np.full(shape, -1.0)
+    for c in centres:
+        d = np.sqrt((x - c[0]) ** 2 + (y - c[1]) ** 2 + (z - c[2]) ** 2)
+        phi = np.maximum(phi, np.tanh((radius - d) * dx / (np.sqrt(2.0) * W0)))
+    return phi
+
+
+@dataclass
+class Problem:
+    """One domain: grid, walls, model parameters and initial condition."""
+    name: str
+    nx: int
+    ny: int
+    nz: int
+    lattice: int = 19
+    walls: Tuple[int, ...] = (NOFLUX,) * 6          # -x,+x,-y,+y,-z,+z
+    dx: float = 1.0
+    dt: float = 1.0
+    W0: float = 1.0
+    tau0: float = 1.0
+    lam: float = 3.2
+    Mcinf: float = 1.0
+    k: float = 0.15
+    D: float = 2.0
+    kappa: float = 20.0
+    aniso: int = 0
+    eps: float = 0.05
+    delta: float = 0.0
+    # initial condition
+    centres: List[Tuple[float, float, float]] = field(default_factory=list)
+    radius: float = 5.0
+    U0: float = -0.55
+    theta0: float = -0.55
+    noise_amp: float = 0.0
+    noise_seed: int = 0
+    steps: int = 100
+    reduce_every: int = 0
+
+    @property
+    def shape(self):
+        return (self.nz, self.ny, self.nx)
+
+    @property
+    def nodes(self):
+        return self.nx * self.ny * self.nz
+
+    def centre(self):
+        """Reference point of the tip measurement (first seed)."""
+        return tuple(self.centres[0]) if self.centres else (0.0, 0.0, 0.0)
+
+    def model_kwargs(self):
+        d = asdict(self)
+        keys = ("lattice", "walls", "dx", "dt", "W0", "tau0", "lam", "Mcinf", "k", "D",
+                "kappa", "aniso", "eps", "delta")
+        return {kk: d[kk] for kk in keys}
+
+    def initial_fields(self):
+        """(phi0, U0, theta0) as float64 arrays of shape (nz, ny, nx)."""
+        phi = sphere_field(self.shape, self.centres, self.radius, self.W0, self.dx)
+        U = np.full(self.shape, self.U0)
+        if self.noise_amp:
+            u = uniform01(self.noise_seed, self.nodes).reshape(self.shape)
+            U = U + self.noise_amp * (2.0 * u - 1.0)
+        th = np.full(self.shape, self.theta0)
+        return phi, U, th
+
+
+# --------------------------------------------------------------------------
+# Workloads.  Units W0 = tau0 = 1 with dx = W0 (one node per interface width).
+# Parameters the workload statements leave open are fixed here and listed in
+# the design notes: Mc_inf = 1, D = 2, lambda = 3.2 (the paper's alloy
+# benchmark, Sec. 4.2), kappa = 10 D, theta0 = -Delta.  The time step is the
+# paper's 3D ratio dt/tau0 = 0.15 (Sec. 4.1): dt = tau0 makes the explicit
+# reaction term unstable wherever a_s < 1 (amplification 1 - 2 dt/(tau0 a_s^2)
+# < -1) and D = 2 per unit time step makes the U scheme unstable.
+# --------------------------------------------------------------------------
+DT = 0.15
+CORNER = (-0.5, -0.5, -0.5)
+SEED_FACES = (SYMMETRY, NOFLUX, SYMMETRY, NOFLUX, SYMMETRY, NOFLUX)
+
+
+def workload_small(steps: int = 300, n: int = 32) -> Problem:
+    """32^3 D3Q19, sphere R=5 at the corner, symmetry walls on the seed faces,
+    no-flux elsewhere, U noise 1e-3 (seed 1)."""
+    return Problem("corner-%d" % n, n, n, n, 19, SEED_FACES, dt=DT, eps=0.05,
+                   k=0.15, U0=-0.55, theta0=-0.55, centres=[CORNER], radius=5.0,
+                   noise_amp=1e-3, noise_seed=1, steps=steps, reduce_every=10)
+
+
+def workload_octant(n: int = 128, steps: int = 5000) -> Problem:
+    """n^3 D3Q19 octant dendrite, R=8 at the corner, walls and noise as the
+    small case, kappa/D = 10."""
+    return Problem("octant-%d" % n, n, n, n, 19, SEED_FACES, dt=DT, eps=0.05,
+                   k=0.15, U0=-0.55, theta0=-0.55, centres=[CORNER], radius=8.0,
+                   noise_amp=1e-3, noise_seed=2, steps=steps, reduce_every=100)
+
+
+def workload_centred(n: int = 256, steps: int = 10000) -> Problem:
+    """n^3 D3Q19, centred seed R=10, all walls no-flux, Delta=0.6, no noise."""
+    c = (n - 1) / 2.0
+    return Problem("centred-%d" % n, n, n, n, 19, (NOFLUX,) * 6, dt=DT, eps=0.05,
+                   k=0.15, U0=-0.6, theta0=-0.6, centres=[(c, c, c)], radius=10.0,
+                   steps=steps, reduce_every=100)

@@ -1,0 +1,200 @@
+/*
+ * lbpf.h -- C ABI of the MI355X (gfx950) lattice-Boltzmann phase-field library.
+ *
+ * The library advances the three-field phase-field model of dilute binary-alloy
+ * solidification of Cartalade, Younsi & Plapp, "Lattice Boltzmann simulations
+ * of 3D crystal growth: numerical schemes for a phase-field model with
+ * anti-trapping current" (arXiv:1602.07483):
+ *   phase field phi       -- Sec. 3.2, non-local BGK scheme, eq. (LBE_Eq_Phase),
+ *                            equilibrium eq. (Feq_Phase), source eq. (LBE_SourceTerm),
+ *                            relaxation time eq. (LBE_RelaxationTime);
+ *   supersaturation U     -- Sec. 3.3, reformulated equation (Supersaturation_Bis),
+ *                            BGK scheme eq. (LBE_Eq_Transport), equilibrium
+ *                            eq. (Feq_Transport), relaxation eq. (RelaxationTime_Concentration);
+ *   temperature theta     -- Sec. 3.1, BGK scheme eq. (LBE_Eq_Temp) with
+ *                            eqs. (EqFunction_Tempr), (Source_Tempr), (ThermalDiffusivity);
+ * on the D3Q15 or D3Q19 lattice (Sec. 3.4, Tables 1 and 2), in the order of
+ * Sec. 3.4 "Algorithm implementation": phi first, then U and theta with the
+ * new phi; split collision (eq. Collision_Stage) and streaming
+ * (eq. Deplacement_STD); bounce-back walls.
+ *
+ * Conventions
+ *  - Every call returns an lbpf_status (0 = success, < 0 = error).  After an
+ *    error, lbpf_last_error(ctx) describes it.
+ *  - Host field arrays are double, shape [nz][ny][nx] with x fastest
+ *    ("canonical layout"), owned by the caller; the library copies them.
+ *  - The context owns all device memory.  It is created on the current HIP
+ *    device and runs on the borrowed HIP stream given at creation (NULL = the
+ *    null stream).  A context is not thread-safe; one context per stream.
+ *  - Work is asynchronous on that stream except where a call says it
+ *    synchronises.
+ *  - Units: the model parameters are in the paper's (physical) units, the
+ *    node spacing is dx and the time step dt.  Positions returned by the
+ *    reductions are in node-index units.
+ */
+#ifndef LBPF_H
+#define LBPF_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct lbpf_ctx lbpf_ctx;
+
+typedef enum {
+    LBPF_OK = 0,
+    LBPF_EINVAL = -1,     /* invalid argument or parameter set */
+    LBPF_ENOMEM = -2,     /* device or host allocation failed */
+    LBPF_EDEVICE = -3,    /* a HIP runtime call failed */
+    LBPF_EUNSTABLE = -4,  /* health check failed: non-finite value or |phi| > 1 + 1e-3 */
+    LBPF_ESTATE = -5      /* call out of order (e.g. step before set_fields) */
+} lbpf_status;
+
+typedef enum { LBPF_D3Q15 = 15, LBPF_D3Q19 = 19 } lbpf_lattice;
+
+/* Walls lie half a link outside the first/last node of each axis. */
+typedef enum {
+    LBPF_WALL_NOFLUX = 0,    /* half-way bounce-back (zero flux, Sec. 4) */
+    LBPF_WALL_SYMMETRY = 1   /* mirror plane: specular reflection */
+} lbpf_wall;
+
+/* How the populations are stored in HBM.  Every type stores the deviation of
+ * each population from its rest equilibrium (w_i phi, (A_i + B_i q/zeta) U,
+ * w_i theta) and updates it in increment form.  Arithmetic is FP32 except F64. */
+typedef enum {
+    LBPF_F32 = 0,       /* FP32 deviations, FP32 fields and collision */
+    LBPF_F16_DEV = 1,   /* FP16 deviations, FP32 fields and collision */
+    LBPF_BF16_DEV = 2,  /* BF16 deviations, FP32 fields and collision */
+    LBPF_F64 = 3        /* FP64 everywhere (verification build) */
+} lbpf_storage;
+
+typedef enum {
+    LBPF_ANISO_CUBIC = 0,   /* eq. (Anisotropic-Function_As): 1 - 3 eps + 4 eps sum n^4 */
+    LBPF_ANISO_K41K61 = 1   /* eq. (As_K41-K61): cubic harmonics K41 (eps) + K61 (delta) */
+} lbpf_aniso;
+
+typedef struct {
+    int32_t nx, ny, nz;     /* nodes per axis, each >= 1 */
+    int32_t lattice;        /* lbpf_lattice */
+    int32_t wall[6];        /* lbpf_wall for faces -x,+x,-y,+y,-z,+z */
+    int32_t storage;        /* lbpf_storage */
+} lbpf_grid;
+
+typedef struct {
+    double dx, dt;          /* node spacing, time step */
+    double W0, tau0;        /* interface width, phase-field time scale */
+    double lambda;          /* coupling constant of eq. (PhaseField_KarmaRappel) */
+    double Mcinf;           /* M c_inf, scaled liquidus slope */
+    double k;               /* partition coefficient, 0 < k < 1 */
+    double D, kappa;        /* solute and thermal diffusivities */
+    int32_t aniso;          /* lbpf_aniso */
+    double eps, delta;      /* anisotropy strengths (delta used by K41K61 only) */
+    int32_t reduce_every;   /* >0: record the reductions every that many steps */
+    double centre[3];       /* reference point of the tip positions (node units) */
+} lbpf_params;
+
+/* Diagnostics of one state, accumulated in FP64 on the device.  The paper
+ * defines only the tip velocity (Sec. 4.1); the others are conservation and
+ * health checks: solute content from the definition of U in Sec. 2,
+ * c/c_inf = zeta(phi)(1 + (1-k)U). */
+typedef struct {
+    int64_t step;             /* time steps taken when the record was made */
+    double solid_fraction;    /* mean of (1 + phi)/2 */
+    double solute_mass;       /* sum of zeta(phi)(1 + (1-k)U) dx^3 */
+    double enthalpy;          /* sum of (theta - phi/2) dx^3, conserved exactly */
+    double tip[3];            /* furthest phi=0 crossing along +x,+y,+z minus centre
+                                 (linear interpolation between nodes; NaN if none) */
+    double phi_min, phi_max;
+    double nonfinite;         /* count of non-finite phi, U, theta values */
+    double sum_U, sum_phi;    /* sums of U and phi, times dx^3 */
+} lbpf_reductions;
+
+/* Create a context: validates the parameters, allocates the populations
+ * (two lattices per field), the fields and the reduction buffers on the
+ * current device.  Errors: EINVAL (n < 1, unsupported lattice or storage,
+ * k not in (0,1), dx, dt, W0, tau0 <= 0, D or kappa < 0, eps outside
+ * [0, 0.25]), ENOMEM, EDEVICE.  *out is NULL on error. */
+lbpf_status lbpf_create(const lbpf_grid* grid, const lbpf_params* params,
+                        void* hip_stream, lbpf_ctx** out);
+
+/* Release every device buffer owned by the context.  NULL is accepted. */
+lbpf_status lbpf_destroy(lbpf_ctx* ctx);
+
+/* Load the initial fields (host, canonical layout, nx*ny*nz doubles each) and
+ * set every population to its equilibrium (phi: eq. Feq_Phase with N from
+ * grad phi; U: eq. Feq_Transport with the anti-trapping current zero; theta:
+ * eq. EqFunction_Tempr).  Resets the step counter and the history.
+ * Synchronises the stream.  Errors: EINVAL (NULL array), EDEVICE. */
+lbpf_status lbpf_set_fields(lbpf_ctx* ctx, const double* phi, const double* U,
+                            const double* theta);
+
+/* Advance nsteps >= 0 time steps, asynchronously on the context stream.  When
+ * reduce_every > 0 a reduction record is appended to the history after every
+ * step whose count is a multiple of reduce_every.  Errors: ESTATE (no fields
+ * yet), EINVAL (nsteps < 0), EDEVICE. */
+lbpf_status lbpf_step(lbpf_ctx* ctx, int64_t nsteps);
+
+/* Wait for the stream, then check the most recent history record, if any:
+ * returns EUNSTABLE when it holds a non-finite value or |phi| > 1 + 1e-3. */
+lbpf_status lbpf_sync(lbpf_ctx* ctx);
+
+/* Copy the current fields to host arrays (each may be NULL to skip it) and,
+ * when red != NULL, compute a fresh reduction record of the current state.
+ * Synchronises the stream.  Returns EUNSTABLE (after copying) when that
+ * record fails the health check. */
+lbpf_status lbpf_read(lbpf_ctx* ctx, double* phi, double* U, double* theta,
+                      lbpf_reductions* red);
+
+/* Copy up to max_records history records, oldest first, into out; *count
+ * receives the number copied.  The history keeps the latest 8192 records.
+ * Synchronises the stream. */
+lbpf_status lbpf_history(lbpf_ctx* ctx, lbpf_reductions* out, int32_t max_records,
+                         int32_t* count);
+
+/* Raw stored population bits of one field (0 = g/phi, 1 = h/U, 2 = f/theta),
+ * layout [Q][nz][ny][nx], in the storage type.  Every storage type holds the
+ * deviation of each population from its rest equilibrium (w_i phi,
+ * (A_i + B_i q(phi)/zeta(phi)) U, w_i theta), so the stored state is the pair
+ * (fields, deviations): a checkpoint is lbpf_read of the fields plus these
+ * three arrays; a restore is lbpf_set_fields of the saved fields followed by
+ * the three writes.  The size of dst/src is Q*nx*ny*nz*lbpf_storage_bytes.
+ * Both synchronise; the fields are not changed by a write.
+ * Errors: EINVAL (bad field, NULL), ESTATE (write before set_fields). */
+lbpf_status lbpf_read_populations(lbpf_ctx* ctx, int32_t field, void* dst);
+lbpf_status lbpf_write_populations(lbpf_ctx* ctx, int32_t field, const void* src);
+
+/* Full populations (deviation + rest equilibrium) of one field in FP64,
+ * layout [Q][nz][ny][nx], for inspection.  Allocates a temporary device
+ * buffer of Q*nx*ny*nz doubles; synchronises.  Errors as above, ENOMEM. */
+lbpf_status lbpf_read_populations_f64(lbpf_ctx* ctx, int32_t field, double* dst);
+
+/* Streaming only (collision = identity) of all three population sets, raw
+ * bits, with the wall rules: checks the index mapping.  Asynchronous. */
+lbpf_status lbpf_debug_stream_only(lbpf_ctx* ctx, int64_t nsteps);
+
+/* Per-kernel timing with HIP events recorded on the context stream around
+ * each launch.  Enabling resets the accumulators.  lbpf_kernel_times
+ * synchronises and returns the summed milliseconds and launch counts of the
+ * phase-field kernel (index 0), the supersaturation/heat kernel (1) and the
+ * reduction kernels (2). */
+lbpf_status lbpf_set_timing(lbpf_ctx* ctx, int32_t enable);
+lbpf_status lbpf_kernel_times(lbpf_ctx* ctx, double ms[3], int64_t launches[3]);
+
+/* Bytes of one stored population for a storage type (0 if invalid). */
+int32_t lbpf_storage_bytes(int32_t storage);
+
+/* Plain device-to-device copy kernel of nbytes (multiple of 16, 16-byte
+ * aligned pointers) on hip_stream, used as the bandwidth reference of the
+ * benchmark.  Asynchronous.  Errors: EINVAL, EDEVICE. */
+lbpf_status lbpf_bench_copy(void* dst, const void* src, int64_t nbytes, void* hip_stream);
+
+/* Description of the last error on ctx (or of the last failed creation when
+ * ctx is NULL); valid until the next call on the same context. */
+const char* lbpf_last_error(const lbpf_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LBPF_H */

@@ -1,0 +1,731 @@
+// kernels.hpp -- gfx950 kernels of one lattice-Boltzmann phase-field time step.
+//
+// Method: Cartalade, Younsi & Plapp (arXiv:1602.07483).  Phase field, Sec. 3.2
+// and the collision stage of Sec. 3.4 (eq. Collision_Stage); supersaturation,
+// Sec. 3.3 (eqs. Supersaturation_Bis, Def_Jtot, Def_S, Def_Qu, LBE_Eq_Transport,
+// Feq_Transport); temperature, Sec. 3.1 (eqs. LBE_Eq_Temp, EqFunction_Tempr,
+// Source_Tempr); anti-trapping current, Sec. 2 (eq. AntiTrapping_Current).
+//
+// GPU formulation (same arithmetic as the paper's collide-then-stream, arranged
+// for HBM bandwidth):
+//  * Pull form, two lattices.  Thread x gathers g_i^{n+1}(x) = g_j*(y) from the
+//    source node y of the incoming link (y = x - e_i inside the domain, the
+//    node itself after bounce-back, the mirror node after a symmetry wall) and
+//    evaluates that source's collision on the fly.  The non-local population
+//    g_i(y + e_i, t) of eq. (Collision_Stage) is then always the destination's
+//    own old population g_i^n(x), so the two reads per link are one shifted
+//    and one aligned load of the same array.  Writing g^{n+1}(x) for all i
+//    at once also yields phi^{n+1}(x) = sum_i g_i^{n+1}(x) in the same kernel.
+//  * Node terms (a_s, N, eta_phi, Q_phi for phi; J_tot, S, Q_U/zeta, Q_theta for
+//    U/theta) are computed once per node for the tile plus a one-node halo
+//    and kept in LDS; the stencil fields (phi^n, resp. phi^{n+1}) are staged in
+//    LDS with a two-node halo.  A block owns a 64 x TY column of nodes and
+//    marches through a slab of z planes, rolling three planes of each.
+//  * Populations are stored as deviations from their rest equilibria
+//    (w_i phi, (A_i + B_i q/zeta) U, w_i theta) and updated in increment form,
+//    in FP32 (or FP16/BF16 storage with FP32 arithmetic, or FP64 for
+//    verification): the fields then absorb one rounding per step instead of
+//    one per population.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <hip/hip_fp16.h>
+#include <hip/hip_bf16.h>
+#include <stdint.h>
+
+#include <type_traits>
+
+#include "lattice.hpp"
+
+namespace lbpf {
+
+constexpr int TX = 64;   // tile width along x = one wavefront
+
+// --------------------------------------------------------------------------
+// Storage codecs
+// --------------------------------------------------------------------------
+// Every storage type holds deviations from the rest equilibrium; the codec is
+// only the conversion between the storage type and the arithmetic type.
+template <class S> struct Codec;
+template <> struct Codec<float> {
+    __device__ static float dec(float s) { return s; }
+    __device__ static float enc(float v) { return v; }
+};
+template <> struct Codec<double> {
+    __device__ static double dec(double s) { return s; }
+    __device__ static double enc(double v) { return v; }
+};
+template <> struct Codec<__half> {
+    __device__ static float dec(__half s) { return __half2float(s); }
+    __device__ static __half enc(float v) { return __float2half_rn(v); }
+};
+template <> struct Codec<__hip_bfloat16> {
+    __device__ static float dec(__hip_bfloat16 s) { return __bfloat162float(s); }
+    __device__ static __hip_bfloat16 enc(float v) { return __float2bfloat16(v); }
+};
+
+// --------------------------------------------------------------------------
+// Kernel constants (precomputed on the host in FP64, converted to T)
+// --------------------------------------------------------------------------
+template <class T>
+struct Coef {
+    int nx, ny, nz;
+    int symm;          // bit f set: face f (-x,+x,-y,+y,-z,+z) is a symmetry wall
+    int zslab;         // z planes per block
+    int nbx, nby, nbz; // tiles per axis
+    long long np;      // elements between two population arrays
+    int aniso;
+    T eps, delta;
+    T inv2dx;          // 1 / (2 dx)
+    T smin;            // |grad phi|^2 below which the normal is undefined
+    T eta_c;           // W0^2 dt / (e^2 tau0 dx^2)           (eq. LBE_RelaxationTime)
+    T cphi_e2;         // dt W0^2 / (dx tau0 e^2)               (eq. Feq_Phase)
+    T dt_tau0;         // dt / tau0
+    T lambda, Mcinf;
+    T k, D;
+    T inv_dt, inv_dx2;
+    T jat_c;           // W0 / (2 sqrt 2)                       (eq. AntiTrapping_Current)
+    T omU, omT;        // 1/eta_U, 1/eta_theta (eqs. RelaxationTime_Concentration, ThermalDiffusivity)
+    T etaU;            // eta_U
+    T dt;
+    T jcoef;           // omU dt / (e^2 dx)
+    T jt;              // dt / (e^2 dx)
+};
+
+__device__ __forceinline__ int clampi(int v, int n) { return v < 0 ? 0 : (v >= n ? n - 1 : v); }
+
+// Block index remapped so that each XCD (blocks are dealt round-robin to the
+// 8 XCDs) receives one contiguous run of tiles: halo and non-local re-reads of
+// neighbouring tiles then hit the same L2.
+__device__ __forceinline__ int xcd_tile(int b, int total) {
+    if ((total & 7) != 0) return b;
+    return (b & 7) * (total >> 3) + (b >> 3);
+}
+
+// Source of the incoming link i at node (x,y,z) for pull streaming.  Returns
+// the source node in (sx,sy,sz), the source direction j and the sign flips
+// (fx,fy,fz) with e_j = (fx ex, fy ey, fz ez).  Walls: half-way bounce-back
+// for no-flux faces, specular reflection for symmetry faces; a link crossing
+// any no-flux face bounces back.
+template <class L>
+struct Src {
+    int sx, sy, sz, j, fx, fy, fz;
+};
+
+template <class L, int I>
+__device__ __forceinline__ Src<L> source(int x, int y, int z, int nx, int ny, int nz, int symm) {
+    constexpr int ex = L::ex(I), ey = L::ey(I), ez = L::ez(I);
+    Src<L> s{x - ex, y - ey, z - ez, I, 1, 1, 1};
+    int mask = 0;
+    bool nf = false;
+    if (ex != 0) {
+        if (s.sx < 0) { mask |= 1; nf |= !(symm & 1); }
+        else if (s.sx >= nx) { mask |= 1; nf |= !(symm & 2); }
+    }
+    if (ey != 0) {
+        if (s.sy < 0) { mask |= 2; nf |= !(symm & 4); }
+        else if (s.sy >= ny) { mask |= 2; nf |= !(symm & 8); }
+    }
+    if (ez != 0) {
+        if (s.sz < 0) { mask |= 4; nf |= !(symm & 16); }
+        else if (s.sz >= nz) { mask |= 4; nf |= !(symm & 32); }
+    }
+    if (mask) {
+        if (nf) {
+            s.sx = x; s.sy = y; s.sz = z; s.fx = -1; s.fy = -1; s.fz = -1;
+        } else {
+            if (mask & 1) { s.sx = x; s.fx = -1; }
+            if (mask & 2) { s.sy = y; s.fy = -1; }
+            if (mask & 4) { s.sz = z; s.fz = -1; }
+        }
+        s.j = find_dir<L>(s.fx * ex, s.fy * ey, s.fz * ez);
+    }
+    return s;
+}
+
+// Compile-time loop over the directions.
+template <int I, int Q>
+struct Unroll {
+    template <class F>
+    __device__ __forceinline__ static void run(F&& f) {
+        f(std::integral_constant<int, I>{});
+        Unroll<I + 1, Q>::run(f);
+    }
+};
+template <int Q>
+struct Unroll<Q, Q> {
+    template <class F>
+    __device__ __forceinline__ static void run(F&&) {}
+};
+
+// --------------------------------------------------------------------------
+// Anisotropy in unit-normal form.  With m = p/|p| (p = grad phi; a_s is even
+// in n = -m), S4 = sum m^4:
+//  cubic (eq. Anisotropic-Function_As): a = 1 - 3 eps + 4 eps S4,
+//        |p| da/dp_a = 16 eps m_a (m_a^2 - S4);
+//  K41/K61 (eq. As_K41-K61): a = 1 + eps (S4 - 3/5) + delta (3 S4 + 66 P - 17/7),
+//        P = mx^2 my^2 mz^2,
+//        |p| da/dp_a = 4 (eps + 3 delta) m_a (m_a^2 - S4)
+//                      + 132 delta m_a m_b^2 m_c^2 (1 - 3 m_a^2).
+// N = |p|^2 a da/dp (eq. TermesAnisotropes) = |p| a (|p| da/dp).
+// --------------------------------------------------------------------------
+template <class T>
+__device__ __forceinline__ void aniso_terms(const Coef<T>& c, T px, T py, T pz, T& a, T& Nx, T& Ny,
+                                            T& Nz) {
+    const T s = px * px + py * py + pz * pz;
+    if (!(s > c.smin)) {
+        a = T(1); Nx = T(0); Ny = T(0); Nz = T(0);
+        return;
+    }
+    const T inv = T(1) / sqrt(s);
+    const T mag = s * inv;
+    const T mx = px * inv, my = py * inv, mz = pz * inv;
+    const T x2 = mx * mx, y2 = my * my, z2 = mz * mz;
+    const T s4 = x2 * x2 + y2 * y2 + z2 * z2;
+    T dx, dy, dz;
+    if (c.aniso == 0) {
+        a = T(1) - T(3) * c.eps + T(4) * c.eps * s4;
+        const T f = T(16) * c.eps;
+        dx = f * mx * (x2 - s4);
+        dy = f * my * (y2 - s4);
+        dz = f * mz * (z2 - s4);
+    } else {
+        a = T(1) + c.eps * (s4 - T(0.6)) + c.delta * (T(3) * s4 + T(66) * x2 * y2 * z2 - T(17.0 / 7.0));
+        const T f = T(4) * (c.eps + T(3) * c.delta);
+        const T g = T(132) * c.delta;
+        dx = f * mx * (x2 - s4) + g * mx * y2 * z2 * (T(1) - T(3) * x2);
+        dy = f * my * (y2 - s4) + g * my * x2 * z2 * (T(1) - T(3) * y2);
+        dz = f * mz * (z2 - s4) + g * mz * x2 * y2 * (T(1) - T(3) * z2);
+    }
+    const T am = mag * a;
+    Nx = am * dx; Ny = am * dy; Nz = am * dz;
+}
+
+// Boundary node (reading of "standard collision on boundary nodes", Sec. 3.4):
+// the node lies on a no-flux face, i.e. one of its links crosses a no-flux wall.
+__device__ __forceinline__ bool on_noflux_face(int x, int y, int z, int nx, int ny, int nz, int symm) {
+    return (x == 0 && !(symm & 1)) || (x == nx - 1 && !(symm & 2)) ||
+           (y == 0 && !(symm & 4)) || (y == ny - 1 && !(symm & 8)) ||
+           (z == 0 && !(symm & 16)) || (z == nz - 1 && !(symm & 32));
+}
+
+// Load one (TX+4) x (TY+4) plane of a field into LDS, mirror ghosts by clamping.
+template <class T, int TY>
+__device__ __forceinline__ void load_plane(T* dst, const T* __restrict__ f, int zz, int x0, int y0,
+                                           int nx, int ny, int nz, int tid) {
+    constexpr int PX = TX + 4, PY = TY + 4, NT = TX * TY;
+    const int gz = clampi(zz, nz);
+    const size_t base = (size_t)gz * (size_t)nx * (size_t)ny;
+    for (int t = tid; t < PX * PY; t += NT) {
+        const int lx = t % PX, ly = t / PX;
+        const int gx = clampi(x0 - 2 + lx, nx), gy = clampi(y0 - 2 + ly, ny);
+        dst[t] = f[base + (size_t)gy * nx + gx];
+    }
+}
+
+// r(phi) = q(phi)/zeta(phi), the same expression wherever a deviation is
+// encoded or decoded.
+template <class T>
+__device__ __forceinline__ T r_of(T f, T zA, T zB) {
+    return T(0.5) * (T(1) - f) / (zA - zB * f);
+}
+
+// ==========================================================================
+// K_phi: phase-field node terms, non-local collision and pull streaming.
+// Reads g^n, phi^n, U^n, theta^n; writes g^{n+1}, phi^{n+1}.
+//
+// Stored: d_i = g_i - w_i phi (deviation from the rest equilibrium).  With
+// the collision of eq. (Collision_Stage) at the source y of link i and the
+// non-local value g_i^n(x):
+//   g_i^{n+1}(x) = w_i phi_x + inc_i,
+//   inc_i = w_i [A_y (phi_y - phi_x) + A_y Q_y dt/tau0 - e_j.(A_y V_y)]
+//           + A_y (1 - omega_y) d_j(y) - (A_y - 1) d_i(x),
+// A = 1/a_s^2 (1 on boundary nodes), V = omega c_phi N / e^2, so that
+//   phi^{n+1}(x) = phi_x + sum_i inc_i,   d_i^{n+1}(x) = inc_i - w_i sum_i inc_i.
+// Only small quantities are rounded besides the one update of phi.
+// ==========================================================================
+template <class L, class T, class S, int TY>
+__global__ __launch_bounds__(TX * TY) void k_phi(const Coef<T> c, const S* __restrict__ gin,
+                                                 S* __restrict__ gout, const T* __restrict__ phin,
+                                                 const T* __restrict__ Un, const T* __restrict__ thn,
+                                                 T* __restrict__ phout) {
+    constexpr int NT = TX * TY;
+    constexpr int PX = TX + 4, PY = TY + 4, HX = TX + 2, HY = TY + 2, HN = HX * HY;
+    constexpr int NTERM = 7;   // A, A(1-omega), A Q dt/tau0, A V (3), phi
+    __shared__ T sphi[3][PX * PY];
+    __shared__ T sterm[3][NTERM][HN];
+
+    const int nx = c.nx, ny = c.ny, nz = c.nz;
+    const int total = c.nbx * c.nby * c.nbz;
+    const int b = xcd_tile(blockIdx.x, total);
+    const int bx = b % c.nbx, by = (b / c.nbx) % c.nby, bz = b / (c.nbx * c.nby);
+    const int tid = threadIdx.x;
+    const int x0 = bx * TX, y0 = by * TY;
+    const int zs = bz * c.zslab;
+    const int ze = min(zs + c.zslab, nz);
+    const int x = x0 + tid % TX, y = y0 + tid / TX;
+    const bool active = x < nx && y < ny;
+    const size_t plane = (size_t)nx * (size_t)ny;
+
+    for (int zz = zs - 2; zz <= ze + 1; ++zz) {
+        // A: phi^n plane zz
+        load_plane<T, TY>(sphi[(zz + 3) % 3], phin, zz, x0, y0, nx, ny, nz, tid);
+        __syncthreads();
+        // B: node terms of plane zz-1 (needs phi^n planes zz-2 .. zz)
+        if (zz >= zs) {
+            const int pz = zz - 1;
+            const T* fm = sphi[(pz + 2) % 3];
+            const T* f0 = sphi[(pz + 3) % 3];
+            const T* fp = sphi[(pz + 4) % 3];
+            T(*st)[HN] = sterm[(pz + 3) % 3];
+            const int gz = clampi(pz, nz);
+            for (int t = tid; t < HN; t += NT) {
+                const int lx = t % HX, ly = t / HX;
+                const int rx = x0 - 1 + lx, ry = y0 - 1 + ly;
+                const int gx = clampi(rx, nx), gy = clampi(ry, ny);
+                const int ctr = (ly + 1) * PX + (lx + 1);
+                const T ph = f0[ctr];
+                const T px = (f0[ctr + 1] - f0[ctr - 1]) * c.inv2dx;
+                const T py = (f0[ctr + PX] - f0[ctr - PX]) * c.inv2dx;
+                const T pzg = (fp[ctr] - fm[ctr]) * c.inv2dx;
+                T a, Nx, Ny, Nz;
+                aniso_terms(c, px, py, pzg, a, Nx, Ny, Nz);
+                const size_t gi = (size_t)gz * plane + (size_t)gy * nx + gx;
+                const T u = Un[gi], th = thn[gi];
+                const T a2 = a * a;
+                const T om = T(1) / (a2 * c.eta_c + T(0.5));          // eq. (LBE_RelaxationTime)
+                const T one_m = T(1) - ph * ph;
+                const T Qp = (ph - c.lambda * (c.Mcinf * u + th) * one_m) * one_m;  // eq. (LBE_SourceTerm)
+                const bool bnd = on_noflux_face(rx, ry, pz, nx, ny, nz, c.symm);
+                const T A = T(1) / (bnd ? T(1) : a2);
+                const T av = A * om * c.cphi_e2;
+                st[0][t] = A;
+                st[1][t] = A * (T(1) - om);
+                st[2][t] = A * Qp * c.dt_tau0;
+                st[3][t] = av * Nx;
+                st[4][t] = av * Ny;
+                st[5][t] = av * Nz;
+                st[6][t] = ph;
+            }
+        }
+        __syncthreads();
+        // C: pull plane zz-2 (terms of planes zz-3 .. zz-1 are ready)
+        if (zz >= zs + 2 && active) {
+            const int z = zz - 2;
+            const size_t xi = (size_t)z * plane + (size_t)y * nx + x;
+            const T phx = sterm[(z + 3) % 3][6][(y - y0 + 1) * HX + (x - x0 + 1)];
+            T inc[L::Q];
+            T dsum = T(0);
+            Unroll<0, L::Q>::run([&](auto ic) {
+                constexpr int I = decltype(ic)::value;
+                const Src<L> s = source<L, I>(x, y, z, nx, ny, nz, c.symm);
+                const size_t si = (size_t)s.sz * plane + (size_t)s.sy * nx + s.sx;
+                const T dj = (T)Codec<S>::dec(gin[(size_t)s.j * c.np + si]);
+                const T dnl = (T)Codec<S>::dec(gin[(size_t)I * c.np + xi]);
+                T(*st)[HN] = sterm[(s.sz + 3) % 3];
+                const int tl = (s.sy - y0 + 1) * HX + (s.sx - x0 + 1);
+                constexpr T wi = T(L::w(I));
+                const T A = st[0][tl];
+                const T eAV = T(s.fx * L::ex(I)) * st[3][tl] + T(s.fy * L::ey(I)) * st[4][tl] +
+                              T(s.fz * L::ez(I)) * st[5][tl];
+                const T v = wi * (A * (st[6][tl] - phx) + st[2][tl] - eAV) + st[1][tl] * dj -
+                            (A - T(1)) * dnl;
+                inc[I] = v;
+                dsum += v;
+            });
+            phout[xi] = phx + dsum;
+            Unroll<0, L::Q>::run([&](auto ic) {
+                constexpr int I = decltype(ic)::value;
+                constexpr T wi = T(L::w(I));
+                gout[(size_t)I * c.np + xi] = Codec<S>::enc(inc[I] - wi * dsum);
+            });
+        }
+    }
+}
+
+// ==========================================================================
+// K_ut: supersaturation and heat node terms (with phi^{n+1}), BGK collisions
+// and pull streaming.  Reads h^n, f^n, phi^n, phi^{n+1}, U^n, theta^n; writes
+// h^{n+1}, f^{n+1}, U^{n+1}, theta^{n+1}.
+//
+// Stored deviations: dh_i = h_i - (A_i + B_i r^o) U with r^o = q/zeta of the
+// phase field current when h was written (phi^n here), and df_i = f_i - w_i theta.
+// With P = r^o U, C = omega_U (r - r^o) U (r from phi^{n+1}), S = source dt
+// and K = omega_U dt J_tot / (e^2 dx) at the source y (eqs. LBE_Eq_Transport,
+// Feq_Transport; A_0 = 1, B_0 = w_0 - 1, A_i = 0 and B_i = w_i otherwise):
+//   h_i^{n+1}(x) = (A_i + B_i r^o_x) U_x + incU_i,
+//   incU_i = [i>0] w_i (P_y - P_x) + B_i C_y + (1 - omega_U) dh_j(y) + w_i (S_y + e_j.K_y),
+//   f_i^{n+1}(x) = w_i theta_x + incT_i,
+//   incT_i = w_i (theta_y - theta_x) + (1 - omega_theta) df_j(y) + w_i (phi^{n+1}_y - phi^n_y)/2,
+// then U^{n+1} = U_x + dU, theta^{n+1} = theta_x + dT and the new deviations
+//   dh_i = incU_i - A_i dU + B_i [(r^o_x - r_x) U_x - r_x dU],  df_i = incT_i - w_i dT.
+// ==========================================================================
+template <class L, class T, class S, int TY>
+__global__ __launch_bounds__(TX * TY) void k_ut(const Coef<T> c, const S* __restrict__ hin,
+                                                S* __restrict__ hout, const S* __restrict__ fin,
+                                                S* __restrict__ fout, const T* __restrict__ phio,
+                                                const T* __restrict__ phnew, const T* __restrict__ Un,
+                                                const T* __restrict__ thn, T* __restrict__ Uout,
+                                                T* __restrict__ thout) {
+    constexpr int NT = TX * TY;
+    constexpr int PX = TX + 4, PY = TY + 4, HX = TX + 2, HY = TY + 2, HN = HX * HY;
+    constexpr int NTERM = 9;   // P, C, S, Kx, Ky, Kz, theta, G, r
+    __shared__ T sphi[3][PX * PY];
+    __shared__ T sterm[3][NTERM][HN];
+
+    const int nx = c.nx, ny = c.ny, nz = c.nz;
+    const int total = c.nbx * c.nby * c.nbz;
+    const int b = xcd_tile(blockIdx.x, total);
+    const int bx = b % c.nbx, by = (b / c.nbx) % c.nby, bz = b / (c.nbx * c.nby);
+    const int tid = threadIdx.x;
+    const int x0 = bx * TX, y0 = by * TY;
+    const int zs = bz * c.zslab;
+    const int ze = min(zs + c.zslab, nz);
+    const int x = x0 + tid % TX, y = y0 + tid / TX;
+    const bool active = x < nx && y < ny;
+    const size_t plane = (size_t)nx * (size_t)ny;
+    const T k = c.k;
+    const T zA = T(0.5) * (T(1) + k), zB = T(0.5) * (T(1) - k);
+
+    for (int zz = zs - 2; zz <= ze + 1; ++zz) {
+        load_plane<T, TY>(sphi[(zz + 3) % 3], phnew, zz, x0, y0, nx, ny, nz, tid);
+        __syncthreads();
+        if (zz >= zs) {
+            const int pz = zz - 1;
+            const T* fm = sphi[(pz + 2) % 3];
+            const T* f0 = sphi[(pz + 3) % 3];
+            const T* fp = sphi[(pz + 4) % 3];
+            T(*st)[HN] = sterm[(pz + 3) % 3];
+            const int gz = clampi(pz, nz);
+            for (int t = tid; t < HN; t += NT) {
+                const int lx = t % HX, ly = t / HX;
+                const int gx = clampi(x0 - 1 + lx, nx), gy = clampi(y0 - 1 + ly, ny);
+                const int ctr = (ly + 1) * PX + (lx + 1);
+                // phi^{n+1} at the node and its six neighbours (mirror ghosts)
+                const T p0 = f0[ctr];
+                const T pn[6] = {f0[ctr + 1], f0[ctr - 1], f0[ctr + PX], f0[ctr - PX], fp[ctr], fm[ctr]};
+                const T w0 = T(1) / (zA - zB * p0);      // 1/zeta
+                const T q0 = T(0.5) * (T(1) - p0);       // q(phi)
+                const T r0 = r_of(p0, zA, zB);           // q/zeta
+                T wn[6], qn[6], rn[6];
+#pragma unroll
+                for (int d = 0; d < 6; ++d) {
+                    wn[d] = T(1) / (zA - zB * pn[d]);
+                    qn[d] = T(0.5) * (T(1) - pn[d]);
+                    rn[d] = r_of(pn[d], zA, zB);
+                }
+                const T Gx = (rn[0] - rn[1]) * c.inv2dx, Gy = (rn[2] - rn[3]) * c.inv2dx,
+                        Gz = (rn[4] - rn[5]) * c.inv2dx;
+                const T Fx = (wn[0] - wn[1]) * c.inv2dx, Fy = (wn[2] - wn[3]) * c.inv2dx,
+                        Fz = (wn[4] - wn[5]) * c.inv2dx;
+                const T gx_ = (pn[0] - pn[1]) * c.inv2dx, gy_ = (pn[2] - pn[3]) * c.inv2dx,
+                        gz_ = (pn[4] - pn[5]) * c.inv2dx;
+                const size_t gi = (size_t)gz * plane + (size_t)gy * nx + gx;
+                const T po = phio[gi], u = Un[gi], th = thn[gi];
+                const T dphi = p0 - po;
+                const T dtphi = dphi * c.inv_dt;
+                const T cu = T(1) + (T(1) - k) * u;
+                // anti-trapping current, eq. (AntiTrapping_Current)
+                T jx = T(0), jy = T(0), jz = T(0);
+                const T s2 = gx_ * gx_ + gy_ * gy_ + gz_ * gz_;
+                if (s2 > c.smin) {
+                    const T f = -c.jat_c * cu * dtphi / sqrt(s2);
+                    jx = f * gx_; jy = f * gy_; jz = f * gz_;
+                }
+                // compact div(q grad(1/zeta))
+                T div = T(0);
+#pragma unroll
+                for (int a = 0; a < 3; ++a)
+                    div += T(0.5) * (q0 + qn[2 * a]) * (wn[2 * a] - w0) -
+                           T(0.5) * (q0 + qn[2 * a + 1]) * (w0 - wn[2 * a + 1]);
+                div *= c.inv_dx2;
+                // J_tot (eq. Def_Jtot), S (eq. Def_S), Q_U/zeta (eq. Def_Qu)
+                const T Du = c.D * u;
+                const T Jx = Du * (Gx + q0 * Fx) + jx * w0;
+                const T Jy = Du * (Gy + q0 * Fy) + jy * w0;
+                const T Jz = Du * (Gz + q0 * Fz) + jz * w0;
+                const T Sflux = Du * div + jx * Fx + jy * Fy + jz * Fz;
+                const T src = Sflux + cu * T(0.5) * dtphi * w0;
+                const T ro = r_of(po, zA, zB);
+                st[0][t] = ro * u;
+                st[1][t] = c.omU * (r0 - ro) * u;
+                st[2][t] = src * c.dt;
+                st[3][t] = c.jcoef * Jx;
+                st[4][t] = c.jcoef * Jy;
+                st[5][t] = c.jcoef * Jz;
+                st[6][t] = th;
+                st[7][t] = T(0.5) * dphi;   // Q_theta dt, eq. (Source_Tempr)
+                st[8][t] = r0;
+            }
+        }
+        __syncthreads();
+        if (zz >= zs + 2 && active) {
+            const int z = zz - 2;
+            const size_t xi = (size_t)z * plane + (size_t)y * nx + x;
+            const int tx_ = (y - y0 + 1) * HX + (x - x0 + 1);
+            T(*sx)[HN] = sterm[(z + 3) % 3];
+            const T Px = sx[0][tx_], Cx = sx[1][tx_], thx = sx[6][tx_], rx = sx[8][tx_];
+            const T Ux = Un[xi];
+            T iu[L::Q], it[L::Q];
+            T du = T(0), dth = T(0);
+            Unroll<0, L::Q>::run([&](auto ic) {
+                constexpr int I = decltype(ic)::value;
+                const Src<L> s = source<L, I>(x, y, z, nx, ny, nz, c.symm);
+                const size_t si = (size_t)s.sz * plane + (size_t)s.sy * nx + s.sx;
+                const T dh = (T)Codec<S>::dec(hin[(size_t)s.j * c.np + si]);
+                const T df = (T)Codec<S>::dec(fin[(size_t)s.j * c.np + si]);
+                T(*st)[HN] = sterm[(s.sz + 3) % 3];
+                const int tl = (s.sy - y0 + 1) * HX + (s.sx - x0 + 1);
+                constexpr T wi = T(L::w(I));
+                constexpr T Bi = (I == 0) ? T(L::w(0)) - T(1) : wi;
+                const T eK = T(s.fx * L::ex(I)) * st[3][tl] + T(s.fy * L::ey(I)) * st[4][tl] +
+                             T(s.fz * L::ez(I)) * st[5][tl];
+                T vu = Bi * st[1][tl] + (T(1) - c.omU) * dh + wi * (st[2][tl] + eK);
+                if constexpr (I != 0) vu += wi * (st[0][tl] - Px);
+                const T vt = wi * (st[6][tl] - thx + st[7][tl]) + (T(1) - c.omT) * df;
+                iu[I] = vu; it[I] = vt;
+                du += vu; dth += vt;
+            });
+            Uout[xi] = Ux + du;
+            thout[xi] = thx + dth;
+            // (r^o_x - r_x) U_x = -C_x / omega_U
+            const T dr = -Cx * c.etaU;
+            Unroll<0, L::Q>::run([&](auto ic) {
+                constexpr int I = decltype(ic)::value;
+                constexpr T wi = T(L::w(I));
+                constexpr T Bi = (I == 0) ? T(L::w(0)) - T(1) : wi;
+                constexpr T Ai = (I == 0) ? T(1) : T(0);
+                const T dhv = iu[I] - Ai * du + Bi * (dr - rx * du);
+                hout[(size_t)I * c.np + xi] = Codec<S>::enc(dhv);
+                fout[(size_t)I * c.np + xi] = Codec<S>::enc(it[I] - wi * dth);
+            });
+        }
+    }
+}
+
+// ==========================================================================
+// Initial populations = equilibria of the given fields (plain per-node kernel,
+// runs once), stored as deviations.  g: eq. (Feq_Phase) with N from grad phi,
+// deviation -w_i e_i.N c_phi/e^2; h: eq. (Feq_Transport) with J_tot =
+// D (grad(q/zeta) + q grad(1/zeta)) U (no anti-trapping current without a
+// time derivative), deviation B_i e_i.J dt/(e^2 dx); f: eq. (EqFunction_Tempr),
+// deviation 0.
+// ==========================================================================
+template <class L, class T, class S>
+__global__ __launch_bounds__(256) void k_init(const Coef<T> c, S* __restrict__ g, S* __restrict__ h,
+                                              S* __restrict__ f, const T* __restrict__ phi,
+                                              const T* __restrict__ U) {
+    const int nx = c.nx, ny = c.ny, nz = c.nz;
+    const size_t n = (size_t)nx * ny * nz;
+    const size_t s = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= n) return;
+    const int x = (int)(s % nx), y = (int)((s / nx) % ny), z = (int)(s / ((size_t)nx * ny));
+    auto at = [&](int xx, int yy, int zz) {
+        return phi[((size_t)clampi(zz, nz) * ny + clampi(yy, ny)) * nx + clampi(xx, nx)];
+    };
+    const T p0 = phi[s];
+    const T pn[6] = {at(x + 1, y, z), at(x - 1, y, z), at(x, y + 1, z),
+                     at(x, y - 1, z), at(x, y, z + 1), at(x, y, z - 1)};
+    T a, Nx, Ny, Nz;
+    aniso_terms(c, (pn[0] - pn[1]) * c.inv2dx, (pn[2] - pn[3]) * c.inv2dx, (pn[4] - pn[5]) * c.inv2dx,
+                a, Nx, Ny, Nz);
+    const T k = c.k, zA = T(0.5) * (T(1) + k), zB = T(0.5) * (T(1) - k);
+    const T q0 = T(0.5) * (T(1) - p0);
+    T wn[6], rn[6];
+#pragma unroll
+    for (int d = 0; d < 6; ++d) {
+        wn[d] = T(1) / (zA - zB * pn[d]);
+        rn[d] = r_of(pn[d], zA, zB);
+    }
+    const T u = U[s];
+    const T Jx = c.D * ((rn[0] - rn[1]) * c.inv2dx + q0 * (wn[0] - wn[1]) * c.inv2dx) * u;
+    const T Jy = c.D * ((rn[2] - rn[3]) * c.inv2dx + q0 * (wn[2] - wn[3]) * c.inv2dx) * u;
+    const T Jz = c.D * ((rn[4] - rn[5]) * c.inv2dx + q0 * (wn[4] - wn[5]) * c.inv2dx) * u;
+    Unroll<0, L::Q>::run([&](auto ic) {
+        constexpr int I = decltype(ic)::value;
+        constexpr T wi = T(L::w(I));
+        const T eN = T(L::ex(I)) * Nx + T(L::ey(I)) * Ny + T(L::ez(I)) * Nz;
+        const T eJ = T(L::ex(I)) * Jx + T(L::ey(I)) * Jy + T(L::ez(I)) * Jz;
+        const size_t o = (size_t)I * c.np + s;
+        g[o] = Codec<S>::enc(-wi * eN * c.cphi_e2);
+        h[o] = Codec<S>::enc((I == 0) ? T(0) : wi * eJ * c.jt);
+        f[o] = Codec<S>::enc(T(0));
+    });
+}
+
+// Full populations in FP64 (deviation + rest equilibrium) for inspection.
+template <class L, class T, class S>
+__global__ __launch_bounds__(256) void k_decode(const Coef<T> c, const S* __restrict__ pop, int field,
+                                                const T* __restrict__ phi, const T* __restrict__ U,
+                                                const T* __restrict__ th, double* __restrict__ out) {
+    const size_t n = (size_t)c.nx * c.ny * c.nz;
+    const size_t s = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= n) return;
+    const T zA = T(0.5) * (T(1) + c.k), zB = T(0.5) * (T(1) - c.k);
+    Unroll<0, L::Q>::run([&](auto ic) {
+        constexpr int I = decltype(ic)::value;
+        constexpr double wi = L::w(I);
+        const double d = (double)(T)Codec<S>::dec(pop[(size_t)I * c.np + s]);
+        double ref;
+        if (field == 0) {
+            ref = wi * (double)phi[s];
+        } else if (field == 1) {
+            const double ru = (double)(r_of(phi[s], zA, zB) * U[s]);
+            ref = (I == 0) ? (double)U[s] - (1.0 - wi) * ru : wi * ru;
+        } else {
+            ref = wi * (double)th[s];
+        }
+        out[(size_t)I * n + s] = d + ref;
+    });
+}
+
+// ==========================================================================
+// Streaming only (collision = identity) on raw bits: checks the pull index
+// mapping and the wall rules.
+// ==========================================================================
+template <class L, class B>
+__global__ __launch_bounds__(256) void k_stream_only(int nx, int ny, int nz, int symm, long long np,
+                                                     const B* __restrict__ in, B* __restrict__ out) {
+    const size_t n = (size_t)nx * ny * nz;
+    const size_t s = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= n) return;
+    const int x = (int)(s % nx), y = (int)((s / nx) % ny), z = (int)(s / ((size_t)nx * ny));
+    Unroll<0, L::Q>::run([&](auto ic) {
+        constexpr int I = decltype(ic)::value;
+        const Src<L> src = source<L, I>(x, y, z, nx, ny, nz, symm);
+        const size_t si = ((size_t)src.sz * ny + src.sy) * nx + src.sx;
+        out[(size_t)I * np + s] = in[(size_t)src.j * np + si];
+    });
+}
+
+// ==========================================================================
+// FP64 reductions: per-block partials (wavefront shuffles, then LDS), then a
+// single-block fixed-order final pass.  Deterministic for a given grid.
+// ==========================================================================
+enum { RV_SOLID = 0, RV_MASS, RV_ENTH, RV_SUMU, RV_SUMPHI, RV_BAD, RV_NSUM,   // sums
+       RV_TIPX = RV_NSUM, RV_TIPY, RV_TIPZ, RV_PMAX, RV_NEG_PMIN, RV_COUNT };   // maxima
+constexpr int RED_STRIDE = 16;   // doubles per partial / record slot
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+    return v;
+}
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_down(v, o, 64));
+    return v;
+}
+
+template <class T>
+__global__ __launch_bounds__(256) void k_reduce_part(int nx, int ny, int nz, double k, double dv,
+                                                     const T* __restrict__ phi, const T* __restrict__ U,
+                                                     const T* __restrict__ th, double* __restrict__ part) {
+    __shared__ double sh[4][RV_COUNT];
+    const size_t n = (size_t)nx * ny * nz;
+    double v[RV_COUNT];
+#pragma unroll
+    for (int i = 0; i < RV_NSUM; ++i) v[i] = 0.0;
+#pragma unroll
+    for (int i = RV_NSUM; i < RV_COUNT; ++i) v[i] = -INFINITY;
+    for (size_t s = (size_t)blockIdx.x * blockDim.x + threadIdx.x; s < n;
+         s += (size_t)gridDim.x * blockDim.x) {
+        const double f = (double)phi[s], u = (double)U[s], t = (double)th[s];
+        if (!isfinite(f) || !isfinite(u) || !isfinite(t)) {
+            v[RV_BAD] += 1.0;
+            continue;
+        }
+        v[RV_SOLID] += 0.5 * (1.0 + f);
+        v[RV_MASS] += (0.5 * (1.0 + k) - 0.5 * (1.0 - k) * f) * (1.0 + (1.0 - k) * u) * dv;
+        v[RV_ENTH] += (t - 0.5 * f) * dv;
+        v[RV_SUMU] += u * dv;
+        v[RV_SUMPHI] += f * dv;
+        v[RV_PMAX] = fmax(v[RV_PMAX], f);
+        v[RV_NEG_PMIN] = fmax(v[RV_NEG_PMIN], -f);
+        if (f > 0.0) {
+            const int x = (int)(s % nx), y = (int)((s / nx) % ny), z = (int)(s / ((size_t)nx * ny));
+            if (x + 1 < nx) {
+                const double fn = (double)phi[s + 1];
+                if (fn <= 0.0) v[RV_TIPX] = fmax(v[RV_TIPX], x + f / (f - fn));
+            }
+            if (y + 1 < ny) {
+                const double fn = (double)phi[s + nx];
+                if (fn <= 0.0) v[RV_TIPY] = fmax(v[RV_TIPY], y + f / (f - fn));
+            }
+            if (z + 1 < nz) {
+                const double fn = (double)phi[s + (size_t)nx * ny];
+                if (fn <= 0.0) v[RV_TIPZ] = fmax(v[RV_TIPZ], z + f / (f - fn));
+            }
+        }
+    }
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+    for (int i = 0; i < RV_COUNT; ++i) {
+        const double r = i < RV_NSUM ? wave_sum(v[i]) : wave_max(v[i]);
+        if (lane == 0) sh[wv][i] = r;
+    }
+    __syncthreads();
+    if (threadIdx.x < RV_COUNT) {
+        const int i = threadIdx.x;
+        double r = sh[0][i];
+        for (int w = 1; w < 4; ++w) r = i < RV_NSUM ? r + sh[w][i] : fmax(r, sh[w][i]);
+        part[(size_t)blockIdx.x * RED_STRIDE + i] = r;
+    }
+}
+
+// Record layout (RED_STRIDE doubles): step, solid, mass, enthalpy, tip x,y,z,
+// phi min, phi max, non-finite count, sum U, sum phi.
+__global__ __launch_bounds__(256) void k_reduce_final(const double* __restrict__ part, int nparts,
+                                                      double inv_n, double cx, double cy, double cz,
+                                                      long long step, double* __restrict__ rec) {
+    __shared__ double sh[4][RV_COUNT];
+    double v[RV_COUNT];
+#pragma unroll
+    for (int i = 0; i < RV_NSUM; ++i) v[i] = 0.0;
+#pragma unroll
+    for (int i = RV_NSUM; i < RV_COUNT; ++i) v[i] = -INFINITY;
+    for (int p = threadIdx.x; p < nparts; p += blockDim.x) {
+#pragma unroll
+        for (int i = 0; i < RV_COUNT; ++i) {
+            const double x = part[(size_t)p * RED_STRIDE + i];
+            v[i] = i < RV_NSUM ? v[i] + x : fmax(v[i], x);
+        }
+    }
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+    for (int i = 0; i < RV_COUNT; ++i) {
+        const double r = i < RV_NSUM ? wave_sum(v[i]) : wave_max(v[i]);
+        if (lane == 0) sh[wv][i] = r;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double r[RV_COUNT];
+        for (int i = 0; i < RV_COUNT; ++i) {
+            r[i] = sh[0][i];
+            for (int w = 1; w < 4; ++w) r[i] = i < RV_NSUM ? r[i] + sh[w][i] : fmax(r[i], sh[w][i]);
+        }
+        const double nanv = __longlong_as_double(0x7ff8000000000000LL);
+        rec[0] = (double)step;
+        rec[1] = r[RV_SOLID] * inv_n;
+        rec[2] = r[RV_MASS];
+        rec[3] = r[RV_ENTH];
+        rec[4] = r[RV_TIPX] > -1e300 ? r[RV_TIPX] - cx : nanv;
+        rec[5] = r[RV_TIPY] > -1e300 ? r[RV_TIPY] - cy : nanv;
+        rec[6] = r[RV_TIPZ] > -1e300 ? r[RV_TIPZ] - cz : nanv;
+        rec[7] = -r[RV_NEG_PMIN];
+        rec[8] = r[RV_PMAX];
+        rec[9] = r[RV_BAD];
+        rec[10] = r[RV_SUMU];
+        rec[11] = r[RV_SUMPHI];
+    }
+}
+
+// Plain 16-byte vector copy: the bandwidth reference.
+__global__ __launch_bounds__(256) void k_copy(const uint4* __restrict__ src, uint4* __restrict__ dst,
+                                              size_t n16) {
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n16;
+         i += (size_t)gridDim.x * blockDim.x)
+        dst[i] = src[i];
+}
+
+}  // namespace lbpf

@@ -1,0 +1,629 @@
+// lbpf.hip -- host runtime and C ABI (include/lbpf.h) of the gfx950
+// lattice-Boltzmann phase-field library.
+//
+// Step order (Sec. 3.4, "Algorithm implementation"): the phase field first
+// (kernel k_phi), then supersaturation and temperature with the new phase
+// field (kernel k_ut).  Each field has two population lattices and two field
+// buffers; the parity `cur` names the current state.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/lbpf.h"
+#include "kernels.hpp"
+
+using namespace lbpf;
+
+namespace {
+
+thread_local std::string g_create_error;
+
+constexpr int HIST_CAP = 8192;
+constexpr int RED_BLOCKS = 1024;
+
+struct TimedLaunch {
+    int kind;
+    hipEvent_t a, b;
+};
+
+}  // namespace
+
+struct lbpf_ctx {
+    lbpf_grid grid;
+    lbpf_params prm;
+    hipStream_t stream = nullptr;
+    int q = 19;
+    int storage = LBPF_F32;
+    size_t sbytes = 4;       // bytes per stored population
+    size_t tbytes = 4;       // bytes per field value (compute type)
+    size_t n = 0;            // nodes
+    size_t np = 0;           // population stride in elements
+    void* pop[3][2] = {};    // [field][parity]
+    void* fld[3][2] = {};    // phi, U, theta [parity]
+    int cur = 0;
+    bool have_fields = false;
+    int64_t step = 0;
+    double* part = nullptr;  // RED_BLOCKS partials
+    double* hist = nullptr;  // HIST_CAP records
+    double* fresh = nullptr; // one record for lbpf_read
+    int64_t hist_count = 0;
+    int ty = 4;
+    int zslab = 16;
+    bool timing = false;
+    std::vector<TimedLaunch> launches;
+    std::vector<hipEvent_t> pool;
+    double t_ms[3] = {0, 0, 0};
+    int64_t t_n[3] = {0, 0, 0};
+    std::string err;
+};
+
+namespace {
+
+#define CHK(call)                                                                  \
+    do {                                                                           \
+        hipError_t e_ = (call);                                                    \
+        if (e_ != hipSuccess) {                                                    \
+            ctx->err = std::string(#call) + ": " + hipGetErrorString(e_);          \
+            return LBPF_EDEVICE;                                                   \
+        }                                                                          \
+    } while (0)
+
+lbpf_status fail(lbpf_ctx* ctx, lbpf_status s, const std::string& msg) {
+    if (ctx) ctx->err = msg;
+    else g_create_error = msg;
+    return s;
+}
+
+template <class T>
+Coef<T> make_coef(const lbpf_ctx* ctx) {
+    const lbpf_params& p = ctx->prm;
+    const lbpf_grid& g = ctx->grid;
+    Coef<T> c{};
+    c.nx = g.nx; c.ny = g.ny; c.nz = g.nz;
+    c.symm = 0;
+    for (int f = 0; f < 6; ++f)
+        if (g.wall[f] == LBPF_WALL_SYMMETRY) c.symm |= 1 << f;
+    c.zslab = ctx->zslab;
+    c.nbx = (g.nx + TX - 1) / TX;
+    c.nby = (g.ny + ctx->ty - 1) / ctx->ty;
+    c.nbz = (g.nz + ctx->zslab - 1) / ctx->zslab;
+    c.np = (long long)ctx->np;
+    c.aniso = p.aniso;
+    c.eps = (T)p.eps;
+    c.delta = (T)p.delta;
+    c.inv2dx = (T)(1.0 / (2.0 * p.dx));
+    c.smin = (T)(1e-12 / (p.dx * p.dx));
+    c.eta_c = (T)(p.W0 * p.W0 * p.dt / (kE2 * p.tau0 * p.dx * p.dx));
+    c.cphi_e2 = (T)(p.dt * p.W0 * p.W0 / (p.dx * p.tau0 * kE2));
+    c.dt_tau0 = (T)(p.dt / p.tau0);
+    c.lambda = (T)p.lambda;
+    c.Mcinf = (T)p.Mcinf;
+    c.k = (T)p.k;
+    c.D = (T)p.D;
+    c.inv_dt = (T)(1.0 / p.dt);
+    c.inv_dx2 = (T)(1.0 / (p.dx * p.dx));
+    c.jat_c = (T)(p.W0 / (2.0 * std::sqrt(2.0)));
+    const double etaU = p.D * p.dt / (kE2 * p.dx * p.dx) + 0.5;
+    const double etaT = p.kappa * p.dt / (kE2 * p.dx * p.dx) + 0.5;
+    c.omU = (T)(1.0 / etaU);
+    c.omT = (T)(1.0 / etaT);
+    c.etaU = (T)etaU;
+    c.dt = (T)p.dt;
+    c.jcoef = (T)(p.dt / (kE2 * p.dx) / etaU);
+    c.jt = (T)(p.dt / (kE2 * p.dx));
+    return c;
+}
+
+int total_tiles(const lbpf_ctx* ctx) {
+    const int nbx = (ctx->grid.nx + TX - 1) / TX;
+    const int nby = (ctx->grid.ny + ctx->ty - 1) / ctx->ty;
+    const int nbz = (ctx->grid.nz + ctx->zslab - 1) / ctx->zslab;
+    return nbx * nby * nbz;
+}
+
+hipEvent_t get_event(lbpf_ctx* ctx) {
+    if (!ctx->pool.empty()) {
+        hipEvent_t e = ctx->pool.back();
+        ctx->pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+// Launch wrapper: optional event pair around the launch.
+template <class F>
+lbpf_status timed(lbpf_ctx* ctx, int kind, F&& launch) {
+    hipEvent_t a = nullptr, b = nullptr;
+    if (ctx->timing) {
+        a = get_event(ctx);
+        b = get_event(ctx);
+        if (!a || !b) return fail(ctx, LBPF_EDEVICE, "hipEventCreate failed");
+        CHK(hipEventRecord(a, ctx->stream));
+    }
+    launch();
+    CHK(hipGetLastError());
+    if (ctx->timing) {
+        CHK(hipEventRecord(b, ctx->stream));
+        ctx->launches.push_back({kind, a, b});
+    }
+    return LBPF_OK;
+}
+
+// ---------------------------------------------------------------- dispatch
+template <class L, class T, class S, int TY>
+lbpf_status launch_step_t(lbpf_ctx* ctx) {
+    const Coef<T> c = make_coef<T>(ctx);
+    const int nb = total_tiles(ctx);
+    const int a = ctx->cur, b = 1 - ctx->cur;
+    lbpf_status st = timed(ctx, 0, [&] {
+        hipLaunchKernelGGL((k_phi<L, T, S, TY>), dim3(nb), dim3(TX * TY), 0, ctx->stream, c,
+                           (const S*)ctx->pop[0][a], (S*)ctx->pop[0][b], (const T*)ctx->fld[0][a],
+                           (const T*)ctx->fld[1][a], (const T*)ctx->fld[2][a], (T*)ctx->fld[0][b]);
+    });
+    if (st) return st;
+    st = timed(ctx, 1, [&] {
+        hipLaunchKernelGGL((k_ut<L, T, S, TY>), dim3(nb), dim3(TX * TY), 0, ctx->stream, c,
+                           (const S*)ctx->pop[1][a], (S*)ctx->pop[1][b], (const S*)ctx->pop[2][a],
+                           (S*)ctx->pop[2][b], (const T*)ctx->fld[0][a], (const T*)ctx->fld[0][b],
+                           (const T*)ctx->fld[1][a], (const T*)ctx->fld[2][a], (T*)ctx->fld[1][b],
+                           (T*)ctx->fld[2][b]);
+    });
+    if (st) return st;
+    ctx->cur = b;
+    return LBPF_OK;
+}
+
+template <class L, class T, class S>
+lbpf_status launch_step_s(lbpf_ctx* ctx) {
+    switch (ctx->ty) {
+        case 1: return launch_step_t<L, T, S, 1>(ctx);
+        case 2: return launch_step_t<L, T, S, 2>(ctx);
+        case 4: return launch_step_t<L, T, S, 4>(ctx);
+        default: return fail(ctx, LBPF_EINVAL, "unsupported tile height");
+    }
+}
+
+template <class L>
+lbpf_status launch_step_l(lbpf_ctx* ctx) {
+    switch (ctx->storage) {
+        case LBPF_F32: return launch_step_s<L, float, float>(ctx);
+        case LBPF_F16_DEV: return launch_step_s<L, float, __half>(ctx);
+        case LBPF_BF16_DEV: return launch_step_s<L, float, __hip_bfloat16>(ctx);
+        case LBPF_F64: return launch_step_s<L, double, double>(ctx);
+    }
+    return fail(ctx, LBPF_EINVAL, "bad storage");
+}
+
+lbpf_status launch_step(lbpf_ctx* ctx) {
+    return ctx->q == 15 ? launch_step_l<D3Q15>(ctx) : launch_step_l<D3Q19>(ctx);
+}
+
+template <class L, class T, class S>
+lbpf_status launch_init_t(lbpf_ctx* ctx) {
+    const Coef<T> c = make_coef<T>(ctx);
+    const int nb = (int)((ctx->n + 255) / 256);
+    const int a = ctx->cur;
+    hipLaunchKernelGGL((k_init<L, T, S>), dim3(nb), dim3(256), 0, ctx->stream, c, (S*)ctx->pop[0][a],
+                       (S*)ctx->pop[1][a], (S*)ctx->pop[2][a], (const T*)ctx->fld[0][a],
+                       (const T*)ctx->fld[1][a]);
+    CHK(hipGetLastError());
+    return LBPF_OK;
+}
+
+template <class L, class T, class S>
+lbpf_status launch_decode_t(lbpf_ctx* ctx, int field, double* dout) {
+    const Coef<T> c = make_coef<T>(ctx);
+    const int nb = (int)((ctx->n + 255) / 256);
+    const int a = ctx->cur;
+    hipLaunchKernelGGL((k_decode<L, T, S>), dim3(nb), dim3(256), 0, ctx->stream, c,
+                       (const S*)ctx->pop[field][a], field, (const T*)ctx->fld[0][a],
+                       (const T*)ctx->fld[1][a], (const T*)ctx->fld[2][a], dout);
+    CHK(hipGetLastError());
+    return LBPF_OK;
+}
+
+template <class L, class T, class S>
+lbpf_status by_storage_init(lbpf_ctx* ctx, int what, int field, double* dout) {
+    return what == 0 ? launch_init_t<L, T, S>(ctx) : launch_decode_t<L, T, S>(ctx, field, dout);
+}
+
+template <class L>
+lbpf_status init_or_decode_l(lbpf_ctx* ctx, int what, int field, double* dout) {
+    switch (ctx->storage) {
+        case LBPF_F32: return by_storage_init<L, float, float>(ctx, what, field, dout);
+        case LBPF_F16_DEV: return by_storage_init<L, float, __half>(ctx, what, field, dout);
+        case LBPF_BF16_DEV: return by_storage_init<L, float, __hip_bfloat16>(ctx, what, field, dout);
+        case LBPF_F64: return by_storage_init<L, double, double>(ctx, what, field, dout);
+    }
+    return fail(ctx, LBPF_EINVAL, "bad storage");
+}
+
+lbpf_status init_or_decode(lbpf_ctx* ctx, int what, int field, double* dout) {
+    return ctx->q == 15 ? init_or_decode_l<D3Q15>(ctx, what, field, dout)
+                        : init_or_decode_l<D3Q19>(ctx, what, field, dout);
+}
+
+template <class L, class B>
+lbpf_status stream_only_t(lbpf_ctx* ctx) {
+    int symm = 0;
+    for (int f = 0; f < 6; ++f)
+        if (ctx->grid.wall[f] == LBPF_WALL_SYMMETRY) symm |= 1 << f;
+    const int nb = (int)((ctx->n + 255) / 256);
+    const int a = ctx->cur, b = 1 - ctx->cur;
+    for (int f = 0; f < 3; ++f)
+        hipLaunchKernelGGL((k_stream_only<L, B>), dim3(nb), dim3(256), 0, ctx->stream, ctx->grid.nx,
+                           ctx->grid.ny, ctx->grid.nz, symm, (long long)ctx->np,
+                           (const B*)ctx->pop[f][a], (B*)ctx->pop[f][b]);
+    CHK(hipGetLastError());
+    // the fields follow the populations' parity unchanged
+    for (int f = 0; f < 3; ++f)
+        CHK(hipMemcpyAsync(ctx->fld[f][b], ctx->fld[f][a], ctx->n * ctx->tbytes,
+                           hipMemcpyDeviceToDevice, ctx->stream));
+    ctx->cur = b;
+    return LBPF_OK;
+}
+
+template <class L>
+lbpf_status stream_only_l(lbpf_ctx* ctx) {
+    switch (ctx->sbytes) {
+        case 2: return stream_only_t<L, uint16_t>(ctx);
+        case 4: return stream_only_t<L, uint32_t>(ctx);
+        case 8: return stream_only_t<L, uint64_t>(ctx);
+    }
+    return fail(ctx, LBPF_EINVAL, "bad storage");
+}
+
+template <class T>
+lbpf_status launch_reduce_t(lbpf_ctx* ctx, double* rec) {
+    const lbpf_params& p = ctx->prm;
+    const int a = ctx->cur;
+    const int nb = (int)std::min<size_t>(RED_BLOCKS, (ctx->n + 255) / 256);
+    lbpf_status st = timed(ctx, 2, [&] {
+        hipLaunchKernelGGL((k_reduce_part<T>), dim3(nb), dim3(256), 0, ctx->stream, ctx->grid.nx,
+                           ctx->grid.ny, ctx->grid.nz, p.k, p.dx * p.dx * p.dx,
+                           (const T*)ctx->fld[0][a], (const T*)ctx->fld[1][a],
+                           (const T*)ctx->fld[2][a], ctx->part);
+    });
+    if (st) return st;
+    return timed(ctx, 2, [&] {
+        hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(256), 0, ctx->stream, ctx->part, nb,
+                           1.0 / (double)ctx->n, p.centre[0], p.centre[1], p.centre[2],
+                           (long long)ctx->step, rec);
+    });
+}
+
+lbpf_status launch_reduce(lbpf_ctx* ctx, double* rec) {
+    return ctx->storage == LBPF_F64 ? launch_reduce_t<double>(ctx, rec)
+                                    : launch_reduce_t<float>(ctx, rec);
+}
+
+void unpack_record(const double* r, lbpf_reductions* out) {
+    out->step = (int64_t)r[0];
+    out->solid_fraction = r[1];
+    out->solute_mass = r[2];
+    out->enthalpy = r[3];
+    out->tip[0] = r[4]; out->tip[1] = r[5]; out->tip[2] = r[6];
+    out->phi_min = r[7];
+    out->phi_max = r[8];
+    out->nonfinite = r[9];
+    out->sum_U = r[10];
+    out->sum_phi = r[11];
+}
+
+bool healthy(const lbpf_reductions& r) {
+    return r.nonfinite == 0.0 && r.phi_max <= 1.0 + 1e-3 && r.phi_min >= -1.0 - 1e-3;
+}
+
+void free_all(lbpf_ctx* ctx) {
+    for (int f = 0; f < 3; ++f)
+        for (int p = 0; p < 2; ++p) {
+            if (ctx->pop[f][p]) (void)hipFree(ctx->pop[f][p]);
+            if (ctx->fld[f][p]) (void)hipFree(ctx->fld[f][p]);
+            ctx->pop[f][p] = ctx->fld[f][p] = nullptr;
+        }
+    if (ctx->part) (void)hipFree(ctx->part);
+    if (ctx->hist) (void)hipFree(ctx->hist);
+    if (ctx->fresh) (void)hipFree(ctx->fresh);
+    ctx->part = ctx->hist = ctx->fresh = nullptr;
+    for (auto& l : ctx->launches) {
+        (void)hipEventDestroy(l.a);
+        (void)hipEventDestroy(l.b);
+    }
+    ctx->launches.clear();
+    for (auto e : ctx->pool) (void)hipEventDestroy(e);
+    ctx->pool.clear();
+}
+
+}  // namespace
+
+extern "C" {
+
+int32_t lbpf_storage_bytes(int32_t storage) {
+    switch (storage) {
+        case LBPF_F32: return 4;
+        case LBPF_F16_DEV: return 2;
+        case LBPF_BF16_DEV: return 2;
+        case LBPF_F64: return 8;
+    }
+    return 0;
+}
+
+const char* lbpf_last_error(const lbpf_ctx* ctx) {
+    return ctx ? ctx->err.c_str() : g_create_error.c_str();
+}
+
+lbpf_status lbpf_create(const lbpf_grid* grid, const lbpf_params* params, void* hip_stream,
+                        lbpf_ctx** out) {
+    if (!out) return fail(nullptr, LBPF_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!grid || !params) return fail(nullptr, LBPF_EINVAL, "grid or params is NULL");
+    const lbpf_grid& g = *grid;
+    const lbpf_params& p = *params;
+    if (g.nx < 1 || g.ny < 1 || g.nz < 1) return fail(nullptr, LBPF_EINVAL, "grid size < 1");
+    if ((double)g.nx * g.ny * g.nz > 2.0e9) return fail(nullptr, LBPF_EINVAL, "grid too large");
+    if (g.lattice != LBPF_D3Q15 && g.lattice != LBPF_D3Q19)
+        return fail(nullptr, LBPF_EINVAL, "lattice must be 15 or 19");
+    if (lbpf_storage_bytes(g.storage) == 0) return fail(nullptr, LBPF_EINVAL, "bad storage");
+    for (int f = 0; f < 6; ++f)
+        if (g.wall[f] != LBPF_WALL_NOFLUX && g.wall[f] != LBPF_WALL_SYMMETRY)
+            return fail(nullptr, LBPF_EINVAL, "bad wall type");
+    if (!(p.dx > 0) || !(p.dt > 0) || !(p.W0 > 0) || !(p.tau0 > 0))
+        return fail(nullptr, LBPF_EINVAL, "dx, dt, W0 and tau0 must be > 0");
+    if (!(p.k > 0 && p.k < 1)) return fail(nullptr, LBPF_EINVAL, "k must lie in (0,1)");
+    if (!(p.D >= 0) || !(p.kappa >= 0)) return fail(nullptr, LBPF_EINVAL, "D, kappa must be >= 0");
+    if (!(p.eps >= 0 && p.eps <= 0.25) || !std::isfinite(p.delta) || !std::isfinite(p.lambda) ||
+        !std::isfinite(p.Mcinf))
+        return fail(nullptr, LBPF_EINVAL, "bad anisotropy or coupling parameter");
+    if (p.aniso != LBPF_ANISO_CUBIC && p.aniso != LBPF_ANISO_K41K61)
+        return fail(nullptr, LBPF_EINVAL, "bad anisotropy function");
+    if (p.reduce_every < 0) return fail(nullptr, LBPF_EINVAL, "reduce_every < 0");
+
+    lbpf_ctx* ctx = new (std::nothrow) lbpf_ctx();
+    if (!ctx) return fail(nullptr, LBPF_ENOMEM, "host allocation failed");
+    ctx->grid = g;
+    ctx->prm = p;
+    ctx->stream = (hipStream_t)hip_stream;
+    ctx->q = g.lattice;
+    ctx->storage = g.storage;
+    ctx->sbytes = (size_t)lbpf_storage_bytes(g.storage);
+    ctx->tbytes = g.storage == LBPF_F64 ? 8 : 4;
+    ctx->ty = g.storage == LBPF_F64 ? 2 : 4;
+    ctx->zslab = 16;
+    ctx->n = (size_t)g.nx * g.ny * g.nz;
+    ctx->np = (ctx->n + 63) / 64 * 64;
+    hipError_t e = hipSuccess;
+    for (int f = 0; f < 3 && e == hipSuccess; ++f)
+        for (int par = 0; par < 2 && e == hipSuccess; ++par) {
+            e = hipMalloc(&ctx->pop[f][par], ctx->np * ctx->q * ctx->sbytes);
+            if (e == hipSuccess) e = hipMalloc(&ctx->fld[f][par], ctx->n * ctx->tbytes);
+        }
+    if (e == hipSuccess) e = hipMalloc((void**)&ctx->part, RED_BLOCKS * RED_STRIDE * sizeof(double));
+    if (e == hipSuccess) e = hipMalloc((void**)&ctx->hist, (size_t)HIST_CAP * RED_STRIDE * sizeof(double));
+    if (e == hipSuccess) e = hipMalloc((void**)&ctx->fresh, RED_STRIDE * sizeof(double));
+    if (e != hipSuccess) {
+        const lbpf_status s = e == hipErrorOutOfMemory ? LBPF_ENOMEM : LBPF_EDEVICE;
+        const std::string msg = std::string("device allocation: ") + hipGetErrorString(e);
+        free_all(ctx);
+        delete ctx;
+        return fail(nullptr, s, msg);
+    }
+    *out = ctx;
+    return LBPF_OK;
+}
+
+lbpf_status lbpf_destroy(lbpf_ctx* ctx) {
+    if (!ctx) return LBPF_OK;
+    if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
+    else (void)hipDeviceSynchronize();
+    free_all(ctx);
+    delete ctx;
+    return LBPF_OK;
+}
+
+lbpf_status lbpf_set_fields(lbpf_ctx* ctx, const double* phi, const double* U, const double* theta) {
+    if (!ctx) return LBPF_EINVAL;
+    if (!phi || !U || !theta) return fail(ctx, LBPF_EINVAL, "NULL field array");
+    ctx->cur = 0;
+    const double* src[3] = {phi, U, theta};
+    for (int f = 0; f < 3; ++f) {
+        if (ctx->tbytes == 8) {
+            CHK(hipMemcpyAsync(ctx->fld[f][0], src[f], ctx->n * 8, hipMemcpyHostToDevice, ctx->stream));
+            CHK(hipStreamSynchronize(ctx->stream));
+        } else {
+            std::vector<float> tmp(ctx->n);
+            for (size_t i = 0; i < ctx->n; ++i) tmp[i] = (float)src[f][i];
+            CHK(hipMemcpyAsync(ctx->fld[f][0], tmp.data(), ctx->n * 4, hipMemcpyHostToDevice,
+                               ctx->stream));
+            CHK(hipStreamSynchronize(ctx->stream));
+        }
+    }
+    lbpf_status st = init_or_decode(ctx, 0, 0, nullptr);
+    if (st) return st;
+    CHK(hipStreamSynchronize(ctx->stream));
+    ctx->have_fields = true;
+    ctx->step = 0;
+    ctx->hist_count = 0;
+    return LBPF_OK;
+}
+
+lbpf_status lbpf_step(lbpf_ctx* ctx, int64_t nsteps) {
+    if (!ctx) return LBPF_EINVAL;
+    if (nsteps < 0) return fail(ctx, LBPF_EINVAL, "nsteps < 0");
+    if (!ctx->have_fields) return fail(ctx, LBPF_ESTATE, "lbpf_set_fields has not been called");
+    const int R = ctx->prm.reduce_every;
+    for (int64_t s = 0; s < nsteps; ++s) {
+        lbpf_status st = launch_step(ctx);
+        if (st) return st;
+        ctx->step++;
+        if (R > 0 && ctx->step % R == 0) {
+            double* rec = ctx->hist + (size_t)(ctx->hist_count % HIST_CAP) * RED_STRIDE;
+            st = launch_reduce(ctx, rec);
+            if (st) return st;
+            ctx->hist_count++;
+        }
+    }
+    return LBPF_OK;
+}
+
+lbpf_status lbpf_sync(lbpf_ctx* ctx) {
+    if (!ctx) return LBPF_EINVAL;
+    CHK(hipStreamSynchronize(ctx->stream));
+    if (ctx->hist_count > 0) {
+        double r[RED_STRIDE];
+        const double* rec = ctx->hist + (size_t)((ctx->hist_count - 1) % HIST_CAP) * RED_STRIDE;
+        CHK(hipMemcpy(r, rec, sizeof(r), hipMemcpyDeviceToHost));
+        lbpf_reductions red;
+        unpack_record(r, &red);
+        if (!healthy(red))
+            return fail(ctx, LBPF_EUNSTABLE, "health check failed at step " + std::to_string(red.step));
+    }
+    return LBPF_OK;
+}
+
+lbpf_status lbpf_read(lbpf_ctx* ctx, double* phi, double* U, double* theta, lbpf_reductions* red) {
+    if (!ctx) return LBPF_EINVAL;
+    if (!ctx->have_fields) return fail(ctx, LBPF_ESTATE, "lbpf_set_fields has not been called");
+    double* dst[3] = {phi, U, theta};
+    CHK(hipStreamSynchronize(ctx->stream));
+    for (int f = 0; f < 3; ++f) {
+        if (!dst[f]) continue;
+        if (ctx->tbytes == 8) {
+            CHK(hipMemcpy(dst[f], ctx->fld[f][ctx->cur], ctx->n * 8, hipMemcpyDeviceToHost));
+        } else {
+            std::vector<float> tmp(ctx->n);
+            CHK(hipMemcpy(tmp.data(), ctx->fld[f][ctx->cur], ctx->n * 4, hipMemcpyDeviceToHost));
+            for (size_t i = 0; i < ctx->n; ++i) dst[f][i] = (double)tmp[i];
+        }
+    }
+    if (red) {
+        const bool was = ctx->timing;
+        ctx->timing = false;
+        lbpf_status st = launch_reduce(ctx, ctx->fresh);
+        ctx->timing = was;
+        if (st) return st;
+        double r[RED_STRIDE];
+        CHK(hipMemcpyAsync(r, ctx->fresh, sizeof(r), hipMemcpyDeviceToHost, ctx->stream));
+        CHK(hipStreamSynchronize(ctx->stream));
+        unpack_record(r, red);
+        if (!healthy(*red))
+            return fail(ctx, LBPF_EUNSTABLE, "health check failed at step " + std::to_string(red->step));
+    }
+    return LBPF_OK;
+}
+
+lbpf_status lbpf_history(lbpf_ctx* ctx, lbpf_reductions* out, int32_t max_records, int32_t* count) {
+    if (!ctx || !count || (max_records > 0 && !out)) return fail(ctx, LBPF_EINVAL, "bad argument");
+    CHK(hipStreamSynchronize(ctx->stream));
+    const int64_t avail = std::min<int64_t>(ctx->hist_count, HIST_CAP);
+    const int64_t first = ctx->hist_count - avail;
+    const int64_t m = std::min<int64_t>(avail, max_records);
+    std::vector<double> buf((size_t)HIST_CAP * RED_STRIDE);
+    CHK(hipMemcpy(buf.data(), ctx->hist, buf.size() * sizeof(double), hipMemcpyDeviceToHost));
+    for (int64_t i = 0; i < m; ++i) {
+        const int64_t k = (first + i) % HIST_CAP;
+        unpack_record(&buf[(size_t)k * RED_STRIDE], &out[i]);
+    }
+    *count = (int32_t)m;
+    return LBPF_OK;
+}
+
+lbpf_status lbpf_read_populations(lbpf_ctx* ctx, int32_t field, void* dst) {
+    if (!ctx) return LBPF_EINVAL;
+    if (field < 0 || field > 2 || !dst) return fail(ctx, LBPF_EINVAL, "bad field or NULL dst");
+    CHK(hipStreamSynchronize(ctx->stream));
+    const size_t row = ctx->n * ctx->sbytes;
+    for (int i = 0; i < ctx->q; ++i)
+        CHK(hipMemcpy((char*)dst + i * row, (const char*)ctx->pop[field][ctx->cur] + i * ctx->np * ctx->sbytes,
+                      row, hipMemcpyDeviceToHost));
+    return LBPF_OK;
+}
+
+lbpf_status lbpf_write_populations(lbpf_ctx* ctx, int32_t field, const void* src) {
+    if (!ctx) return LBPF_EINVAL;
+    if (field < 0 || field > 2 || !src) return fail(ctx, LBPF_EINVAL, "bad field or NULL src");
+    if (!ctx->have_fields) return fail(ctx, LBPF_ESTATE, "lbpf_set_fields has not been called");
+    CHK(hipStreamSynchronize(ctx->stream));
+    const size_t row = ctx->n * ctx->sbytes;
+    for (int i = 0; i < ctx->q; ++i)
+        CHK(hipMemcpy((char*)ctx->pop[field][ctx->cur] + i * ctx->np * ctx->sbytes, (const char*)src + i * row,
+                      row, hipMemcpyHostToDevice));
+    return LBPF_OK;
+}
+
+lbpf_status lbpf_read_populations_f64(lbpf_ctx* ctx, int32_t field, double* dst) {
+    if (!ctx) return LBPF_EINVAL;
+    if (field < 0 || field > 2 || !dst) return fail(ctx, LBPF_EINVAL, "bad field or NULL dst");
+    if (!ctx->have_fields) return fail(ctx, LBPF_ESTATE, "lbpf_set_fields has not been called");
+    double* d = nullptr;
+    const size_t bytes = ctx->n * ctx->q * sizeof(double);
+    CHK(hipStreamSynchronize(ctx->stream));
+    CHK(hipMalloc((void**)&d, bytes));
+    lbpf_status st = init_or_decode(ctx, 1, field, d);
+    hipError_t e = hipSuccess;
+    if (!st) e = hipMemcpyAsync(dst, d, bytes, hipMemcpyDeviceToHost, ctx->stream);
+    if (!st && e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+    (void)hipFree(d);
+    if (st) return st;
+    if (e != hipSuccess) return fail(ctx, LBPF_EDEVICE, std::string("decode copy: ") + hipGetErrorString(e));
+    return LBPF_OK;
+}
+
+lbpf_status lbpf_debug_stream_only(lbpf_ctx* ctx, int64_t nsteps) {
+    if (!ctx) return LBPF_EINVAL;
+    if (nsteps < 0) return fail(ctx, LBPF_EINVAL, "nsteps < 0");
+    if (!ctx->have_fields) return fail(ctx, LBPF_ESTATE, "lbpf_set_fields has not been called");
+    for (int64_t s = 0; s < nsteps; ++s) {
+        lbpf_status st = ctx->q == 15 ? stream_only_l<D3Q15>(ctx) : stream_only_l<D3Q19>(ctx);
+        if (st) return st;
+    }
+    return LBPF_OK;
+}
+
+lbpf_status lbpf_set_timing(lbpf_ctx* ctx, int32_t enable) {
+    if (!ctx) return LBPF_EINVAL;
+    CHK(hipStreamSynchronize(ctx->stream));
+    for (auto& l : ctx->launches) {
+        ctx->pool.push_back(l.a);
+        ctx->pool.push_back(l.b);
+    }
+    ctx->launches.clear();
+    for (int i = 0; i < 3; ++i) { ctx->t_ms[i] = 0; ctx->t_n[i] = 0; }
+    ctx->timing = enable != 0;
+    return LBPF_OK;
+}
+
+lbpf_status lbpf_kernel_times(lbpf_ctx* ctx, double ms[3], int64_t launches[3]) {
+    if (!ctx || !ms || !launches) return fail(ctx, LBPF_EINVAL, "bad argument");
+    CHK(hipStreamSynchronize(ctx->stream));
+    for (auto& l : ctx->launches) {
+        float t = 0.f;
+        CHK(hipEventElapsedTime(&t, l.a, l.b));
+        ctx->t_ms[l.kind] += t;
+        ctx->t_n[l.kind] += 1;
+        ctx->pool.push_back(l.a);
+        ctx->pool.push_back(l.b);
+    }
+    ctx->launches.clear();
+    for (int i = 0; i < 3; ++i) { ms[i] = ctx->t_ms[i]; launches[i] = ctx->t_n[i]; }
+    return LBPF_OK;
+}
+
+lbpf_status lbpf_bench_copy(void* dst, const void* src, int64_t nbytes, void* hip_stream) {
+    if (!dst || !src || nbytes < 0 || (nbytes % 16) != 0 || ((uintptr_t)dst % 16) || ((uintptr_t)src % 16))
+        return LBPF_EINVAL;
+    const size_t n16 = (size_t)nbytes / 16;
+    if (n16 == 0) return LBPF_OK;
+    const int nb = (int)std::min<size_t>(4096, (n16 + 255) / 256);
+    hipLaunchKernelGGL(k_copy, dim3(nb), dim3(256), 0, (hipStream_t)hip_stream, (const uint4*)src,
+                       (uint4*)dst, n16);
+    return hipGetLastError() == hipSuccess ? LBPF_OK : LBPF_EDEVICE;
+}
+
+}  // extern "C"

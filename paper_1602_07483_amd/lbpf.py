@@ -1,0 +1,238 @@
+"""ctypes binding of the C ABI declared in include/lbpf.h.
+
+Argument marshalling only: every step of the time step runs in the HIP
+kernels of liblbpf.so.  There is no CPU fallback; importing this module
+raises if the library has not been built.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "liblbpf.so")
+
+LBPF_OK, LBPF_EINVAL, LBPF_ENOMEM, LBPF_EDEVICE, LBPF_EUNSTABLE, LBPF_ESTATE = 0, -1, -2, -3, -4, -5
+LBPF_D3Q15, LBPF_D3Q19 = 15, 19
+LBPF_WALL_NOFLUX, LBPF_WALL_SYMMETRY = 0, 1
+LBPF_F32, LBPF_F16_DEV, LBPF_BF16_DEV, LBPF_F64 = 0, 1, 2, 3
+LBPF_ANISO_CUBIC, LBPF_ANISO_K41K61 = 0, 1
+
+STORAGE = {"f32": LBPF_F32, "f16": LBPF_F16_DEV, "bf16": LBPF_BF16_DEV, "f64": LBPF_F64}
+_POP_DTYPE = {LBPF_F32: np.uint32, LBPF_F16_DEV: np.uint16, LBPF_BF16_DEV: np.uint16,
+              LBPF_F64: np.uint64}
+
+
+class lbpf_grid(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
+                ("lattice", ctypes.c_int32), ("wall", ctypes.c_int32 * 6),
+                ("storage", ctypes.c_int32)]
+
+
+class lbpf_params(ctypes.Structure):
+    _fields_ = [("dx", ctypes.c_double), ("dt", ctypes.c_double),
+                ("W0", ctypes.c_double), ("tau0", ctypes.c_double),
+                ("lam", ctypes.c_double), ("Mcinf", ctypes.c_double),
+                ("k", ctypes.c_double), ("D", ctypes.c_double), ("kappa", ctypes.c_double),
+                ("aniso", ctypes.c_int32), ("eps", ctypes.c_double), ("delta", ctypes.c_double),
+                ("reduce_every", ctypes.c_int32), ("centre", ctypes.c_double * 3)]
+
+
+class lbpf_reductions(ctypes.Structure):
+    _fields_ = [("step", ctypes.c_int64), ("solid_fraction", ctypes.c_double),
+                ("solute_mass", ctypes.c_double), ("enthalpy", ctypes.c_double),
+                ("tip", ctypes.c_double * 3), ("phi_min", ctypes.c_double),
+                ("phi_max", ctypes.c_double), ("nonfinite", ctypes.c_double),
+                ("sum_U", ctypes.c_double), ("sum_phi", ctypes.c_double)]
+
+    def as_dict(self):
+        return {"step": self.step, "solid_fraction": self.solid_fraction,
+                "solute_mass": self.solute_mass, "enthalpy": self.enthalpy,
+                "tip": tuple(self.tip), "phi_min": self.phi_min, "phi_max": self.phi_max,
+                "nonfinite": self.nonfinite, "sum_U": self.sum_U, "sum_phi": self.sum_phi}
+
+
+# Exported symbols, in header order (a CPU test checks each one is exported).
+SYMBOLS = ["lbpf_create", "lbpf_destroy", "lbpf_set_fields", "lbpf_step", "lbpf_sync",
+           "lbpf_read", "lbpf_history", "lbpf_read_populations", "lbpf_write_populations",
+           "lbpf_read_populations_f64",
+           "lbpf_debug_stream_only", "lbpf_set_timing", "lbpf_kernel_times",
+           "lbpf_storage_bytes", "lbpf_bench_copy", "lbpf_last_error"]
+
+
+class LbpfError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__("lbpf status %d: %s" % (status, msg))
+        self.status = status
+
+
+def load():
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError("liblbpf.so is not built (run python -m paper_1602_07483_amd.build)")
+    lib = ctypes.CDLL(LIB_PATH)
+    P = ctypes.POINTER
+    vp, dp = ctypes.c_void_p, P(ctypes.c_double)
+    sig = {
+        "lbpf_create": ([P(lbpf_grid), P(lbpf_params), vp, P(vp)], ctypes.c_int),
+        "lbpf_destroy": ([vp], ctypes.c_int),
+        "lbpf_set_fields": ([vp, dp, dp, dp], ctypes.c_int),
+        "lbpf_step": ([vp, ctypes.c_int64], ctypes.c_int),
+        "lbpf_sync": ([vp], ctypes.c_int),
+        "lbpf_read": ([vp, dp, dp, dp, P(lbpf_reductions)], ctypes.c_int),
+        "lbpf_history": ([vp, P(lbpf_reductions), ctypes.c_int32, P(ctypes.c_int32)], ctypes.c_int),
+        "lbpf_read_populations": ([vp, ctypes.c_int32, vp], ctypes.c_int),
+        "lbpf_write_populations": ([vp, ctypes.c_int32, vp], ctypes.c_int),
+        "lbpf_read_populations_f64": ([vp, ctypes.c_int32, dp], ctypes.c_int),
+        "lbpf_debug_stream_only": ([vp, ctypes.c_int64], ctypes.c_int),
+        "lbpf_set_timing": ([vp, ctypes.c_int32], ctypes.c_int),
+        "lbpf_kernel_times": ([vp, dp, P(ctypes.c_int64)], ctypes.c_int),
+        "lbpf_storage_bytes": ([ctypes.c_int32], ctypes.c_int32),
+        "lbpf_bench_copy": ([vp, vp, ctypes.c_int64, vp], ctypes.c_int),
+        "lbpf_last_error": ([vp], ctypes.c_char_p),
+    }
+    for name, (args, res) in sig.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = res
+    return lib
+
+
+_LIB = None
+
+
+def lib():
+    global _LIB
+    if _LIB is None:
+        _LIB = load()
+    return _LIB
+
+
+def _dptr(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double)) if a is not None else None
+
+
+def lbpf_storage_bytes(storage):
+    return lib().lbpf_storage_bytes(int(storage))
+
+
+def lbpf_bench_copy(dst_ptr, src_ptr, nbytes, stream_ptr=0):
+    return lib().lbpf_bench_copy(ctypes.c_void_p(dst_ptr), ctypes.c_void_p(src_ptr),
+                                 int(nbytes), ctypes.c_void_p(stream_ptr))
+
+
+class Solver:
+    """One lbpf context.  Methods mirror the C entry points
+    (lbpf_create/set_fields/step/read/...); arrays are numpy (nz, ny, nx)."""
+
+    def __init__(self, nx, ny, nz, lattice=19, walls=(0,) * 6, storage="f32", dx=1.0, dt=1.0,
+                 W0=1.0, tau0=1.0, lam=3.2, Mcinf=1.0, k=0.15, D=2.0, kappa=20.0, aniso=0,
+                 eps=0.05, delta=0.0, reduce_every=0, centre=(0.0, 0.0, 0.0), stream=0):
+        self._lib = lib()
+        g = lbpf_grid()
+        g.nx, g.ny, g.nz, g.lattice = int(nx), int(ny), int(nz), int(lattice)
+        for i, w in enumerate(walls):
+            g.wall[i] = int(w)
+        g.storage = STORAGE[storage] if isinstance(storage, str) else int(storage)
+        p = lbpf_params()
+        p.dx, p.dt, p.W0, p.tau0 = dx, dt, W0, tau0
+        p.lam, p.Mcinf, p.k, p.D, p.kappa = lam, Mcinf, k, D, kappa
+        p.aniso, p.eps, p.delta = int(aniso), eps, delta
+        p.reduce_every = int(reduce_every)
+        for i in range(3):
+            p.centre[i] = float(centre[i])
+        self.grid, self.params = g, p
+        self.shape = (int(nz), int(ny), int(nx))
+        self.q = int(lattice)
+        self.storage = g.storage
+        h = ctypes.c_void_p()
+        st = self._lib.lbpf_create(ctypes.byref(g), ctypes.byref(p), ctypes.c_void_p(stream),
+                                   ctypes.byref(h))
+        if st != LBPF_OK:
+            raise LbpfError(st, self._lib.lbpf_last_error(None).decode())
+        self._h = h
+
+    # -- helpers
+    def _check(self, st):
+        if st != LBPF_OK:
+            raise LbpfError(st, self._lib.lbpf_last_error(self._h).decode())
+        return st
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.lbpf_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- C entry points
+    def set_fields(self, phi, U, theta):
+        a = [np.ascontiguousarray(v, dtype=np.float64).reshape(self.shape) for v in (phi, U, theta)]
+        self._check(self._lib.lbpf_set_fields(self._h, _dptr(a[0]), _dptr(a[1]), _dptr(a[2])))
+
+    def step(self, n=1):
+        self._check(self._lib.lbpf_step(self._h, int(n)))
+
+    def sync(self, check=True):
+        st = self._lib.lbpf_sync(self._h)
+        return self._check(st) if check else st
+
+    def read(self, reductions=True, check=True):
+        """(phi, U, theta, reductions-dict or None); raises on EUNSTABLE if check."""
+        out = [np.empty(self.shape) for _ in range(3)]
+        red = lbpf_reductions() if reductions else None
+        st = self._lib.lbpf_read(self._h, _dptr(out[0]), _dptr(out[1]), _dptr(out[2]),
+                                 ctypes.byref(red) if red is not None else None)
+        if check:
+            self._check(st)
+        return out[0], out[1], out[2], (red.as_dict() if red is not None else None)
+
+    def read_status(self):
+        red = lbpf_reductions()
+        st = self._lib.lbpf_read(self._h, None, None, None, ctypes.byref(red))
+        return st, red.as_dict()
+
+    def history(self, max_records=8192):
+        buf = (lbpf_reductions * max_records)()
+        cnt = ctypes.c_int32()
+        self._check(self._lib.lbpf_history(self._h, buf, int(max_records), ctypes.byref(cnt)))
+        return [buf[i].as_dict() for i in range(cnt.value)]
+
+    def read_populations(self, field):
+        out = np.empty((self.q,) + self.shape, dtype=_POP_DTYPE[self.storage])
+        self._check(self._lib.lbpf_read_populations(self._h, int(field),
+                                                    out.ctypes.data_as(ctypes.c_void_p)))
+        return out
+
+    def read_populations_f64(self, field):
+        out = np.empty((self.q,) + self.shape)
+        self._check(self._lib.lbpf_read_populations_f64(self._h, int(field), _dptr(out)))
+        return out
+
+    def write_populations(self, field, arr):
+        a = np.ascontiguousarray(arr).view(_POP_DTYPE[self.storage]).reshape((self.q,) + self.shape)
+        self._check(self._lib.lbpf_write_populations(self._h, int(field),
+                                                     a.ctypes.data_as(ctypes.c_void_p)))
+
+    def debug_stream_only(self, n=1):
+        self._check(self._lib.lbpf_debug_stream_only(self._h, int(n)))
+
+    def set_timing(self, enable=True):
+        self._check(self._lib.lbpf_set_timing(self._h, 1 if enable else 0))
+
+    def kernel_times(self):
+        ms = (ctypes.c_double * 3)()
+        n = (ctypes.c_int64 * 3)()
+        self._check(self._lib.lbpf_kernel_times(self._h, ms, n))
+        return list(ms), list(n)
+
+
+def solver_for(problem, storage="f32", stream=0, **over):
+    """Solver configured from an inputs.Problem (keyword overrides allowed)."""
+    kw = problem.model_kwargs()
+    kw.update(over)
+    return Solver(problem.nx, problem.ny, problem.nz, storage=storage,
+                  reduce_every=problem.reduce_every, centre=problem.centre(), stream=stream, **kw)

@@ -1,0 +1,141 @@
+"""GPU library vs the FP64 oracle, through the C ABI.
+
+Tolerances:
+  * streaming/indexing: bit-exact (integer tags moved by both sides);
+  * FP64 verification build vs the FP64 oracle: 1e-11 max-abs after 300 steps
+    (rounding order and fused multiply-adds only);
+  * FP32 build: max|dphi|, max|dU| <= 1e-5 after 200 steps (the stated target).
+"""
+import numpy as np
+import pytest
+
+from oracle import Oracle, R_SOLID, R_MASS, R_ENTHALPY, R_TIPX, R_TIPY, R_TIPZ, R_PHIMIN, \
+    R_PHIMAX, R_SUMU, R_SUMPHI
+from paper_1602_07483_amd import lbpf
+from paper_1602_07483_amd.inputs import Problem, workload_small, NOFLUX, SYMMETRY, DT
+from tests.pairs import make_oracle, make_gpu, maxabs
+
+pytestmark = pytest.mark.gpu
+
+
+def ragged_problem(lattice=19, aniso=0, walls=(SYMMETRY, NOFLUX, NOFLUX, SYMMETRY, SYMMETRY, NOFLUX)):
+    # sizes not multiples of the 64 x 4 tile nor of the z slab
+    return Problem("ragged", 37, 21, 19, lattice, walls, dt=DT, aniso=aniso,
+                   eps=0.0 if aniso else 0.05, delta=-0.02 if aniso else 0.0,
+                   centres=[(-0.5, 20.5, -0.5)], radius=6.0, U0=-0.5, theta0=-0.5,
+                   noise_amp=1e-3, noise_seed=3)
+
+
+# ------------------------------------------------------------- permutation
+@pytest.mark.parametrize("lattice", [15, 19])
+@pytest.mark.parametrize("storage", ["f32", "f64", "f16"])
+def test_stream_only_bitexact(lattice, storage):
+    walls = (SYMMETRY, NOFLUX, NOFLUX, SYMMETRY, SYMMETRY, NOFLUX)
+    if storage == "f16":
+        shape = (9, 11, 12)    # 16-bit tags stay below 0x7C00 (no Inf/NaN patterns)
+    else:
+        shape = (19, 21, 37)
+    nz, ny, nx = shape
+    pb = Problem("perm", nx, ny, nz, lattice, walls, dt=DT, centres=[(3.0, 3.0, 3.0)])
+    s = make_gpu(pb, storage=storage)
+    o = make_oracle(pb)
+    q = lattice
+    ntag = q * nx * ny * nz
+    rng = np.random.default_rng(lattice)
+    for field in range(3):
+        tags = rng.permutation(ntag).reshape((q,) + shape)
+        if storage == "f32":
+            raw = tags.astype(np.float32).view(np.uint32)
+        elif storage == "f64":
+            raw = tags.astype(np.float64).view(np.uint64)
+        else:
+            raw = tags.astype(np.uint16)
+        s.write_populations(field, raw)
+        o.set_pops(field, tags.astype(np.float64))
+    done = 0
+    for n in (1, 6, 57):
+        s.debug_stream_only(n)
+        o.stream_only(n)
+        done += n
+        for field in range(3):
+            g = s.read_populations(field)
+            ref = o.pops(field)
+            if storage == "f32":
+                gv = g.view(np.float32).astype(np.float64)
+            elif storage == "f64":
+                gv = g.view(np.float64)
+            else:
+                gv = g.astype(np.float64)
+            assert np.array_equal(gv, ref), "field %d after %d steps" % (field, done)
+            assert np.array_equal(np.sort(gv.ravel()), np.arange(ntag)), "not a permutation"
+
+
+# ------------------------------------------------------------- FP64 build
+def _run_both(pb, storage, steps):
+    s = make_gpu(pb, storage=storage)
+    o = make_oracle(pb)
+    s.step(steps)
+    o.step(steps)
+    gphi, gU, gth, red = s.read()
+    ophi, oU, oth = o.fields()
+    return (gphi, gU, gth, red), (ophi, oU, oth, o.reduce(pb.centre()))
+
+
+def test_fp64_matches_oracle_small_workload():
+    pb = workload_small(steps=300)
+    (gphi, gU, gth, red), (ophi, oU, oth, ored) = _run_both(pb, "f64", 300)
+    for name, a, b in (("phi", gphi, ophi), ("U", gU, oU), ("theta", gth, oth)):
+        err = maxabs(a, b)
+        print("fp64 %s max-abs %.3e" % (name, err))
+        assert err <= 1e-11, name
+    assert abs(red["solute_mass"] - ored[R_MASS]) <= 1e-9 * abs(ored[R_MASS])
+    assert abs(red["enthalpy"] - ored[R_ENTHALPY]) <= 1e-9 * max(1.0, abs(ored[R_ENTHALPY]))
+    assert abs(red["solid_fraction"] - ored[R_SOLID]) <= 1e-12
+    for a, key in enumerate((R_TIPX, R_TIPY, R_TIPZ)):
+        assert abs(red["tip"][a] - ored[key]) <= 1e-9
+
+
+@pytest.mark.parametrize("lattice,aniso", [(19, 0), (15, 0), (19, 1)])
+def test_fp64_matches_oracle_ragged(lattice, aniso):
+    pb = ragged_problem(lattice, aniso)
+    (gphi, gU, gth, red), (ophi, oU, oth, ored) = _run_both(pb, "f64", 60)
+    for name, a, b in (("phi", gphi, ophi), ("U", gU, oU), ("theta", gth, oth)):
+        err = maxabs(a, b)
+        print("fp64 ragged q%d aniso%d %s max-abs %.3e" % (lattice, aniso, name, err))
+        assert err <= 1e-11, name
+
+
+# ------------------------------------------------------------- FP32 build
+def test_fp32_matches_oracle_200_steps():
+    pb = workload_small(steps=200)
+    (gphi, gU, gth, red), (ophi, oU, oth, ored) = _run_both(pb, "f32", 200)
+    ephi, eU, eth = maxabs(gphi, ophi), maxabs(gU, oU), maxabs(gth, oth)
+    print("fp32 200 steps: max|dphi| %.3e max|dU| %.3e max|dtheta| %.3e" % (ephi, eU, eth))
+    assert ephi <= 1e-5
+    assert eU <= 1e-5
+    assert eth <= 1e-5
+
+
+@pytest.mark.parametrize("storage", ["f16", "bf16"])
+def test_mixed_storage_error_report(storage):
+    pb = workload_small(steps=200)
+    (gphi, gU, gth, red), (ophi, oU, oth, ored) = _run_both(pb, storage, 200)
+    ephi, eU = maxabs(gphi, ophi), maxabs(gU, oU)
+    print("%s 200 steps: max|dphi| %.3e max|dU| %.3e" % (storage, ephi, eU))
+    # deviation storage: bounded by the 16-bit rounding of the deviations
+    assert ephi <= (2e-3 if storage == "f16" else 2e-2)
+    assert eU <= (2e-3 if storage == "f16" else 2e-2)
+
+
+def test_fp64_populations_match_oracle():
+    pb = ragged_problem(19, 0)
+    s = make_gpu(pb, storage="f64")
+    o = make_oracle(pb)
+    for f in range(3):
+        assert maxabs(s.read_populations_f64(f), o.pops(f)) <= 1e-14, "init field %d" % f
+    s.step(25)
+    o.step(25)
+    for f in range(3):
+        err = maxabs(s.read_populations_f64(f), o.pops(f))
+        print("fp64 populations field %d max-abs %.3e" % (f, err))
+        assert err <= 1e-12, "field %d" % f

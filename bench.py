@@ -1,0 +1,199 @@
+#!/usr/bin/env python3
+"""Benchmark of the lattice-Boltzmann phase-field time step on one MI355X.
+
+Workload: 256^3 nodes, D3Q19 for phi, U and theta, one centred seed of radius
+10 in an undercooled melt (Delta = 0.6, eps = 0.05, k = 0.15), all walls
+no-flux; FP32 populations (headline) and FP16/BF16 deviation storage.  A step
+is one full time step of all three fields (one phase-field kernel + one
+supersaturation/heat kernel).  Inputs are resident in HBM before the timed
+region; the timed region is exactly --steps steps between two device
+synchronisations.
+
+Prints one JSON line.  The roofline entry is for the dominant kernel: its
+algorithmic bytes per launch divided by its mean launch time, measured with
+HIP events on the library's stream during the timed region.  The CPU baseline
+is the FP64 oracle on a bounded sample of the same workload.
+"""
+import argparse
+import hashlib
+import json
+import os
+import re
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "MLUPS (all 3 fields) and HBM GB/s vs roofline; FP32 vs mixed storage, 1 GPU"
+HBM_PEAK_GBS = 8000.0
+# Algorithmic bytes per lattice update and kernel, D3Q19, b bytes per stored
+# population, 4-byte fields: k_phi reads/writes 19 g (2*19*b) + reads phi, U,
+# theta and writes phi (16 B); k_ut reads/writes 19 h and 19 f (4*19*b) +
+# reads phi^n, phi^{n+1}, U, theta and writes U, theta (24 B).
+def bytes_per_lup(q, b):
+    return {"k_phi": 2 * q * b + 16, "k_ut": 4 * q * b + 24}
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in ("kernels.hpp", "lattice.hpp"):
+        with open(os.path.join(ROOT, "paper_1602_07483_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel, storage):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if
+    it was taken on the current kernel source; otherwise None."""
+    path = os.path.join(ROOT, "profiles", "traffic_%s_256cube_%s.md" % (kernel, storage))
+    if not os.path.exists(path):
+        return None
+    text = open(path).read()
+    m_hash = re.search(r"kernel source hash:\s*([0-9a-f]+)", text)
+    m_bytes = re.search(r"HBM bytes per launch \(scaled\):\s*([0-9.eE+]+)", text)
+    if not m_hash or not m_bytes or m_hash.group(1) != kernel_source_hash():
+        return None
+    return float(m_bytes.group(1))
+
+
+def run_gpu(storage, steps, warmup, n):
+    import torch
+    from paper_1602_07483_amd import lbpf
+    from paper_1602_07483_amd.inputs import workload_centred
+
+    pb = workload_centred(n=n)
+    pb.reduce_every = 0
+    stream = torch.cuda.current_stream().cuda_stream
+    s = lbpf.solver_for(pb, storage=storage, stream=stream)
+    s.set_fields(*pb.initial_fields())
+    # launch shape picked by the library's autotuner (state restored after)
+    launch, _ = s.autotune(6)
+    s.step(warmup)
+    s.sync()
+    torch.cuda.synchronize()
+    s.set_timing(True)
+    t0 = time.perf_counter()
+    s.step(steps)
+    s.sync()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms, cnt = s.kernel_times()
+    s.set_timing(False)
+    _, _, _, red = s.read()
+    s.close()
+    lups = float(n) ** 3 * steps
+    b = lbpf.lbpf_storage_bytes(lbpf.STORAGE[storage])
+    bpl = bytes_per_lup(19, b)
+    kern = {}
+    for i, name in enumerate(("k_phi", "k_ut")):
+        avg_ms = ms[i] / max(cnt[i], 1)
+        per_launch = bpl[name] * float(n) ** 3
+        kern[name] = {"avg_ms": avg_ms, "launches": cnt[i], "bytes_per_launch": per_launch,
+                      "GBps": per_launch / (avg_ms * 1e-3) / 1e9}
+    return {"mlups": lups / wall / 1e6, "ms_per_step": wall / steps * 1e3,
+            "launch": {"tile": [launch[0], launch[1]], "zslab": launch[2], "xcd_remap": launch[3]},
+            "algorithmic_GBps": lups * (bpl["k_phi"] + bpl["k_ut"]) / wall / 1e9,
+            "kernels": kern, "solid_fraction": red["solid_fraction"],
+            "phi_range": [red["phi_min"], red["phi_max"]]}
+
+
+def copy_bandwidth(nbytes=2 << 30, reps=20):
+    import torch
+    from paper_1602_07483_amd import lbpf
+    a = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    b = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    stream = torch.cuda.current_stream().cuda_stream
+    lbpf.lbpf_bench_copy(b.data_ptr(), a.data_ptr(), nbytes, stream)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        lbpf.lbpf_bench_copy(b.data_ptr(), a.data_ptr(), nbytes, stream)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / reps
+    return 2.0 * nbytes / dt / 1e9
+
+
+def cpu_baseline(n=256, budget_s=12.0, max_steps=12):
+    """The FP64 oracle, as it stands, on the same workload: steps until about
+    budget_s of stepping (initialisation excluded)."""
+    import oracle
+    from paper_1602_07483_amd.inputs import workload_centred
+    pb = workload_centred(n=n)
+    o = oracle.Oracle(pb.nx, pb.ny, pb.nz, **pb.model_kwargs())
+    o.init(*pb.initial_fields())
+    steps = 0
+    t0 = time.perf_counter()
+    while steps < max_steps:
+        o.step(1)
+        steps += 1
+        if time.perf_counter() - t0 > budget_s:
+            break
+    dt = time.perf_counter() - t0
+    o.close()
+    return {"value": float(n) ** 3 * steps / dt / 1e6, "unit": "MLUPS",
+            "cores": oracle.num_threads(), "kind": "oracle",
+            "sample": "%d^3 D3Q19 centred-seed workload, %d FP64 steps on the host" % (n, steps)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=50)
+    ap.add_argument("--n", type=int, default=256)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
+    ap.add_argument("--no-variants", action="store_true", help="FP32 only")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py: this build runs on one GPU only; --gpus %d is not supported "
+              "(the design notes describe how the step would shard)" % args.gpus, file=sys.stderr)
+        return 2
+    rank = int(os.environ.get("RANK", "0"))
+
+    res = run_gpu("f32", args.steps, args.warmup, args.n)
+    variants = {}
+    if not args.no_variants:
+        for st in ("f16", "bf16"):
+            r = run_gpu(st, args.steps, args.warmup, args.n)
+            variants[st] = {"mlups": r["mlups"], "ms_per_step": r["ms_per_step"], "launch": r["launch"],
+                            "algorithmic_GBps": r["algorithmic_GBps"],
+                            "speedup_vs_f32": r["mlups"] / res["mlups"],
+                            "kernels": r["kernels"]}
+    copy_gbs = copy_bandwidth()
+
+    dom = max(res["kernels"], key=lambda k: res["kernels"][k]["avg_ms"])
+    kd = res["kernels"][dom]
+    traffic = measured_traffic(dom, "f32")
+    roofline = {"bound": "hbm", "kernel": dom, "achieved": kd["GBps"], "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": kd["GBps"] / HBM_PEAK_GBS, "traffic": traffic,
+                "algorithmic_bytes_per_launch": kd["bytes_per_launch"],
+                "avg_launch_ms": kd["avg_ms"], "copy_kernel_GBps": copy_gbs}
+
+    cpu = None
+    if rank == 0 and not args.no_cpu:
+        cpu = cpu_baseline(args.n)
+
+    line = {
+        "metric": METRIC, "value": res["mlups"], "unit": "MLUPS", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": res["ms_per_step"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "centred seed R=10, %d^3 D3Q19, phi/U/theta, Delta=0.6, "
+                               "eps=0.05, k=0.15, no-flux walls" % args.n,
+                   "nodes": args.n ** 3, "lattice": "D3Q19", "storage": "f32"},
+        "algorithmic_GBps": res["algorithmic_GBps"],
+        "launch": res["launch"],
+        "kernels": res["kernels"],
+        "variants": variants,
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "health": {"solid_fraction": res["solid_fraction"], "phi_range": res["phi_range"]},
+    }
+    if rank == 0:
+        print(json.dumps(line), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

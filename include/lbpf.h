@@ -182,6 +182,28 @@ lbpf_status lbpf_debug_stream_only(lbpf_ctx* ctx, int64_t nsteps);
 lbpf_status lbpf_set_timing(lbpf_ctx* ctx, int32_t enable);
 lbpf_status lbpf_kernel_times(lbpf_ctx* ctx, double ms[3], int64_t launches[3]);
 
+/* Launch shape of the two step kernels: a tile of tile_x x tile_y nodes per
+ * block (one thread per node), marching through zslab planes; xcd_remap = 1
+ * deals each of the 8 XCDs one contiguous run of tiles (neighbouring tiles
+ * then share that XCD's L2), 0 keeps the hardware's round-robin order.
+ * Supported tiles: 64x2, 64x4, 32x4, 32x8, 32x16 (FP64 storage: 64x2 and
+ * 32x4); zslab >= 1.  The shape changes speed only, never results.
+ * Default: 32x8 (FP64: 32x4), zslab 8, remap 1.
+ * Errors: EINVAL (unsupported shape or flag). */
+lbpf_status lbpf_set_launch(lbpf_ctx* ctx, int32_t tile_x, int32_t tile_y, int32_t zslab,
+                            int32_t xcd_remap);
+lbpf_status lbpf_get_launch(lbpf_ctx* ctx, int32_t* tile_x, int32_t* tile_y, int32_t* zslab,
+                            int32_t* xcd_remap);
+
+/* Autotuner: times every supported tile shape with zslab in {2,4,8,16,32}
+ * and both XCD orders
+ * (steps_per_candidate steps each, after two untimed steps), keeps the
+ * fastest and restores the state it started from (a temporary device
+ * snapshot of one lattice and the fields is allocated).  *best_ms_per_step
+ * (may be NULL) receives the best time.  Synchronises.
+ * Errors: ESTATE (no fields yet), EINVAL, ENOMEM, EDEVICE. */
+lbpf_status lbpf_autotune(lbpf_ctx* ctx, int32_t steps_per_candidate, double* best_ms_per_step);
+
 /* Bytes of one stored population for a storage type (0 if invalid). */
 int32_t lbpf_storage_bytes(int32_t storage);
 

@@ -60,6 +60,8 @@ def _load():
     lib.orc_reduce.argtypes = [ctypes.c_void_p, dp, dp]
     lib.orc_step_count.restype = ctypes.c_int64
     lib.orc_step_count.argtypes = [ctypes.c_void_p]
+    lib.orc_num_threads.restype = ctypes.c_int
+    lib.orc_num_threads.argtypes = []
     lib.orc_lattice.argtypes = [ctypes.c_int, P(ctypes.c_int32), dp, dp, dp, dp]
     lib.orc_anisotropy.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_double,
                                    dp, dp, dp]
@@ -68,6 +70,11 @@ def _load():
                             ctypes.c_double, dp]
     _lib = lib
     return lib
+
+
+def num_threads():
+    """OpenMP threads used by the oracle's loops."""
+    return int(_load().orc_num_threads())
 
 
 def _dptr(a):

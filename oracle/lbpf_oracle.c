@@ -44,6 +44,9 @@
 #include <math.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 #define MAXQ 19
 #define SMIN 1e-12
@@ -310,6 +313,15 @@ orc_ctx* orc_create(const orc_params* p)
 }
 
 int64_t orc_step_count(const orc_ctx* c) { return c->steps; }
+
+int orc_num_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
 
 /* ------------------------------------------------------------------------- */
 /* Streaming, Sec. 3.4 eq. (Deplacement_STD), with the walls of reading R4.   */

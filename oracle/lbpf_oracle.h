@@ -69,6 +69,8 @@ void     orc_get_pops(const orc_ctx* c, int field, double* out);
 void     orc_set_pops(orc_ctx* c, int field, const double* in);
 void     orc_reduce(const orc_ctx* c, const double centre[3], double* out);
 int64_t  orc_step_count(const orc_ctx* c);
+/* OpenMP threads the oracle's loops use. */
+int      orc_num_threads(void);
 
 /* Pieces exposed for the pins. */
 int      orc_lattice(int q, int32_t* e /* q*3 */, double* w, double* A, double* B, double* e2);

@@ -18,9 +18,13 @@
 //    at once also yields phi^{n+1}(x) = sum_i g_i^{n+1}(x) in the same kernel.
 //  * Node terms (a_s, N, eta_phi, Q_phi for phi; J_tot, S, Q_U/zeta, Q_theta for
 //    U/theta) are computed once per node for the tile plus a one-node halo
-//    and kept in LDS; the stencil fields (phi^n, resp. phi^{n+1}) are staged in
-//    LDS with a two-node halo.  A block owns a 64 x TY column of nodes and
-//    marches through a slab of z planes, rolling three planes of each.
+//    and kept in LDS as two 4-vectors; the stencil field (phi^n, resp.
+//    phi^{n+1} with 1/zeta) is staged in LDS with a two-node halo.  A block
+//    owns a TX x TY column of nodes and marches through a slab of z planes,
+//    rolling three planes of each.
+//  * Links that cannot cross a wall (every link of a tile away from the
+//    walls) take a fast path: compile-time direction, a uniform base pointer
+//    and a 32-bit node offset.  Links that cross a wall take the general path.
 //  * Populations are stored as deviations from their rest equilibria
 //    (w_i phi, (A_i + B_i q/zeta) U, w_i theta) and updated in increment form,
 //    in FP32 (or FP16/BF16 storage with FP32 arithmetic, or FP64 for
@@ -39,13 +43,10 @@
 
 namespace lbpf {
 
-constexpr int TX = 64;   // tile width along x = one wavefront
-
 // --------------------------------------------------------------------------
-// Storage codecs
+// Storage codecs.  Every storage type holds deviations from the rest
+// equilibrium; the codec is only the conversion to the arithmetic type.
 // --------------------------------------------------------------------------
-// Every storage type holds deviations from the rest equilibrium; the codec is
-// only the conversion between the storage type and the arithmetic type.
 template <class S> struct Codec;
 template <> struct Codec<float> {
     __device__ static float dec(float s) { return s; }
@@ -64,6 +65,29 @@ template <> struct Codec<__hip_bfloat16> {
     __device__ static __hip_bfloat16 enc(float v) { return __float2bfloat16(v); }
 };
 
+// Population stores are never re-read by the writing kernel: stream them.
+__device__ __forceinline__ void st_nt(float* p, float v) { __builtin_nontemporal_store(v, p); }
+__device__ __forceinline__ void st_nt(double* p, double v) { __builtin_nontemporal_store(v, p); }
+__device__ __forceinline__ void st_nt(__half* p, __half v) {
+    __builtin_nontemporal_store(__half_as_ushort(v), reinterpret_cast<unsigned short*>(p));
+}
+__device__ __forceinline__ void st_nt(__hip_bfloat16* p, __hip_bfloat16 v) {
+    unsigned short b;
+    __builtin_memcpy(&b, &v, sizeof(b));
+    __builtin_nontemporal_store(b, reinterpret_cast<unsigned short*>(p));
+}
+
+// Reciprocal and reciprocal square root: the hardware instructions (about
+// 1 ulp) in FP32, exact operations in the FP64 verification build.
+__device__ __forceinline__ float frcp(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ double frcp(double x) { return 1.0 / x; }
+__device__ __forceinline__ float frsq(float x) { return __builtin_amdgcn_rsqf(x); }
+__device__ __forceinline__ double frsq(double x) { return 1.0 / sqrt(x); }
+
+template <class T> struct alignas(4 * sizeof(T) > 16 ? 16 : 4 * sizeof(T)) V4 { T x, y, z, w; };
+template <class T> struct alignas(2 * sizeof(T)) V2 { T x, y; };
+template <class T> struct Terms { V4<T> a, b; };
+
 // --------------------------------------------------------------------------
 // Kernel constants (precomputed on the host in FP64, converted to T)
 // --------------------------------------------------------------------------
@@ -73,6 +97,7 @@ struct Coef {
     int symm;          // bit f set: face f (-x,+x,-y,+y,-z,+z) is a symmetry wall
     int zslab;         // z planes per block
     int nbx, nby, nbz; // tiles per axis
+    int remap;         // 1: deal contiguous runs of tiles to each XCD
     long long np;      // elements between two population arrays
     int aniso;
     T eps, delta;
@@ -97,25 +122,31 @@ __device__ __forceinline__ int clampi(int v, int n) { return v < 0 ? 0 : (v >= n
 // Block index remapped so that each XCD (blocks are dealt round-robin to the
 // 8 XCDs) receives one contiguous run of tiles: halo and non-local re-reads of
 // neighbouring tiles then hit the same L2.
-__device__ __forceinline__ int xcd_tile(int b, int total) {
-    if ((total & 7) != 0) return b;
+__device__ __forceinline__ int xcd_tile(int b, int total, int remap) {
+    if (!remap || (total & 7) != 0) return b;
     return (b & 7) * (total >> 3) + (b >> 3);
 }
 
-// Source of the incoming link i at node (x,y,z) for pull streaming.  Returns
-// the source node in (sx,sy,sz), the source direction j and the sign flips
-// (fx,fy,fz) with e_j = (fx ex, fy ey, fz ez).  Walls: half-way bounce-back
-// for no-flux faces, specular reflection for symmetry faces; a link crossing
-// any no-flux face bounces back.
-template <class L>
+// r(phi) = q(phi)/zeta(phi), the same expression wherever a deviation is
+// encoded or decoded.
+template <class T>
+__device__ __forceinline__ T r_of(T f, T zA, T zB) {
+    return T(0.5) * (T(1) - f) * frcp(zA - zB * f);
+}
+
+// Source of the incoming link i at node (x,y,z) for pull streaming, general
+// path.  Returns the source node (sx,sy,sz), the source direction j and the
+// sign flips (fx,fy,fz) with e_j = (fx ex, fy ey, fz ez).  Walls: half-way
+// bounce-back for no-flux faces, specular reflection for symmetry faces; a
+// link crossing any no-flux face bounces back.
 struct Src {
     int sx, sy, sz, j, fx, fy, fz;
 };
 
 template <class L, int I>
-__device__ __forceinline__ Src<L> source(int x, int y, int z, int nx, int ny, int nz, int symm) {
+__device__ __forceinline__ Src source(int x, int y, int z, int nx, int ny, int nz, int symm) {
     constexpr int ex = L::ex(I), ey = L::ey(I), ez = L::ez(I);
-    Src<L> s{x - ex, y - ey, z - ez, I, 1, 1, 1};
+    Src s{x - ex, y - ey, z - ez, I, 1, 1, 1};
     int mask = 0;
     bool nf = false;
     if (ex != 0) {
@@ -141,6 +172,64 @@ __device__ __forceinline__ Src<L> source(int x, int y, int z, int nx, int ny, in
         s.j = find_dir<L>(s.fx * ex, s.fy * ey, s.fz * ez);
     }
     return s;
+}
+
+// Runtime-direction version of source(), for the few links that cross a wall.
+template <class L>
+__device__ __noinline__ Src source_rt(int i, int x, int y, int z, int nx, int ny, int nz, int symm) {
+    const int ex = L::ex(i), ey = L::ey(i), ez = L::ez(i);
+    Src s{x - ex, y - ey, z - ez, i, 1, 1, 1};
+    int mask = 0;
+    bool nf = false;
+    if (s.sx < 0) { mask |= 1; nf |= !(symm & 1); }
+    else if (s.sx >= nx) { mask |= 1; nf |= !(symm & 2); }
+    if (s.sy < 0) { mask |= 2; nf |= !(symm & 4); }
+    else if (s.sy >= ny) { mask |= 2; nf |= !(symm & 8); }
+    if (s.sz < 0) { mask |= 4; nf |= !(symm & 16); }
+    else if (s.sz >= nz) { mask |= 4; nf |= !(symm & 32); }
+    if (mask) {
+        if (nf) {
+            s.sx = x; s.sy = y; s.sz = z; s.fx = -1; s.fy = -1; s.fz = -1;
+        } else {
+            if (mask & 1) { s.sx = x; s.fx = -1; }
+            if (mask & 2) { s.sy = y; s.fy = -1; }
+            if (mask & 4) { s.sz = z; s.fz = -1; }
+        }
+        s.j = find_dir<L>(s.fx * ex, s.fy * ey, s.fz * ez);
+    }
+    return s;
+}
+
+// Does the incoming link I of a node with the given face flags cross a wall?
+struct Faces {
+    bool xl, xh, yl, yh, zl, zh;   // node lies on the -x, +x, -y, +y, -z, +z face
+};
+template <class L, int I>
+__device__ __forceinline__ bool crosses(const Faces& f) {
+    constexpr int ex = L::ex(I), ey = L::ey(I), ez = L::ez(I);
+    bool c = false;
+    if (ex > 0) c |= f.xl;
+    if (ex < 0) c |= f.xh;
+    if (ey > 0) c |= f.yl;
+    if (ey < 0) c |= f.yh;
+    if (ez > 0) c |= f.zl;
+    if (ez < 0) c |= f.zh;
+    return c;
+}
+
+template <class L>
+__device__ __forceinline__ bool crosses_rt(int i, const Faces& f) {
+    const int ex = L::ex(i), ey = L::ey(i), ez = L::ez(i);
+    return (ex > 0 && f.xl) || (ex < 0 && f.xh) || (ey > 0 && f.yl) || (ey < 0 && f.yh) ||
+           (ez > 0 && f.zl) || (ez < 0 && f.zh);
+}
+
+// A value the compiler must treat as changed here: keeps per-direction base
+// pointers from being hoisted into (and spilled from) scalar registers.
+template <class V>
+__device__ __forceinline__ V opaque(V v) {
+    asm volatile("" : "+s"(v));
+    return v;
 }
 
 // Compile-time loop over the directions.
@@ -177,7 +266,7 @@ __device__ __forceinline__ void aniso_terms(const Coef<T>& c, T px, T py, T pz, 
         a = T(1); Nx = T(0); Ny = T(0); Nz = T(0);
         return;
     }
-    const T inv = T(1) / sqrt(s);
+    const T inv = frsq(s);
     const T mag = s * inv;
     const T mx = px * inv, my = py * inv, mz = pz * inv;
     const T x2 = mx * mx, y2 = my * my, z2 = mz * mz;
@@ -209,26 +298,78 @@ __device__ __forceinline__ bool on_noflux_face(int x, int y, int z, int nx, int 
            (z == 0 && !(symm & 16)) || (z == nz - 1 && !(symm & 32));
 }
 
-// Load one (TX+4) x (TY+4) plane of a field into LDS, mirror ghosts by clamping.
-template <class T, int TY>
+// Shared per-block geometry of the 2.5D march.
+template <int TX, int TY>
+struct Tile {
+    static constexpr int NT = TX * TY;
+    static constexpr int PX = TX + 4, PY = TY + 4, PN = PX * PY;   // stencil field, halo 2
+    static constexpr int HX = TX + 2, HY = TY + 2, HN = HX * HY;   // node terms, halo 1
+    int x0, y0, zs, ze, x, y, lt;
+    bool active, xy_inner;
+    Faces f;
+    template <class T>
+    __device__ Tile(const Coef<T>& c) {
+        const int total = c.nbx * c.nby * c.nbz;
+        const int b = xcd_tile(blockIdx.x, total, c.remap);
+        const int bx = b % c.nbx, by = (b / c.nbx) % c.nby, bz = b / (c.nbx * c.nby);
+        x0 = bx * TX;
+        y0 = by * TY;
+        zs = bz * c.zslab;
+        ze = min(zs + c.zslab, c.nz);
+        x = x0 + (int)threadIdx.x % TX;
+        y = y0 + (int)threadIdx.x / TX;
+        lt = (y - y0 + 1) * HX + (x - x0 + 1);
+        active = x < c.nx && y < c.ny;
+        // no node of the tile lies on an x or y face
+        xy_inner = x0 > 0 && x0 + TX < c.nx && y0 > 0 && y0 + TY < c.ny;
+        f.xl = x == 0; f.xh = x == c.nx - 1;
+        f.yl = y == 0; f.yh = y == c.ny - 1;
+        f.zl = false; f.zh = false;
+    }
+};
+
+// Load one (TX+4) x (TY+4) plane of phi into LDS, mirror ghosts by clamping.
+template <class T, int TX, int TY>
 __device__ __forceinline__ void load_plane(T* dst, const T* __restrict__ f, int zz, int x0, int y0,
-                                           int nx, int ny, int nz, int tid) {
-    constexpr int PX = TX + 4, PY = TY + 4, NT = TX * TY;
+                                           int nx, int ny, int nz) {
+    using G = Tile<TX, TY>;
     const int gz = clampi(zz, nz);
     const size_t base = (size_t)gz * (size_t)nx * (size_t)ny;
-    for (int t = tid; t < PX * PY; t += NT) {
-        const int lx = t % PX, ly = t / PX;
+    for (int t = threadIdx.x; t < G::PN; t += G::NT) {
+        const int lx = t % G::PX, ly = t / G::PX;
         const int gx = clampi(x0 - 2 + lx, nx), gy = clampi(y0 - 2 + ly, ny);
         dst[t] = f[base + (size_t)gy * nx + gx];
     }
 }
 
-// r(phi) = q(phi)/zeta(phi), the same expression wherever a deviation is
-// encoded or decoded.
-template <class T>
-__device__ __forceinline__ T r_of(T f, T zA, T zB) {
-    return T(0.5) * (T(1) - f) / (zA - zB * f);
+// Same, storing (phi, 1/zeta(phi)).
+template <class T, int TX, int TY>
+__device__ __forceinline__ void load_plane_w(V2<T>* dst, const T* __restrict__ f, int zz, int x0,
+                                             int y0, int nx, int ny, int nz, T zA, T zB) {
+    using G = Tile<TX, TY>;
+    const int gz = clampi(zz, nz);
+    const size_t base = (size_t)gz * (size_t)nx * (size_t)ny;
+    for (int t = threadIdx.x; t < G::PN; t += G::NT) {
+        const int lx = t % G::PX, ly = t / G::PX;
+        const int gx = clampi(x0 - 2 + lx, nx), gy = clampi(y0 - 2 + ly, ny);
+        const T p = f[base + (size_t)gy * nx + gx];
+        dst[t] = V2<T>{p, frcp(zA - zB * p)};
+    }
 }
+
+// ==========================================================================
+// The march.  Iteration zz of a block stages the stencil-field plane zz (A),
+// computes the node terms of plane zz-1 (B) and pulls plane zz-2 (C).  All
+// global loads an iteration needs (the field plane, the fields at the term
+// nodes and the populations of the pulled plane) are issued together at the
+// end of the previous iteration, so each iteration waits for memory once.
+// ==========================================================================
+template <int TX, int TY>
+struct March {
+    using G = Tile<TX, TY>;
+    static constexpr int NA = (G::PN + G::NT - 1) / G::NT;   // staged values per thread
+    static constexpr int NB = (G::HN + G::NT - 1) / G::NT;   // term nodes per thread
+};
 
 // ==========================================================================
 // K_phi: phase-field node terms, non-local collision and pull streaming.
@@ -243,103 +384,179 @@ __device__ __forceinline__ T r_of(T f, T zA, T zB) {
 // A = 1/a_s^2 (1 on boundary nodes), V = omega c_phi N / e^2, so that
 //   phi^{n+1}(x) = phi_x + sum_i inc_i,   d_i^{n+1}(x) = inc_i - w_i sum_i inc_i.
 // Only small quantities are rounded besides the one update of phi.
+// LDS terms: a = (A, A(1-omega), A Q dt/tau0, phi), b = (A V, 0).
 // ==========================================================================
-template <class L, class T, class S, int TY>
+template <class L, class T, class S, int TX, int TY>
 __global__ __launch_bounds__(TX * TY) void k_phi(const Coef<T> c, const S* __restrict__ gin,
                                                  S* __restrict__ gout, const T* __restrict__ phin,
                                                  const T* __restrict__ Un, const T* __restrict__ thn,
                                                  T* __restrict__ phout) {
-    constexpr int NT = TX * TY;
-    constexpr int PX = TX + 4, PY = TY + 4, HX = TX + 2, HY = TY + 2, HN = HX * HY;
-    constexpr int NTERM = 7;   // A, A(1-omega), A Q dt/tau0, A V (3), phi
-    __shared__ T sphi[3][PX * PY];
-    __shared__ T sterm[3][NTERM][HN];
+    using G = Tile<TX, TY>;
+    using M = March<TX, TY>;
+    __shared__ T sphi[3][G::PN];
+    __shared__ Terms<T> sterm[3][G::HN];
 
+    G tile(c);
     const int nx = c.nx, ny = c.ny, nz = c.nz;
-    const int total = c.nbx * c.nby * c.nbz;
-    const int b = xcd_tile(blockIdx.x, total);
-    const int bx = b % c.nbx, by = (b / c.nbx) % c.nby, bz = b / (c.nbx * c.nby);
-    const int tid = threadIdx.x;
-    const int x0 = bx * TX, y0 = by * TY;
-    const int zs = bz * c.zslab;
-    const int ze = min(zs + c.zslab, nz);
-    const int x = x0 + tid % TX, y = y0 + tid / TX;
-    const bool active = x < nx && y < ny;
-    const size_t plane = (size_t)nx * (size_t)ny;
+    const unsigned plane = (unsigned)nx * (unsigned)ny;
 
-    for (int zz = zs - 2; zz <= ze + 1; ++zz) {
-        // A: phi^n plane zz
-        load_plane<T, TY>(sphi[(zz + 3) % 3], phin, zz, x0, y0, nx, ny, nz, tid);
+    // registers filled one iteration ahead
+    T pa[M::NA];                       // phi^n of the staged plane
+    T pu[M::NB], pt[M::NB];            // U^n, theta^n at the term nodes
+    T pj[L::Q], pnl[L::Q];             // d_j(source) and d_i(x) of the pulled plane
+    auto prefetch = [&](int zz) {
+        {   // A of iteration zz
+            const size_t base = (size_t)clampi(zz, nz) * plane;
+#pragma unroll
+            for (int k = 0; k < M::NA; ++k) {
+                const int t = (int)threadIdx.x + k * G::NT;
+                if (t < G::PN) {
+                    const int gx = clampi(tile.x0 - 2 + t % G::PX, nx), gy = clampi(tile.y0 - 2 + t / G::PX, ny);
+                    pa[k] = phin[base + (size_t)gy * nx + gx];
+                }
+            }
+        }
+        if (zz >= tile.zs) {   // B of iteration zz: terms of plane zz-1
+            const size_t base = (size_t)clampi(zz - 1, nz) * plane;
+#pragma unroll
+            for (int k = 0; k < M::NB; ++k) {
+                const int t = (int)threadIdx.x + k * G::NT;
+                if (t < G::HN) {
+                    const int gx = clampi(tile.x0 - 1 + t % G::HX, nx), gy = clampi(tile.y0 - 1 + t / G::HX, ny);
+                    const size_t gi = base + (size_t)gy * nx + gx;
+                    pu[k] = Un[gi];
+                    pt[k] = thn[gi];
+                }
+            }
+        }
+        if (zz >= tile.zs + 2 && tile.active) {   // C of iteration zz: plane zz-2
+            const int z = zz - 2;
+            const unsigned xi = (unsigned)z * plane + (unsigned)tile.y * nx + tile.x;
+            Faces f = tile.f;
+            f.zl = z == 0;
+            f.zh = z == nz - 1;
+            const size_t np = (size_t)opaque(c.np);
+            Unroll<0, L::Q>::run([&](auto ic) {
+                constexpr int I = decltype(ic)::value;
+                constexpr int ex = L::ex(I), ey = L::ey(I), ez = L::ez(I);
+                const S* gI = gin + (size_t)I * np;
+                unsigned so = xi - (unsigned)(ex + ey * nx + ez * (int)plane);
+                so = crosses<L, I>(f) ? xi : so;     // wall links: any in-bounds address
+                pnl[I] = (T)Codec<S>::dec(gI[xi]);
+                pj[I] = (T)Codec<S>::dec(gI[so]);
+            });
+        }
+    };
+
+    prefetch(tile.zs - 2);
+    for (int zz = tile.zs - 2; zz <= tile.ze + 1; ++zz) {
+        // A: stage phi^n plane zz
+        {
+            T* dst = sphi[(zz + 3) % 3];
+#pragma unroll
+            for (int k = 0; k < M::NA; ++k) {
+                const int t = (int)threadIdx.x + k * G::NT;
+                if (t < G::PN) dst[t] = pa[k];
+            }
+        }
         __syncthreads();
         // B: node terms of plane zz-1 (needs phi^n planes zz-2 .. zz)
-        if (zz >= zs) {
+        if (zz >= tile.zs) {
             const int pz = zz - 1;
             const T* fm = sphi[(pz + 2) % 3];
             const T* f0 = sphi[(pz + 3) % 3];
             const T* fp = sphi[(pz + 4) % 3];
-            T(*st)[HN] = sterm[(pz + 3) % 3];
-            const int gz = clampi(pz, nz);
-            for (int t = tid; t < HN; t += NT) {
-                const int lx = t % HX, ly = t / HX;
-                const int rx = x0 - 1 + lx, ry = y0 - 1 + ly;
-                const int gx = clampi(rx, nx), gy = clampi(ry, ny);
-                const int ctr = (ly + 1) * PX + (lx + 1);
+            Terms<T>* st = sterm[(pz + 3) % 3];
+#pragma unroll
+            for (int k = 0; k < M::NB; ++k) {
+                const int t = (int)threadIdx.x + k * G::NT;
+                if (t >= G::HN) break;
+                const int lx = t % G::HX, ly = t / G::HX;
+                const int rx = tile.x0 - 1 + lx, ry = tile.y0 - 1 + ly;
+                const int ctr = (ly + 1) * G::PX + (lx + 1);
                 const T ph = f0[ctr];
                 const T px = (f0[ctr + 1] - f0[ctr - 1]) * c.inv2dx;
-                const T py = (f0[ctr + PX] - f0[ctr - PX]) * c.inv2dx;
+                const T py = (f0[ctr + G::PX] - f0[ctr - G::PX]) * c.inv2dx;
                 const T pzg = (fp[ctr] - fm[ctr]) * c.inv2dx;
                 T a, Nx, Ny, Nz;
                 aniso_terms(c, px, py, pzg, a, Nx, Ny, Nz);
-                const size_t gi = (size_t)gz * plane + (size_t)gy * nx + gx;
-                const T u = Un[gi], th = thn[gi];
                 const T a2 = a * a;
-                const T om = T(1) / (a2 * c.eta_c + T(0.5));          // eq. (LBE_RelaxationTime)
+                const T om = frcp(a2 * c.eta_c + T(0.5));            // eq. (LBE_RelaxationTime)
                 const T one_m = T(1) - ph * ph;
-                const T Qp = (ph - c.lambda * (c.Mcinf * u + th) * one_m) * one_m;  // eq. (LBE_SourceTerm)
+                const T Qp = (ph - c.lambda * (c.Mcinf * pu[k] + pt[k]) * one_m) * one_m;  // eq. (LBE_SourceTerm)
                 const bool bnd = on_noflux_face(rx, ry, pz, nx, ny, nz, c.symm);
-                const T A = T(1) / (bnd ? T(1) : a2);
+                const T A = bnd ? T(1) : frcp(a2);
                 const T av = A * om * c.cphi_e2;
-                st[0][t] = A;
-                st[1][t] = A * (T(1) - om);
-                st[2][t] = A * Qp * c.dt_tau0;
-                st[3][t] = av * Nx;
-                st[4][t] = av * Ny;
-                st[5][t] = av * Nz;
-                st[6][t] = ph;
+                st[t].a = V4<T>{A, A * (T(1) - om), A * Qp * c.dt_tau0, ph};
+                st[t].b = V4<T>{av * Nx, av * Ny, av * Nz, T(0)};
             }
         }
         __syncthreads();
         // C: pull plane zz-2 (terms of planes zz-3 .. zz-1 are ready)
-        if (zz >= zs + 2 && active) {
+        if (zz >= tile.zs + 2 && tile.active) {
             const int z = zz - 2;
-            const size_t xi = (size_t)z * plane + (size_t)y * nx + x;
-            const T phx = sterm[(z + 3) % 3][6][(y - y0 + 1) * HX + (x - x0 + 1)];
+            const unsigned xi = (unsigned)z * plane + (unsigned)tile.y * nx + tile.x;
+            const int sl[3] = {(z + 2) % 3, (z + 3) % 3, (z + 4) % 3};   // planes z-1, z, z+1
+            const T phx = sterm[sl[1]][tile.lt].a.w;
+            Faces f = tile.f;
+            f.zl = z == 0;
+            f.zh = z == nz - 1;
+            const bool edge = !(tile.xy_inner && z > 0 && z < nz - 1);
+            const size_t np = (size_t)opaque(c.np);
             T inc[L::Q];
             T dsum = T(0);
-            Unroll<0, L::Q>::run([&](auto ic) {
+            // Every link as if its source x - e_i were inside the domain; on
+            // edge tiles, links that cross a wall contribute zero here.
+            auto fast = [&](auto ic, auto edge_c) {
                 constexpr int I = decltype(ic)::value;
-                const Src<L> s = source<L, I>(x, y, z, nx, ny, nz, c.symm);
-                const size_t si = (size_t)s.sz * plane + (size_t)s.sy * nx + s.sx;
-                const T dj = (T)Codec<S>::dec(gin[(size_t)s.j * c.np + si]);
-                const T dnl = (T)Codec<S>::dec(gin[(size_t)I * c.np + xi]);
-                T(*st)[HN] = sterm[(s.sz + 3) % 3];
-                const int tl = (s.sy - y0 + 1) * HX + (s.sx - x0 + 1);
+                constexpr bool EDGE = decltype(edge_c)::value;
+                constexpr int ex = L::ex(I), ey = L::ey(I), ez = L::ez(I);
                 constexpr T wi = T(L::w(I));
-                const T A = st[0][tl];
-                const T eAV = T(s.fx * L::ex(I)) * st[3][tl] + T(s.fy * L::ey(I)) * st[4][tl] +
-                              T(s.fz * L::ez(I)) * st[5][tl];
-                const T v = wi * (A * (st[6][tl] - phx) + st[2][tl] - eAV) + st[1][tl] * dj -
-                            (A - T(1)) * dnl;
+                const Terms<T>& t = sterm[sl[1 - ez]][tile.lt - ex - ey * G::HX];
+                const T eAV = T(ex) * t.b.x + T(ey) * t.b.y + T(ez) * t.b.z;
+                T v = wi * (t.a.x * (t.a.w - phx) + t.a.z - eAV) + t.a.y * pj[I] - (t.a.x - T(1)) * pnl[I];
+                if constexpr (EDGE) v = crosses<L, I>(f) ? T(0) : v;
                 inc[I] = v;
                 dsum += v;
-            });
+            };
+            // Links that cross a wall: source after bounce-back or reflection.
+            auto wall_link = [&](int i) -> T {
+                const Src s = source_rt<L>(i, tile.x, tile.y, z, nx, ny, nz, c.symm);
+                const size_t si = ((size_t)s.sz * ny + s.sy) * nx + s.sx;
+                const T dj = (T)Codec<S>::dec(gin[(size_t)s.j * np + si]);
+                const T dnl = (T)Codec<S>::dec(gin[(size_t)i * np + xi]);
+                const Terms<T>& t = sterm[(s.sz + 3) % 3][(s.sy - tile.y0 + 1) * G::HX + (s.sx - tile.x0 + 1)];
+                const T eAV = T(s.fx * L::ex(i)) * t.b.x + T(s.fy * L::ey(i)) * t.b.y +
+                              T(s.fz * L::ez(i)) * t.b.z;
+                return T(L::w(i)) * (t.a.x * (t.a.w - phx) + t.a.z - eAV) + t.a.y * dj -
+                       (t.a.x - T(1)) * dnl;
+            };
+            const bool on_face = f.xl || f.xh || f.yl || f.yh || f.zl || f.zh;
+            if (!edge) {
+                Unroll<0, L::Q>::run([&](auto ic) { fast(ic, std::false_type{}); });
+            } else {
+                Unroll<0, L::Q>::run([&](auto ic) { fast(ic, std::true_type{}); });
+                if (on_face) {
+#pragma unroll 1
+                    for (int i = 1; i < L::Q; ++i)
+                        if (crosses_rt<L>(i, f)) dsum += wall_link(i);
+                }
+            }
             phout[xi] = phx + dsum;
             Unroll<0, L::Q>::run([&](auto ic) {
                 constexpr int I = decltype(ic)::value;
                 constexpr T wi = T(L::w(I));
-                gout[(size_t)I * c.np + xi] = Codec<S>::enc(inc[I] - wi * dsum);
+                st_nt(&gout[(size_t)I * np + xi], Codec<S>::enc(inc[I] - wi * dsum));
             });
+            if (edge && on_face) {
+                // overwrite the wall-crossing links (same thread, same address)
+#pragma unroll 1
+                for (int i = 1; i < L::Q; ++i)
+                    if (crosses_rt<L>(i, f))
+                        gout[(size_t)i * np + xi] = Codec<S>::enc(wall_link(i) - T(L::w(i)) * dsum);
+            }
         }
+        if (zz + 1 <= tile.ze + 1) prefetch(zz + 1);
     }
 }
 
@@ -356,72 +573,123 @@ __global__ __launch_bounds__(TX * TY) void k_phi(const Coef<T> c, const S* __res
 //   h_i^{n+1}(x) = (A_i + B_i r^o_x) U_x + incU_i,
 //   incU_i = [i>0] w_i (P_y - P_x) + B_i C_y + (1 - omega_U) dh_j(y) + w_i (S_y + e_j.K_y),
 //   f_i^{n+1}(x) = w_i theta_x + incT_i,
-//   incT_i = w_i (theta_y - theta_x) + (1 - omega_theta) df_j(y) + w_i (phi^{n+1}_y - phi^n_y)/2,
+//   incT_i = w_i (theta_y + (phi^{n+1}_y - phi^n_y)/2 - theta_x) + (1 - omega_theta) df_j(y),
 // then U^{n+1} = U_x + dU, theta^{n+1} = theta_x + dT and the new deviations
 //   dh_i = incU_i - A_i dU + B_i [(r^o_x - r_x) U_x - r_x dU],  df_i = incT_i - w_i dT.
+// LDS terms: a = (P, C, S, theta + dphi/2), b = (K, r).
 // ==========================================================================
-template <class L, class T, class S, int TY>
+template <class L, class T, class S, int TX, int TY>
 __global__ __launch_bounds__(TX * TY) void k_ut(const Coef<T> c, const S* __restrict__ hin,
                                                 S* __restrict__ hout, const S* __restrict__ fin,
                                                 S* __restrict__ fout, const T* __restrict__ phio,
                                                 const T* __restrict__ phnew, const T* __restrict__ Un,
                                                 const T* __restrict__ thn, T* __restrict__ Uout,
                                                 T* __restrict__ thout) {
-    constexpr int NT = TX * TY;
-    constexpr int PX = TX + 4, PY = TY + 4, HX = TX + 2, HY = TY + 2, HN = HX * HY;
-    constexpr int NTERM = 9;   // P, C, S, Kx, Ky, Kz, theta, G, r
-    __shared__ T sphi[3][PX * PY];
-    __shared__ T sterm[3][NTERM][HN];
+    using G = Tile<TX, TY>;
+    using M = March<TX, TY>;
+    __shared__ V2<T> sphi[3][G::PN];      // (phi^{n+1}, 1/zeta)
+    __shared__ Terms<T> sterm[3][G::HN];
 
+    G tile(c);
     const int nx = c.nx, ny = c.ny, nz = c.nz;
-    const int total = c.nbx * c.nby * c.nbz;
-    const int b = xcd_tile(blockIdx.x, total);
-    const int bx = b % c.nbx, by = (b / c.nbx) % c.nby, bz = b / (c.nbx * c.nby);
-    const int tid = threadIdx.x;
-    const int x0 = bx * TX, y0 = by * TY;
-    const int zs = bz * c.zslab;
-    const int ze = min(zs + c.zslab, nz);
-    const int x = x0 + tid % TX, y = y0 + tid / TX;
-    const bool active = x < nx && y < ny;
-    const size_t plane = (size_t)nx * (size_t)ny;
+    const unsigned plane = (unsigned)nx * (unsigned)ny;
     const T k = c.k;
     const T zA = T(0.5) * (T(1) + k), zB = T(0.5) * (T(1) - k);
+    const T omU1 = T(1) - c.omU, omT1 = T(1) - c.omT;
 
-    for (int zz = zs - 2; zz <= ze + 1; ++zz) {
-        load_plane<T, TY>(sphi[(zz + 3) % 3], phnew, zz, x0, y0, nx, ny, nz, tid);
+    T pa[M::NA];                          // phi^{n+1} of the staged plane
+    T po_[M::NB], pu[M::NB], pt[M::NB];   // phi^n, U^n, theta^n at the term nodes
+    T ph_[L::Q], pf_[L::Q];               // dh_j, df_j of the pulled plane's sources
+    T pUx = T(0), pthx = T(0);            // U^n, theta^n of the pulled node
+    auto prefetch = [&](int zz) {
+        {
+            const size_t base = (size_t)clampi(zz, nz) * plane;
+#pragma unroll
+            for (int kk = 0; kk < M::NA; ++kk) {
+                const int t = (int)threadIdx.x + kk * G::NT;
+                if (t < G::PN) {
+                    const int gx = clampi(tile.x0 - 2 + t % G::PX, nx), gy = clampi(tile.y0 - 2 + t / G::PX, ny);
+                    pa[kk] = phnew[base + (size_t)gy * nx + gx];
+                }
+            }
+        }
+        if (zz >= tile.zs) {
+            const size_t base = (size_t)clampi(zz - 1, nz) * plane;
+#pragma unroll
+            for (int kk = 0; kk < M::NB; ++kk) {
+                const int t = (int)threadIdx.x + kk * G::NT;
+                if (t < G::HN) {
+                    const int gx = clampi(tile.x0 - 1 + t % G::HX, nx), gy = clampi(tile.y0 - 1 + t / G::HX, ny);
+                    const size_t gi = base + (size_t)gy * nx + gx;
+                    po_[kk] = phio[gi];
+                    pu[kk] = Un[gi];
+                    pt[kk] = thn[gi];
+                }
+            }
+        }
+        if (zz >= tile.zs + 2 && tile.active) {
+            const int z = zz - 2;
+            const unsigned xi = (unsigned)z * plane + (unsigned)tile.y * nx + tile.x;
+            Faces f = tile.f;
+            f.zl = z == 0;
+            f.zh = z == nz - 1;
+            const size_t np = (size_t)opaque(c.np);
+            pUx = Un[xi];
+            pthx = thn[xi];
+            Unroll<0, L::Q>::run([&](auto ic) {
+                constexpr int I = decltype(ic)::value;
+                constexpr int ex = L::ex(I), ey = L::ey(I), ez = L::ez(I);
+                unsigned so = xi - (unsigned)(ex + ey * nx + ez * (int)plane);
+                so = crosses<L, I>(f) ? xi : so;     // wall links: any in-bounds address
+                ph_[I] = (T)Codec<S>::dec(hin[(size_t)I * np + so]);
+                pf_[I] = (T)Codec<S>::dec(fin[(size_t)I * np + so]);
+            });
+        }
+    };
+
+    prefetch(tile.zs - 2);
+    for (int zz = tile.zs - 2; zz <= tile.ze + 1; ++zz) {
+        {
+            V2<T>* dst = sphi[(zz + 3) % 3];
+#pragma unroll
+            for (int kk = 0; kk < M::NA; ++kk) {
+                const int t = (int)threadIdx.x + kk * G::NT;
+                if (t < G::PN) dst[t] = V2<T>{pa[kk], frcp(zA - zB * pa[kk])};
+            }
+        }
         __syncthreads();
-        if (zz >= zs) {
+        if (zz >= tile.zs) {
             const int pz = zz - 1;
-            const T* fm = sphi[(pz + 2) % 3];
-            const T* f0 = sphi[(pz + 3) % 3];
-            const T* fp = sphi[(pz + 4) % 3];
-            T(*st)[HN] = sterm[(pz + 3) % 3];
-            const int gz = clampi(pz, nz);
-            for (int t = tid; t < HN; t += NT) {
-                const int lx = t % HX, ly = t / HX;
-                const int gx = clampi(x0 - 1 + lx, nx), gy = clampi(y0 - 1 + ly, ny);
-                const int ctr = (ly + 1) * PX + (lx + 1);
-                // phi^{n+1} at the node and its six neighbours (mirror ghosts)
-                const T p0 = f0[ctr];
-                const T pn[6] = {f0[ctr + 1], f0[ctr - 1], f0[ctr + PX], f0[ctr - PX], fp[ctr], fm[ctr]};
-                const T w0 = T(1) / (zA - zB * p0);      // 1/zeta
+            const V2<T>* fm = sphi[(pz + 2) % 3];
+            const V2<T>* f0 = sphi[(pz + 3) % 3];
+            const V2<T>* fp = sphi[(pz + 4) % 3];
+            Terms<T>* st = sterm[(pz + 3) % 3];
+#pragma unroll
+            for (int kk = 0; kk < M::NB; ++kk) {
+                const int t = (int)threadIdx.x + kk * G::NT;
+                if (t >= G::HN) break;
+                const int lx = t % G::HX, ly = t / G::HX;
+                const int ctr = (ly + 1) * G::PX + (lx + 1);
+                // phi^{n+1} and 1/zeta at the node and its six neighbours (mirror ghosts)
+                const V2<T> c0 = f0[ctr];
+                const V2<T> nb[6] = {f0[ctr + 1], f0[ctr - 1], f0[ctr + G::PX], f0[ctr - G::PX],
+                                     fp[ctr], fm[ctr]};
+                const T p0 = c0.x, w0 = c0.y;
                 const T q0 = T(0.5) * (T(1) - p0);       // q(phi)
-                const T r0 = r_of(p0, zA, zB);           // q/zeta
-                T wn[6], qn[6], rn[6];
+                const T r0 = q0 * w0;                    // q/zeta
+                T qn[6], rn[6];
 #pragma unroll
                 for (int d = 0; d < 6; ++d) {
-                    wn[d] = T(1) / (zA - zB * pn[d]);
-                    qn[d] = T(0.5) * (T(1) - pn[d]);
-                    rn[d] = r_of(pn[d], zA, zB);
+                    qn[d] = T(0.5) * (T(1) - nb[d].x);
+                    rn[d] = qn[d] * nb[d].y;
                 }
                 const T Gx = (rn[0] - rn[1]) * c.inv2dx, Gy = (rn[2] - rn[3]) * c.inv2dx,
                         Gz = (rn[4] - rn[5]) * c.inv2dx;
-                const T Fx = (wn[0] - wn[1]) * c.inv2dx, Fy = (wn[2] - wn[3]) * c.inv2dx,
-                        Fz = (wn[4] - wn[5]) * c.inv2dx;
-                const T gx_ = (pn[0] - pn[1]) * c.inv2dx, gy_ = (pn[2] - pn[3]) * c.inv2dx,
-                        gz_ = (pn[4] - pn[5]) * c.inv2dx;
-                const size_t gi = (size_t)gz * plane + (size_t)gy * nx + gx;
-                const T po = phio[gi], u = Un[gi], th = thn[gi];
+                const T Fx = (nb[0].y - nb[1].y) * c.inv2dx, Fy = (nb[2].y - nb[3].y) * c.inv2dx,
+                        Fz = (nb[4].y - nb[5].y) * c.inv2dx;
+                const T gx_ = (nb[0].x - nb[1].x) * c.inv2dx, gy_ = (nb[2].x - nb[3].x) * c.inv2dx,
+                        gz_ = (nb[4].x - nb[5].x) * c.inv2dx;
+                const T po = po_[kk], u = pu[kk], th = pt[kk];
                 const T dphi = p0 - po;
                 const T dtphi = dphi * c.inv_dt;
                 const T cu = T(1) + (T(1) - k) * u;
@@ -429,15 +697,15 @@ __global__ __launch_bounds__(TX * TY) void k_ut(const Coef<T> c, const S* __rest
                 T jx = T(0), jy = T(0), jz = T(0);
                 const T s2 = gx_ * gx_ + gy_ * gy_ + gz_ * gz_;
                 if (s2 > c.smin) {
-                    const T f = -c.jat_c * cu * dtphi / sqrt(s2);
+                    const T f = -c.jat_c * cu * dtphi * frsq(s2);
                     jx = f * gx_; jy = f * gy_; jz = f * gz_;
                 }
                 // compact div(q grad(1/zeta))
                 T div = T(0);
 #pragma unroll
                 for (int a = 0; a < 3; ++a)
-                    div += T(0.5) * (q0 + qn[2 * a]) * (wn[2 * a] - w0) -
-                           T(0.5) * (q0 + qn[2 * a + 1]) * (w0 - wn[2 * a + 1]);
+                    div += T(0.5) * (q0 + qn[2 * a]) * (nb[2 * a].y - w0) -
+                           T(0.5) * (q0 + qn[2 * a + 1]) * (w0 - nb[2 * a + 1].y);
                 div *= c.inv_dx2;
                 // J_tot (eq. Def_Jtot), S (eq. Def_S), Q_U/zeta (eq. Def_Qu)
                 const T Du = c.D * u;
@@ -447,59 +715,98 @@ __global__ __launch_bounds__(TX * TY) void k_ut(const Coef<T> c, const S* __rest
                 const T Sflux = Du * div + jx * Fx + jy * Fy + jz * Fz;
                 const T src = Sflux + cu * T(0.5) * dtphi * w0;
                 const T ro = r_of(po, zA, zB);
-                st[0][t] = ro * u;
-                st[1][t] = c.omU * (r0 - ro) * u;
-                st[2][t] = src * c.dt;
-                st[3][t] = c.jcoef * Jx;
-                st[4][t] = c.jcoef * Jy;
-                st[5][t] = c.jcoef * Jz;
-                st[6][t] = th;
-                st[7][t] = T(0.5) * dphi;   // Q_theta dt, eq. (Source_Tempr)
-                st[8][t] = r0;
+                st[t].a = V4<T>{ro * u, c.omU * (r0 - ro) * u, src * c.dt, th + T(0.5) * dphi};
+                st[t].b = V4<T>{c.jcoef * Jx, c.jcoef * Jy, c.jcoef * Jz, r0};
             }
         }
         __syncthreads();
-        if (zz >= zs + 2 && active) {
+        if (zz >= tile.zs + 2 && tile.active) {
             const int z = zz - 2;
-            const size_t xi = (size_t)z * plane + (size_t)y * nx + x;
-            const int tx_ = (y - y0 + 1) * HX + (x - x0 + 1);
-            T(*sx)[HN] = sterm[(z + 3) % 3];
-            const T Px = sx[0][tx_], Cx = sx[1][tx_], thx = sx[6][tx_], rx = sx[8][tx_];
-            const T Ux = Un[xi];
+            const unsigned xi = (unsigned)z * plane + (unsigned)tile.y * nx + tile.x;
+            const int sl[3] = {(z + 2) % 3, (z + 3) % 3, (z + 4) % 3};
+            const Terms<T>& own = sterm[sl[1]][tile.lt];
+            const T Px = own.a.x, Cx = own.a.y, rx = own.b.w;
+            const T Ux = pUx, thx = pthx;
+            Faces f = tile.f;
+            f.zl = z == 0;
+            f.zh = z == nz - 1;
+            const bool edge = !(tile.xy_inner && z > 0 && z < nz - 1);
+            const size_t np = (size_t)opaque(c.np);
             T iu[L::Q], it[L::Q];
             T du = T(0), dth = T(0);
-            Unroll<0, L::Q>::run([&](auto ic) {
+            auto fast = [&](auto ic, auto edge_c) {
                 constexpr int I = decltype(ic)::value;
-                const Src<L> s = source<L, I>(x, y, z, nx, ny, nz, c.symm);
-                const size_t si = (size_t)s.sz * plane + (size_t)s.sy * nx + s.sx;
-                const T dh = (T)Codec<S>::dec(hin[(size_t)s.j * c.np + si]);
-                const T df = (T)Codec<S>::dec(fin[(size_t)s.j * c.np + si]);
-                T(*st)[HN] = sterm[(s.sz + 3) % 3];
-                const int tl = (s.sy - y0 + 1) * HX + (s.sx - x0 + 1);
+                constexpr bool EDGE = decltype(edge_c)::value;
+                constexpr int ex = L::ex(I), ey = L::ey(I), ez = L::ez(I);
                 constexpr T wi = T(L::w(I));
                 constexpr T Bi = (I == 0) ? T(L::w(0)) - T(1) : wi;
-                const T eK = T(s.fx * L::ex(I)) * st[3][tl] + T(s.fy * L::ey(I)) * st[4][tl] +
-                             T(s.fz * L::ez(I)) * st[5][tl];
-                T vu = Bi * st[1][tl] + (T(1) - c.omU) * dh + wi * (st[2][tl] + eK);
-                if constexpr (I != 0) vu += wi * (st[0][tl] - Px);
-                const T vt = wi * (st[6][tl] - thx + st[7][tl]) + (T(1) - c.omT) * df;
+                const Terms<T>& t = sterm[sl[1 - ez]][tile.lt - ex - ey * G::HX];
+                const T eK = T(ex) * t.b.x + T(ey) * t.b.y + T(ez) * t.b.z;
+                T vu = Bi * t.a.y + omU1 * ph_[I] + wi * (t.a.z + eK);
+                if constexpr (I != 0) vu += wi * (t.a.x - Px);
+                T vt = wi * (t.a.w - thx) + omT1 * pf_[I];
+                if constexpr (EDGE) {
+                    const bool cr = crosses<L, I>(f);
+                    vu = cr ? T(0) : vu;
+                    vt = cr ? T(0) : vt;
+                }
                 iu[I] = vu; it[I] = vt;
                 du += vu; dth += vt;
-            });
+            };
+            auto wall_link = [&](int i, T& vu, T& vt) {
+                const Src s = source_rt<L>(i, tile.x, tile.y, z, nx, ny, nz, c.symm);
+                const size_t si = ((size_t)s.sz * ny + s.sy) * nx + s.sx;
+                const T dh = (T)Codec<S>::dec(hin[(size_t)s.j * np + si]);
+                const T df = (T)Codec<S>::dec(fin[(size_t)s.j * np + si]);
+                const Terms<T>& t = sterm[(s.sz + 3) % 3][(s.sy - tile.y0 + 1) * G::HX + (s.sx - tile.x0 + 1)];
+                const T wi = T(L::w(i));
+                const T eK = T(s.fx * L::ex(i)) * t.b.x + T(s.fy * L::ey(i)) * t.b.y +
+                             T(s.fz * L::ez(i)) * t.b.z;
+                // i > 0 here: A_i = 0, B_i = w_i
+                vu = wi * t.a.y + omU1 * dh + wi * (t.a.z + eK) + wi * (t.a.x - Px);
+                vt = wi * (t.a.w - thx) + omT1 * df;
+            };
+            const bool on_face = f.xl || f.xh || f.yl || f.yh || f.zl || f.zh;
+            if (!edge) {
+                Unroll<0, L::Q>::run([&](auto ic) { fast(ic, std::false_type{}); });
+            } else {
+                Unroll<0, L::Q>::run([&](auto ic) { fast(ic, std::true_type{}); });
+                if (on_face) {
+#pragma unroll 1
+                    for (int i = 1; i < L::Q; ++i)
+                        if (crosses_rt<L>(i, f)) {
+                            T vu, vt;
+                            wall_link(i, vu, vt);
+                            du += vu;
+                            dth += vt;
+                        }
+                }
+            }
             Uout[xi] = Ux + du;
             thout[xi] = thx + dth;
-            // (r^o_x - r_x) U_x = -C_x / omega_U
-            const T dr = -Cx * c.etaU;
+            // (r^o_x - r_x) U_x - r_x dU, with (r^o_x - r_x) U_x = -C_x / omega_U
+            const T hb = -Cx * c.etaU - rx * du;
             Unroll<0, L::Q>::run([&](auto ic) {
                 constexpr int I = decltype(ic)::value;
                 constexpr T wi = T(L::w(I));
                 constexpr T Bi = (I == 0) ? T(L::w(0)) - T(1) : wi;
-                constexpr T Ai = (I == 0) ? T(1) : T(0);
-                const T dhv = iu[I] - Ai * du + Bi * (dr - rx * du);
-                hout[(size_t)I * c.np + xi] = Codec<S>::enc(dhv);
-                fout[(size_t)I * c.np + xi] = Codec<S>::enc(it[I] - wi * dth);
+                const T dhv = (I == 0) ? iu[I] - du + Bi * hb : iu[I] + Bi * hb;
+                st_nt(&hout[(size_t)I * np + xi], Codec<S>::enc(dhv));
+                st_nt(&fout[(size_t)I * np + xi], Codec<S>::enc(it[I] - wi * dth));
             });
+            if (edge && on_face) {
+#pragma unroll 1
+                for (int i = 1; i < L::Q; ++i)
+                    if (crosses_rt<L>(i, f)) {
+                        T vu, vt;
+                        wall_link(i, vu, vt);
+                        const T wi = T(L::w(i));
+                        hout[(size_t)i * np + xi] = Codec<S>::enc(vu + wi * hb);
+                        fout[(size_t)i * np + xi] = Codec<S>::enc(vt - wi * dth);
+                    }
+            }
         }
+        if (zz + 1 <= tile.ze + 1) prefetch(zz + 1);
     }
 }
 
@@ -534,8 +841,8 @@ __global__ __launch_bounds__(256) void k_init(const Coef<T> c, S* __restrict__ g
     T wn[6], rn[6];
 #pragma unroll
     for (int d = 0; d < 6; ++d) {
-        wn[d] = T(1) / (zA - zB * pn[d]);
-        rn[d] = r_of(pn[d], zA, zB);
+        wn[d] = frcp(zA - zB * pn[d]);
+        rn[d] = T(0.5) * (T(1) - pn[d]) * wn[d];
     }
     const T u = U[s];
     const T Jx = c.D * ((rn[0] - rn[1]) * c.inv2dx + q0 * (wn[0] - wn[1]) * c.inv2dx) * u;
@@ -592,7 +899,7 @@ __global__ __launch_bounds__(256) void k_stream_only(int nx, int ny, int nz, int
     const int x = (int)(s % nx), y = (int)((s / nx) % ny), z = (int)(s / ((size_t)nx * ny));
     Unroll<0, L::Q>::run([&](auto ic) {
         constexpr int I = decltype(ic)::value;
-        const Src<L> src = source<L, I>(x, y, z, nx, ny, nz, symm);
+        const Src src = source<L, I>(x, y, z, nx, ny, nz, symm);
         const size_t si = ((size_t)src.sz * ny + src.sy) * nx + src.sx;
         out[(size_t)I * np + s] = in[(size_t)src.j * np + si];
     });
@@ -720,12 +1027,21 @@ __global__ __launch_bounds__(256) void k_reduce_final(const double* __restrict__
     }
 }
 
-// Plain 16-byte vector copy: the bandwidth reference.
-__global__ __launch_bounds__(256) void k_copy(const uint4* __restrict__ src, uint4* __restrict__ dst,
+// Plain 16-byte vector copy, four loads in flight per thread and streaming
+// hints: the practical bandwidth reference.
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+__global__ __launch_bounds__(256) void k_copy(const u32x4* __restrict__ src, u32x4* __restrict__ dst,
                                               size_t n16) {
-    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n16;
-         i += (size_t)gridDim.x * blockDim.x)
-        dst[i] = src[i];
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    for (; i + 3 * stride < n16; i += 4 * stride) {
+        u32x4 v[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) v[u] = __builtin_nontemporal_load(&src[i + u * stride]);
+#pragma unroll
+        for (int u = 0; u < 4; ++u) __builtin_nontemporal_store(v[u], &dst[i + u * stride]);
+    }
+    for (; i < n16; i += stride) dst[i] = src[i];
 }
 
 }  // namespace lbpf

@@ -31,6 +31,13 @@ struct TimedLaunch {
     hipEvent_t a, b;
 };
 
+// Tile shapes (TX x TY threads; a wavefront covers 64/TX rows).
+struct Shape {
+    int tx, ty;
+};
+constexpr Shape kShapes[] = {{64, 2}, {64, 4}, {32, 4}, {32, 8}, {32, 16}};
+constexpr int kNumShapes = 5;
+
 }  // namespace
 
 struct lbpf_ctx {
@@ -52,8 +59,9 @@ struct lbpf_ctx {
     double* hist = nullptr;  // HIST_CAP records
     double* fresh = nullptr; // one record for lbpf_read
     int64_t hist_count = 0;
-    int ty = 4;
-    int zslab = 16;
+    int shape = 3;           // tile shape id, see kShapes
+    int zslab = 8;
+    int remap = 1;           // XCD-chunked tile order
     bool timing = false;
     std::vector<TimedLaunch> launches;
     std::vector<hipEvent_t> pool;
@@ -89,8 +97,9 @@ Coef<T> make_coef(const lbpf_ctx* ctx) {
     for (int f = 0; f < 6; ++f)
         if (g.wall[f] == LBPF_WALL_SYMMETRY) c.symm |= 1 << f;
     c.zslab = ctx->zslab;
-    c.nbx = (g.nx + TX - 1) / TX;
-    c.nby = (g.ny + ctx->ty - 1) / ctx->ty;
+    c.remap = ctx->remap;
+    c.nbx = (g.nx + kShapes[ctx->shape].tx - 1) / kShapes[ctx->shape].tx;
+    c.nby = (g.ny + kShapes[ctx->shape].ty - 1) / kShapes[ctx->shape].ty;
     c.nbz = (g.nz + ctx->zslab - 1) / ctx->zslab;
     c.np = (long long)ctx->np;
     c.aniso = p.aniso;
@@ -120,8 +129,8 @@ Coef<T> make_coef(const lbpf_ctx* ctx) {
 }
 
 int total_tiles(const lbpf_ctx* ctx) {
-    const int nbx = (ctx->grid.nx + TX - 1) / TX;
-    const int nby = (ctx->grid.ny + ctx->ty - 1) / ctx->ty;
+    const int nbx = (ctx->grid.nx + kShapes[ctx->shape].tx - 1) / kShapes[ctx->shape].tx;
+    const int nby = (ctx->grid.ny + kShapes[ctx->shape].ty - 1) / kShapes[ctx->shape].ty;
     const int nbz = (ctx->grid.nz + ctx->zslab - 1) / ctx->zslab;
     return nbx * nby * nbz;
 }
@@ -157,19 +166,19 @@ lbpf_status timed(lbpf_ctx* ctx, int kind, F&& launch) {
 }
 
 // ---------------------------------------------------------------- dispatch
-template <class L, class T, class S, int TY>
+template <class L, class T, class S, int TX, int TY>
 lbpf_status launch_step_t(lbpf_ctx* ctx) {
     const Coef<T> c = make_coef<T>(ctx);
     const int nb = total_tiles(ctx);
     const int a = ctx->cur, b = 1 - ctx->cur;
     lbpf_status st = timed(ctx, 0, [&] {
-        hipLaunchKernelGGL((k_phi<L, T, S, TY>), dim3(nb), dim3(TX * TY), 0, ctx->stream, c,
+        hipLaunchKernelGGL((k_phi<L, T, S, TX, TY>), dim3(nb), dim3(TX * TY), 0, ctx->stream, c,
                            (const S*)ctx->pop[0][a], (S*)ctx->pop[0][b], (const T*)ctx->fld[0][a],
                            (const T*)ctx->fld[1][a], (const T*)ctx->fld[2][a], (T*)ctx->fld[0][b]);
     });
     if (st) return st;
     st = timed(ctx, 1, [&] {
-        hipLaunchKernelGGL((k_ut<L, T, S, TY>), dim3(nb), dim3(TX * TY), 0, ctx->stream, c,
+        hipLaunchKernelGGL((k_ut<L, T, S, TX, TY>), dim3(nb), dim3(TX * TY), 0, ctx->stream, c,
                            (const S*)ctx->pop[1][a], (S*)ctx->pop[1][b], (const S*)ctx->pop[2][a],
                            (S*)ctx->pop[2][b], (const T*)ctx->fld[0][a], (const T*)ctx->fld[0][b],
                            (const T*)ctx->fld[1][a], (const T*)ctx->fld[2][a], (T*)ctx->fld[1][b],
@@ -180,14 +189,41 @@ lbpf_status launch_step_t(lbpf_ctx* ctx) {
     return LBPF_OK;
 }
 
+// Static LDS of one block of k_ut, the larger of the two step kernels.
+template <class T, int TX, int TY>
+constexpr size_t lds_bytes() {
+    return 3 * (size_t)(TX + 4) * (TY + 4) * 2 * sizeof(T) + 3 * (size_t)(TX + 2) * (TY + 2) * 8 * sizeof(T);
+}
+
+template <class T>
+bool shape_ok(int shape) {
+    switch (shape) {
+        case 0: return lds_bytes<T, 64, 2>() <= 65536;
+        case 1: return lds_bytes<T, 64, 4>() <= 65536;
+        case 2: return lds_bytes<T, 32, 4>() <= 65536;
+        case 3: return lds_bytes<T, 32, 8>() <= 65536;
+        case 4: return lds_bytes<T, 32, 16>() <= 65536 + 16384;
+    }
+    return false;
+}
+
 template <class L, class T, class S>
 lbpf_status launch_step_s(lbpf_ctx* ctx) {
-    switch (ctx->ty) {
-        case 1: return launch_step_t<L, T, S, 1>(ctx);
-        case 2: return launch_step_t<L, T, S, 2>(ctx);
-        case 4: return launch_step_t<L, T, S, 4>(ctx);
-        default: return fail(ctx, LBPF_EINVAL, "unsupported tile height");
+    if constexpr (sizeof(T) == 8) {
+        switch (ctx->shape) {
+            case 0: return launch_step_t<L, T, S, 64, 2>(ctx);
+            case 2: return launch_step_t<L, T, S, 32, 4>(ctx);
+        }
+    } else {
+        switch (ctx->shape) {
+            case 0: return launch_step_t<L, T, S, 64, 2>(ctx);
+            case 1: return launch_step_t<L, T, S, 64, 4>(ctx);
+            case 2: return launch_step_t<L, T, S, 32, 4>(ctx);
+            case 3: return launch_step_t<L, T, S, 32, 8>(ctx);
+            case 4: return launch_step_t<L, T, S, 32, 16>(ctx);
+        }
     }
+    return fail(ctx, LBPF_EINVAL, "tile shape not available for this storage");
 }
 
 template <class L>
@@ -394,8 +430,8 @@ lbpf_status lbpf_create(const lbpf_grid* grid, const lbpf_params* params, void* 
     ctx->storage = g.storage;
     ctx->sbytes = (size_t)lbpf_storage_bytes(g.storage);
     ctx->tbytes = g.storage == LBPF_F64 ? 8 : 4;
-    ctx->ty = g.storage == LBPF_F64 ? 2 : 4;
-    ctx->zslab = 16;
+    ctx->shape = g.storage == LBPF_F64 ? 2 : 3;
+    ctx->zslab = 8;
     ctx->n = (size_t)g.nx * g.ny * g.nz;
     ctx->np = (ctx->n + 63) / 64 * 64;
     hipError_t e = hipSuccess;
@@ -615,14 +651,108 @@ lbpf_status lbpf_kernel_times(lbpf_ctx* ctx, double ms[3], int64_t launches[3]) 
     return LBPF_OK;
 }
 
+lbpf_status lbpf_set_launch(lbpf_ctx* ctx, int32_t tile_x, int32_t tile_y, int32_t zslab,
+                            int32_t xcd_remap) {
+    if (!ctx) return LBPF_EINVAL;
+    if (zslab < 1) return fail(ctx, LBPF_EINVAL, "zslab < 1");
+    if (xcd_remap != 0 && xcd_remap != 1) return fail(ctx, LBPF_EINVAL, "xcd_remap must be 0 or 1");
+    for (int i = 0; i < kNumShapes; ++i) {
+        if (kShapes[i].tx != tile_x || kShapes[i].ty != tile_y) continue;
+        const bool ok = ctx->storage == LBPF_F64 ? (i == 0 || i == 2) : true;
+        if (!ok) return fail(ctx, LBPF_EINVAL, "tile shape not available for FP64 storage");
+        ctx->shape = i;
+        ctx->zslab = zslab;
+        ctx->remap = xcd_remap;
+        return LBPF_OK;
+    }
+    return fail(ctx, LBPF_EINVAL, "unsupported tile shape");
+}
+
+lbpf_status lbpf_get_launch(lbpf_ctx* ctx, int32_t* tile_x, int32_t* tile_y, int32_t* zslab,
+                            int32_t* xcd_remap) {
+    if (!ctx || !tile_x || !tile_y || !zslab || !xcd_remap) return LBPF_EINVAL;
+    *tile_x = kShapes[ctx->shape].tx;
+    *tile_y = kShapes[ctx->shape].ty;
+    *zslab = ctx->zslab;
+    *xcd_remap = ctx->remap;
+    return LBPF_OK;
+}
+
+lbpf_status lbpf_autotune(lbpf_ctx* ctx, int32_t steps_per_candidate, double* best_ms_per_step) {
+    if (!ctx) return LBPF_EINVAL;
+    if (steps_per_candidate < 1) return fail(ctx, LBPF_EINVAL, "steps_per_candidate < 1");
+    if (!ctx->have_fields) return fail(ctx, LBPF_ESTATE, "lbpf_set_fields has not been called");
+    CHK(hipStreamSynchronize(ctx->stream));
+    // snapshot of the current state (populations and fields of parity cur)
+    const size_t pbytes = ctx->np * ctx->q * ctx->sbytes, fbytes = ctx->n * ctx->tbytes;
+    void* snap = nullptr;
+    CHK(hipMalloc(&snap, 3 * (pbytes + fbytes)));
+    const int cur0 = ctx->cur;
+    for (int f = 0; f < 3; ++f) {
+        CHK(hipMemcpyAsync((char*)snap + f * pbytes, ctx->pop[f][cur0], pbytes, hipMemcpyDeviceToDevice, ctx->stream));
+        CHK(hipMemcpyAsync((char*)snap + 3 * pbytes + f * fbytes, ctx->fld[f][cur0], fbytes,
+                           hipMemcpyDeviceToDevice, ctx->stream));
+    }
+    const bool was_timing = ctx->timing;
+    ctx->timing = false;
+    const int shape0 = ctx->shape, zslab0 = ctx->zslab, remap0 = ctx->remap;
+    int best_shape = shape0, best_z = zslab0, best_r = remap0;
+    double best = 1e300;
+    hipEvent_t ea = nullptr, eb = nullptr;
+    lbpf_status st = LBPF_OK;
+    if (hipEventCreate(&ea) != hipSuccess || hipEventCreate(&eb) != hipSuccess) st = fail(ctx, LBPF_EDEVICE, "hipEventCreate");
+    const int zs_list[] = {2, 4, 8, 16, 32};
+    for (int sh = 0; sh < kNumShapes && !st; ++sh) {
+        if (ctx->storage == LBPF_F64 ? !(sh == 0 || sh == 2) : false) continue;
+        for (int zi = 0; zi < 10 && !st; ++zi) {
+            const int zsl = zs_list[zi % 5];
+            if (zsl > 2 * ctx->grid.nz && zi % 5 > 0) continue;
+            ctx->shape = sh;
+            ctx->zslab = zsl;
+            ctx->remap = zi / 5;
+            for (int w = 0; w < 2 && !st; ++w) st = launch_step(ctx);
+            if (st) break;
+            if (hipEventRecord(ea, ctx->stream) != hipSuccess) { st = fail(ctx, LBPF_EDEVICE, "event"); break; }
+            for (int k = 0; k < steps_per_candidate && !st; ++k) st = launch_step(ctx);
+            if (st) break;
+            float ms = 0.f;
+            if (hipEventRecord(eb, ctx->stream) != hipSuccess || hipEventSynchronize(eb) != hipSuccess ||
+                hipEventElapsedTime(&ms, ea, eb) != hipSuccess) {
+                st = fail(ctx, LBPF_EDEVICE, "event timing");
+                break;
+            }
+            const double per = ms / steps_per_candidate;
+            if (per < best) { best = per; best_shape = sh; best_z = zsl; best_r = ctx->remap; }
+        }
+    }
+    if (ea) (void)hipEventDestroy(ea);
+    if (eb) (void)hipEventDestroy(eb);
+    // restore the state and keep the best launch shape
+    ctx->cur = cur0;
+    for (int f = 0; f < 3; ++f) {
+        (void)hipMemcpyAsync(ctx->pop[f][cur0], (char*)snap + f * pbytes, pbytes, hipMemcpyDeviceToDevice, ctx->stream);
+        (void)hipMemcpyAsync(ctx->fld[f][cur0], (char*)snap + 3 * pbytes + f * fbytes, fbytes,
+                             hipMemcpyDeviceToDevice, ctx->stream);
+    }
+    (void)hipStreamSynchronize(ctx->stream);
+    (void)hipFree(snap);
+    ctx->timing = was_timing;
+    if (st) { ctx->shape = shape0; ctx->zslab = zslab0; ctx->remap = remap0; return st; }
+    ctx->shape = best_shape;
+    ctx->zslab = best_z;
+    ctx->remap = best_r;
+    if (best_ms_per_step) *best_ms_per_step = best;
+    return LBPF_OK;
+}
+
 lbpf_status lbpf_bench_copy(void* dst, const void* src, int64_t nbytes, void* hip_stream) {
     if (!dst || !src || nbytes < 0 || (nbytes % 16) != 0 || ((uintptr_t)dst % 16) || ((uintptr_t)src % 16))
         return LBPF_EINVAL;
     const size_t n16 = (size_t)nbytes / 16;
     if (n16 == 0) return LBPF_OK;
-    const int nb = (int)std::min<size_t>(4096, (n16 + 255) / 256);
-    hipLaunchKernelGGL(k_copy, dim3(nb), dim3(256), 0, (hipStream_t)hip_stream, (const uint4*)src,
-                       (uint4*)dst, n16);
+    const int nb = (int)std::min<size_t>(32768, (n16 + 255) / 256);
+    hipLaunchKernelGGL(k_copy, dim3(nb), dim3(256), 0, (hipStream_t)hip_stream, (const u32x4*)src,
+                       (u32x4*)dst, n16);
     return hipGetLastError() == hipSuccess ? LBPF_OK : LBPF_EDEVICE;
 }
 

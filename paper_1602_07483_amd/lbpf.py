@@ -57,6 +57,7 @@ SYMBOLS = ["lbpf_create", "lbpf_destroy", "lbpf_set_fields", "lbpf_step", "lbpf_
            "lbpf_read", "lbpf_history", "lbpf_read_populations", "lbpf_write_populations",
            "lbpf_read_populations_f64",
            "lbpf_debug_stream_only", "lbpf_set_timing", "lbpf_kernel_times",
+           "lbpf_set_launch", "lbpf_get_launch", "lbpf_autotune",
            "lbpf_storage_bytes", "lbpf_bench_copy", "lbpf_last_error"]
 
 
@@ -86,6 +87,11 @@ def load():
         "lbpf_debug_stream_only": ([vp, ctypes.c_int64], ctypes.c_int),
         "lbpf_set_timing": ([vp, ctypes.c_int32], ctypes.c_int),
         "lbpf_kernel_times": ([vp, dp, P(ctypes.c_int64)], ctypes.c_int),
+        "lbpf_set_launch": ([vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32],
+                            ctypes.c_int),
+        "lbpf_get_launch": ([vp, P(ctypes.c_int32), P(ctypes.c_int32), P(ctypes.c_int32),
+                             P(ctypes.c_int32)], ctypes.c_int),
+        "lbpf_autotune": ([vp, ctypes.c_int32, dp], ctypes.c_int),
         "lbpf_storage_bytes": ([ctypes.c_int32], ctypes.c_int32),
         "lbpf_bench_copy": ([vp, vp, ctypes.c_int64, vp], ctypes.c_int),
         "lbpf_last_error": ([vp], ctypes.c_char_p),
@@ -222,6 +228,21 @@ class Solver:
 
     def set_timing(self, enable=True):
         self._check(self._lib.lbpf_set_timing(self._h, 1 if enable else 0))
+
+    def set_launch(self, tile_x, tile_y, zslab, xcd_remap=1):
+        self._check(self._lib.lbpf_set_launch(self._h, int(tile_x), int(tile_y), int(zslab),
+                                              int(xcd_remap)))
+
+    def get_launch(self):
+        a, b, c, d = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        self._check(self._lib.lbpf_get_launch(self._h, ctypes.byref(a), ctypes.byref(b),
+                                              ctypes.byref(c), ctypes.byref(d)))
+        return a.value, b.value, c.value, d.value
+
+    def autotune(self, steps_per_candidate=10):
+        best = ctypes.c_double()
+        self._check(self._lib.lbpf_autotune(self._h, int(steps_per_candidate), ctypes.byref(best)))
+        return self.get_launch(), best.value
 
     def kernel_times(self):
         ms = (ctypes.c_double * 3)()

@@ -57,7 +57,7 @@ def measured_traffic(kernel, storage):
     return float(m_bytes.group(1))
 
 
-def run_gpu(storage, steps, warmup, n):
+def run_gpu(storage, steps, warmup, n, launch=None):
     import torch
     from paper_1602_07483_amd import lbpf
     from paper_1602_07483_amd.inputs import workload_centred
@@ -67,8 +67,12 @@ def run_gpu(storage, steps, warmup, n):
     stream = torch.cuda.current_stream().cuda_stream
     s = lbpf.solver_for(pb, storage=storage, stream=stream)
     s.set_fields(*pb.initial_fields())
-    # launch shape picked by the library's autotuner (state restored after)
-    launch, _ = s.autotune(6)
+    if launch is None:
+        # launch shape picked by the library's autotuner (state restored after)
+        launch, _ = s.autotune(6)
+    else:
+        s.set_launch(*launch)
+        launch = s.get_launch()
     s.step(warmup)
     s.sync()
     torch.cuda.synchronize()
@@ -144,6 +148,8 @@ def main():
     ap.add_argument("--n", type=int, default=256)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
     ap.add_argument("--no-variants", action="store_true", help="FP32 only")
+    ap.add_argument("--launch", default=None,
+                    help="tile_x,tile_y,zslab,xcd_remap instead of the autotuner")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU only; --gpus %d is not supported "
@@ -151,11 +157,12 @@ def main():
         return 2
     rank = int(os.environ.get("RANK", "0"))
 
-    res = run_gpu("f32", args.steps, args.warmup, args.n)
+    launch = tuple(int(v) for v in args.launch.split(",")) if args.launch else None
+    res = run_gpu("f32", args.steps, args.warmup, args.n, launch)
     variants = {}
     if not args.no_variants:
         for st in ("f16", "bf16"):
-            r = run_gpu(st, args.steps, args.warmup, args.n)
+            r = run_gpu(st, args.steps, args.warmup, args.n, launch)
             variants[st] = {"mlups": r["mlups"], "ms_per_step": r["ms_per_step"], "launch": r["launch"],
                             "algorithmic_GBps": r["algorithmic_GBps"],
                             "speedup_vs_f32": r["mlups"] / res["mlups"],

@@ -77,6 +77,42 @@ __device__ __forceinline__ void st_nt(__hip_bfloat16* p, __hip_bfloat16 v) {
     __builtin_nontemporal_store(b, reinterpret_cast<unsigned short*>(p));
 }
 
+// Raw buffer access.  One resource spans all Q arrays of a field (used when
+// they total less than 4 GiB): every link then reads at the thread's own
+// byte offset plus a per-direction scalar offset, so no vector instruction is
+// spent on addressing; offsets past the end read 0 and drop stores.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void* p, unsigned bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)bytes, 0x00020000);
+}
+template <class S> __device__ __forceinline__ S buf_ld(__amdgpu_buffer_rsrc_t r, unsigned v, unsigned s);
+template <> __device__ __forceinline__ float buf_ld<float>(__amdgpu_buffer_rsrc_t r, unsigned v, unsigned s) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, (int)v, (int)s, 0));
+}
+template <> __device__ __forceinline__ double buf_ld<double>(__amdgpu_buffer_rsrc_t r, unsigned v, unsigned s) {
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, (int)v, (int)s, 0));
+}
+template <> __device__ __forceinline__ __half buf_ld<__half>(__amdgpu_buffer_rsrc_t r, unsigned v, unsigned s) {
+    return __ushort_as_half(__builtin_amdgcn_raw_buffer_load_b16(r, (int)v, (int)s, 0));
+}
+template <> __device__ __forceinline__ __hip_bfloat16 buf_ld<__hip_bfloat16>(__amdgpu_buffer_rsrc_t r, unsigned v,
+                                                                            unsigned s) {
+    return __builtin_bit_cast(__hip_bfloat16, __builtin_amdgcn_raw_buffer_load_b16(r, (int)v, (int)s, 0));
+}
+// streaming (non-temporal) stores
+__device__ __forceinline__ void buf_st(float x, __amdgpu_buffer_rsrc_t r, unsigned v, unsigned s) {
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, x), r, (int)v, (int)s, 2);
+}
+__device__ __forceinline__ void buf_st(double x, __amdgpu_buffer_rsrc_t r, unsigned v, unsigned s) {
+    typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, x), r, (int)v, (int)s, 2);
+}
+__device__ __forceinline__ void buf_st(__half x, __amdgpu_buffer_rsrc_t r, unsigned v, unsigned s) {
+    __builtin_amdgcn_raw_buffer_store_b16(__half_as_ushort(x), r, (int)v, (int)s, 2);
+}
+__device__ __forceinline__ void buf_st(__hip_bfloat16 x, __amdgpu_buffer_rsrc_t r, unsigned v, unsigned s) {
+    __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, x), r, (int)v, (int)s, 2);
+}
+
 // Reciprocal and reciprocal square root: the hardware instructions (about
 // 1 ulp) in FP32, exact operations in the FP64 verification build.
 __device__ __forceinline__ float frcp(float x) { return __builtin_amdgcn_rcpf(x); }
@@ -86,7 +122,6 @@ __device__ __forceinline__ double frsq(double x) { return 1.0 / sqrt(x); }
 
 template <class T> struct alignas(4 * sizeof(T) > 16 ? 16 : 4 * sizeof(T)) V4 { T x, y, z, w; };
 template <class T> struct alignas(2 * sizeof(T)) V2 { T x, y; };
-template <class T> struct Terms { V4<T> a, b; };
 
 // --------------------------------------------------------------------------
 // Kernel constants (precomputed on the host in FP64, converted to T)
@@ -386,19 +421,23 @@ struct March {
 // Only small quantities are rounded besides the one update of phi.
 // LDS terms: a = (A, A(1-omega), A Q dt/tau0, phi), b = (A V, 0).
 // ==========================================================================
-template <class L, class T, class S, int TX, int TY>
-__global__ __launch_bounds__(TX * TY) void k_phi(const Coef<T> c, const S* __restrict__ gin,
+template <class L, class T, class S, int TX, int TY, bool BUF>
+__global__ __launch_bounds__(TX * TY, (sizeof(T) == 4 ? 4 : 1)) void k_phi(const Coef<T> c, const S* __restrict__ gin,
                                                  S* __restrict__ gout, const T* __restrict__ phin,
                                                  const T* __restrict__ Un, const T* __restrict__ thn,
                                                  T* __restrict__ phout) {
     using G = Tile<TX, TY>;
     using M = March<TX, TY>;
     __shared__ T sphi[3][G::PN];
-    __shared__ Terms<T> sterm[3][G::HN];
+    __shared__ V4<T> sta[3][G::HN];       // node terms, first 4-vector
+    __shared__ V4<T> stb[3][G::HN];       // node terms, second 4-vector
 
     G tile(c);
     const int nx = c.nx, ny = c.ny, nz = c.nz;
     const unsigned plane = (unsigned)nx * (unsigned)ny;
+    const unsigned pbytes = (unsigned)((size_t)L::Q * (size_t)c.np * sizeof(S));
+    const __amdgpu_buffer_rsrc_t rin = make_rsrc(gin, BUF ? pbytes : 0u);
+    const __amdgpu_buffer_rsrc_t rout = make_rsrc(gout, BUF ? pbytes : 0u);
 
     // registers filled one iteration ahead
     T pa[M::NA];                       // phi^n of the staged plane
@@ -439,11 +478,20 @@ __global__ __launch_bounds__(TX * TY) void k_phi(const Coef<T> c, const S* __res
             Unroll<0, L::Q>::run([&](auto ic) {
                 constexpr int I = decltype(ic)::value;
                 constexpr int ex = L::ex(I), ey = L::ey(I), ez = L::ez(I);
-                const S* gI = gin + (size_t)I * np;
-                unsigned so = xi - (unsigned)(ex + ey * nx + ez * (int)plane);
-                so = crosses<L, I>(f) ? xi : so;     // wall links: any in-bounds address
-                pnl[I] = (T)Codec<S>::dec(gI[xi]);
-                pj[I] = (T)Codec<S>::dec(gI[so]);
+                const int off = ex + ey * nx + ez * (int)plane;
+                const bool cr = crosses<L, I>(f);    // wall links: read any in-bounds value
+                if constexpr (BUF) {
+                    const unsigned vx = xi * (unsigned)sizeof(S);
+                    const unsigned sI = (unsigned)(I * np) * (unsigned)sizeof(S);
+                    const unsigned vj = cr ? vx + (unsigned)off * (unsigned)sizeof(S) : vx;
+                    pnl[I] = (T)Codec<S>::dec(buf_ld<S>(rin, vx, sI));
+                    pj[I] = (T)Codec<S>::dec(buf_ld<S>(rin, vj, sI - (unsigned)off * (unsigned)sizeof(S)));
+                } else {
+                    const S* gI = gin + (size_t)I * np;
+                    const unsigned so = cr ? xi : xi - (unsigned)off;
+                    pnl[I] = (T)Codec<S>::dec(gI[xi]);
+                    pj[I] = (T)Codec<S>::dec(gI[so]);
+                }
             });
         }
     };
@@ -466,7 +514,8 @@ __global__ __launch_bounds__(TX * TY) void k_phi(const Coef<T> c, const S* __res
             const T* fm = sphi[(pz + 2) % 3];
             const T* f0 = sphi[(pz + 3) % 3];
             const T* fp = sphi[(pz + 4) % 3];
-            Terms<T>* st = sterm[(pz + 3) % 3];
+            V4<T>* sa = sta[(pz + 3) % 3];
+            V4<T>* sb = stb[(pz + 3) % 3];
 #pragma unroll
             for (int k = 0; k < M::NB; ++k) {
                 const int t = (int)threadIdx.x + k * G::NT;
@@ -487,8 +536,8 @@ __global__ __launch_bounds__(TX * TY) void k_phi(const Coef<T> c, const S* __res
                 const bool bnd = on_noflux_face(rx, ry, pz, nx, ny, nz, c.symm);
                 const T A = bnd ? T(1) : frcp(a2);
                 const T av = A * om * c.cphi_e2;
-                st[t].a = V4<T>{A, A * (T(1) - om), A * Qp * c.dt_tau0, ph};
-                st[t].b = V4<T>{av * Nx, av * Ny, av * Nz, T(0)};
+                sa[t] = V4<T>{A, A * (T(1) - om), A * Qp * c.dt_tau0, ph};
+                sb[t] = V4<T>{av * Nx, av * Ny, av * Nz, T(0)};
             }
         }
         __syncthreads();
@@ -497,7 +546,7 @@ __global__ __launch_bounds__(TX * TY) void k_phi(const Coef<T> c, const S* __res
             const int z = zz - 2;
             const unsigned xi = (unsigned)z * plane + (unsigned)tile.y * nx + tile.x;
             const int sl[3] = {(z + 2) % 3, (z + 3) % 3, (z + 4) % 3};   // planes z-1, z, z+1
-            const T phx = sterm[sl[1]][tile.lt].a.w;
+            const T phx = sta[sl[1]][tile.lt].w;
             Faces f = tile.f;
             f.zl = z == 0;
             f.zh = z == nz - 1;
@@ -512,9 +561,10 @@ __global__ __launch_bounds__(TX * TY) void k_phi(const Coef<T> c, const S* __res
                 constexpr bool EDGE = decltype(edge_c)::value;
                 constexpr int ex = L::ex(I), ey = L::ey(I), ez = L::ez(I);
                 constexpr T wi = T(L::w(I));
-                const Terms<T>& t = sterm[sl[1 - ez]][tile.lt - ex - ey * G::HX];
-                const T eAV = T(ex) * t.b.x + T(ey) * t.b.y + T(ez) * t.b.z;
-                T v = wi * (t.a.x * (t.a.w - phx) + t.a.z - eAV) + t.a.y * pj[I] - (t.a.x - T(1)) * pnl[I];
+                const int tl = tile.lt - ex - ey * G::HX;
+                const V4<T> ta = sta[sl[1 - ez]][tl], tb = stb[sl[1 - ez]][tl];
+                const T eAV = T(ex) * tb.x + T(ey) * tb.y + T(ez) * tb.z;
+                T v = wi * (ta.x * (ta.w - phx) + ta.z - eAV) + ta.y * pj[I] - (ta.x - T(1)) * pnl[I];
                 if constexpr (EDGE) v = crosses<L, I>(f) ? T(0) : v;
                 inc[I] = v;
                 dsum += v;
@@ -525,11 +575,12 @@ __global__ __launch_bounds__(TX * TY) void k_phi(const Coef<T> c, const S* __res
                 const size_t si = ((size_t)s.sz * ny + s.sy) * nx + s.sx;
                 const T dj = (T)Codec<S>::dec(gin[(size_t)s.j * np + si]);
                 const T dnl = (T)Codec<S>::dec(gin[(size_t)i * np + xi]);
-                const Terms<T>& t = sterm[(s.sz + 3) % 3][(s.sy - tile.y0 + 1) * G::HX + (s.sx - tile.x0 + 1)];
-                const T eAV = T(s.fx * L::ex(i)) * t.b.x + T(s.fy * L::ey(i)) * t.b.y +
-                              T(s.fz * L::ez(i)) * t.b.z;
-                return T(L::w(i)) * (t.a.x * (t.a.w - phx) + t.a.z - eAV) + t.a.y * dj -
-                       (t.a.x - T(1)) * dnl;
+                const int tsl = (s.sz + 3) % 3, tl = (s.sy - tile.y0 + 1) * G::HX + (s.sx - tile.x0 + 1);
+                const V4<T> ta = sta[tsl][tl], tb = stb[tsl][tl];
+                const T eAV = T(s.fx * L::ex(i)) * tb.x + T(s.fy * L::ey(i)) * tb.y +
+                              T(s.fz * L::ez(i)) * tb.z;
+                return T(L::w(i)) * (ta.x * (ta.w - phx) + ta.z - eAV) + ta.y * dj -
+                       (ta.x - T(1)) * dnl;
             };
             const bool on_face = f.xl || f.xh || f.yl || f.yh || f.zl || f.zh;
             if (!edge) {
@@ -546,7 +597,11 @@ __global__ __launch_bounds__(TX * TY) void k_phi(const Coef<T> c, const S* __res
             Unroll<0, L::Q>::run([&](auto ic) {
                 constexpr int I = decltype(ic)::value;
                 constexpr T wi = T(L::w(I));
-                st_nt(&gout[(size_t)I * np + xi], Codec<S>::enc(inc[I] - wi * dsum));
+                const S v = Codec<S>::enc(inc[I] - wi * dsum);
+                if constexpr (BUF)
+                    buf_st(v, rout, xi * (unsigned)sizeof(S), (unsigned)(I * np) * (unsigned)sizeof(S));
+                else
+                    st_nt(&gout[(size_t)I * np + xi], v);
             });
             if (edge && on_face) {
                 // overwrite the wall-crossing links (same thread, same address)
@@ -578,8 +633,8 @@ __global__ __launch_bounds__(TX * TY) void k_phi(const Coef<T> c, const S* __res
 //   dh_i = incU_i - A_i dU + B_i [(r^o_x - r_x) U_x - r_x dU],  df_i = incT_i - w_i dT.
 // LDS terms: a = (P, C, S, theta + dphi/2), b = (K, r).
 // ==========================================================================
-template <class L, class T, class S, int TX, int TY>
-__global__ __launch_bounds__(TX * TY) void k_ut(const Coef<T> c, const S* __restrict__ hin,
+template <class L, class T, class S, int TX, int TY, bool BUF>
+__global__ __launch_bounds__(TX * TY, (sizeof(T) == 4 ? 3 : 1)) void k_ut(const Coef<T> c, const S* __restrict__ hin,
                                                 S* __restrict__ hout, const S* __restrict__ fin,
                                                 S* __restrict__ fout, const T* __restrict__ phio,
                                                 const T* __restrict__ phnew, const T* __restrict__ Un,
@@ -588,7 +643,8 @@ __global__ __launch_bounds__(TX * TY) void k_ut(const Coef<T> c, const S* __rest
     using G = Tile<TX, TY>;
     using M = March<TX, TY>;
     __shared__ V2<T> sphi[3][G::PN];      // (phi^{n+1}, 1/zeta)
-    __shared__ Terms<T> sterm[3][G::HN];
+    __shared__ V4<T> sta[3][G::HN];       // node terms, first 4-vector
+    __shared__ V4<T> stb[3][G::HN];       // node terms, second 4-vector
 
     G tile(c);
     const int nx = c.nx, ny = c.ny, nz = c.nz;
@@ -596,6 +652,11 @@ __global__ __launch_bounds__(TX * TY) void k_ut(const Coef<T> c, const S* __rest
     const T k = c.k;
     const T zA = T(0.5) * (T(1) + k), zB = T(0.5) * (T(1) - k);
     const T omU1 = T(1) - c.omU, omT1 = T(1) - c.omT;
+    const unsigned pbytes = (unsigned)((size_t)L::Q * (size_t)c.np * sizeof(S));
+    const __amdgpu_buffer_rsrc_t rhin = make_rsrc(hin, BUF ? pbytes : 0u);
+    const __amdgpu_buffer_rsrc_t rfin = make_rsrc(fin, BUF ? pbytes : 0u);
+    const __amdgpu_buffer_rsrc_t rhout = make_rsrc(hout, BUF ? pbytes : 0u);
+    const __amdgpu_buffer_rsrc_t rfout = make_rsrc(fout, BUF ? pbytes : 0u);
 
     T pa[M::NA];                          // phi^{n+1} of the staged plane
     T po_[M::NB], pu[M::NB], pt[M::NB];   // phi^n, U^n, theta^n at the term nodes
@@ -639,10 +700,19 @@ __global__ __launch_bounds__(TX * TY) void k_ut(const Coef<T> c, const S* __rest
             Unroll<0, L::Q>::run([&](auto ic) {
                 constexpr int I = decltype(ic)::value;
                 constexpr int ex = L::ex(I), ey = L::ey(I), ez = L::ez(I);
-                unsigned so = xi - (unsigned)(ex + ey * nx + ez * (int)plane);
-                so = crosses<L, I>(f) ? xi : so;     // wall links: any in-bounds address
-                ph_[I] = (T)Codec<S>::dec(hin[(size_t)I * np + so]);
-                pf_[I] = (T)Codec<S>::dec(fin[(size_t)I * np + so]);
+                const int off = ex + ey * nx + ez * (int)plane;
+                const bool cr = crosses<L, I>(f);    // wall links: read any in-bounds value
+                if constexpr (BUF) {
+                    const unsigned vx = xi * (unsigned)sizeof(S);
+                    const unsigned vj = cr ? vx + (unsigned)off * (unsigned)sizeof(S) : vx;
+                    const unsigned sj = (unsigned)(I * np) * (unsigned)sizeof(S) - (unsigned)off * (unsigned)sizeof(S);
+                    ph_[I] = (T)Codec<S>::dec(buf_ld<S>(rhin, vj, sj));
+                    pf_[I] = (T)Codec<S>::dec(buf_ld<S>(rfin, vj, sj));
+                } else {
+                    const unsigned so = cr ? xi : xi - (unsigned)off;
+                    ph_[I] = (T)Codec<S>::dec(hin[(size_t)I * np + so]);
+                    pf_[I] = (T)Codec<S>::dec(fin[(size_t)I * np + so]);
+                }
             });
         }
     };
@@ -663,7 +733,8 @@ __global__ __launch_bounds__(TX * TY) void k_ut(const Coef<T> c, const S* __rest
             const V2<T>* fm = sphi[(pz + 2) % 3];
             const V2<T>* f0 = sphi[(pz + 3) % 3];
             const V2<T>* fp = sphi[(pz + 4) % 3];
-            Terms<T>* st = sterm[(pz + 3) % 3];
+            V4<T>* sa = sta[(pz + 3) % 3];
+            V4<T>* sb = stb[(pz + 3) % 3];
 #pragma unroll
             for (int kk = 0; kk < M::NB; ++kk) {
                 const int t = (int)threadIdx.x + kk * G::NT;
@@ -715,8 +786,8 @@ __global__ __launch_bounds__(TX * TY) void k_ut(const Coef<T> c, const S* __rest
                 const T Sflux = Du * div + jx * Fx + jy * Fy + jz * Fz;
                 const T src = Sflux + cu * T(0.5) * dtphi * w0;
                 const T ro = r_of(po, zA, zB);
-                st[t].a = V4<T>{ro * u, c.omU * (r0 - ro) * u, src * c.dt, th + T(0.5) * dphi};
-                st[t].b = V4<T>{c.jcoef * Jx, c.jcoef * Jy, c.jcoef * Jz, r0};
+                sa[t] = V4<T>{ro * u, c.omU * (r0 - ro) * u, src * c.dt, th + T(0.5) * dphi};
+                sb[t] = V4<T>{c.jcoef * Jx, c.jcoef * Jy, c.jcoef * Jz, r0};
             }
         }
         __syncthreads();
@@ -724,8 +795,7 @@ __global__ __launch_bounds__(TX * TY) void k_ut(const Coef<T> c, const S* __rest
             const int z = zz - 2;
             const unsigned xi = (unsigned)z * plane + (unsigned)tile.y * nx + tile.x;
             const int sl[3] = {(z + 2) % 3, (z + 3) % 3, (z + 4) % 3};
-            const Terms<T>& own = sterm[sl[1]][tile.lt];
-            const T Px = own.a.x, Cx = own.a.y, rx = own.b.w;
+            const T Px = sta[sl[1]][tile.lt].x, Cx = sta[sl[1]][tile.lt].y, rx = stb[sl[1]][tile.lt].w;
             const T Ux = pUx, thx = pthx;
             Faces f = tile.f;
             f.zl = z == 0;
@@ -740,11 +810,12 @@ __global__ __launch_bounds__(TX * TY) void k_ut(const Coef<T> c, const S* __rest
                 constexpr int ex = L::ex(I), ey = L::ey(I), ez = L::ez(I);
                 constexpr T wi = T(L::w(I));
                 constexpr T Bi = (I == 0) ? T(L::w(0)) - T(1) : wi;
-                const Terms<T>& t = sterm[sl[1 - ez]][tile.lt - ex - ey * G::HX];
-                const T eK = T(ex) * t.b.x + T(ey) * t.b.y + T(ez) * t.b.z;
-                T vu = Bi * t.a.y + omU1 * ph_[I] + wi * (t.a.z + eK);
-                if constexpr (I != 0) vu += wi * (t.a.x - Px);
-                T vt = wi * (t.a.w - thx) + omT1 * pf_[I];
+                const int tl = tile.lt - ex - ey * G::HX;
+                const V4<T> ta = sta[sl[1 - ez]][tl], tb = stb[sl[1 - ez]][tl];
+                const T eK = T(ex) * tb.x + T(ey) * tb.y + T(ez) * tb.z;
+                T vu = Bi * ta.y + omU1 * ph_[I] + wi * (ta.z + eK);
+                if constexpr (I != 0) vu += wi * (ta.x - Px);
+                T vt = wi * (ta.w - thx) + omT1 * pf_[I];
                 if constexpr (EDGE) {
                     const bool cr = crosses<L, I>(f);
                     vu = cr ? T(0) : vu;
@@ -758,13 +829,14 @@ __global__ __launch_bounds__(TX * TY) void k_ut(const Coef<T> c, const S* __rest
                 const size_t si = ((size_t)s.sz * ny + s.sy) * nx + s.sx;
                 const T dh = (T)Codec<S>::dec(hin[(size_t)s.j * np + si]);
                 const T df = (T)Codec<S>::dec(fin[(size_t)s.j * np + si]);
-                const Terms<T>& t = sterm[(s.sz + 3) % 3][(s.sy - tile.y0 + 1) * G::HX + (s.sx - tile.x0 + 1)];
+                const int tsl = (s.sz + 3) % 3, tl = (s.sy - tile.y0 + 1) * G::HX + (s.sx - tile.x0 + 1);
+                const V4<T> ta = sta[tsl][tl], tb = stb[tsl][tl];
                 const T wi = T(L::w(i));
-                const T eK = T(s.fx * L::ex(i)) * t.b.x + T(s.fy * L::ey(i)) * t.b.y +
-                             T(s.fz * L::ez(i)) * t.b.z;
+                const T eK = T(s.fx * L::ex(i)) * tb.x + T(s.fy * L::ey(i)) * tb.y +
+                             T(s.fz * L::ez(i)) * tb.z;
                 // i > 0 here: A_i = 0, B_i = w_i
-                vu = wi * t.a.y + omU1 * dh + wi * (t.a.z + eK) + wi * (t.a.x - Px);
-                vt = wi * (t.a.w - thx) + omT1 * df;
+                vu = wi * ta.y + omU1 * dh + wi * (ta.z + eK) + wi * (ta.x - Px);
+                vt = wi * (ta.w - thx) + omT1 * df;
             };
             const bool on_face = f.xl || f.xh || f.yl || f.yh || f.zl || f.zh;
             if (!edge) {
@@ -791,8 +863,15 @@ __global__ __launch_bounds__(TX * TY) void k_ut(const Coef<T> c, const S* __rest
                 constexpr T wi = T(L::w(I));
                 constexpr T Bi = (I == 0) ? T(L::w(0)) - T(1) : wi;
                 const T dhv = (I == 0) ? iu[I] - du + Bi * hb : iu[I] + Bi * hb;
-                st_nt(&hout[(size_t)I * np + xi], Codec<S>::enc(dhv));
-                st_nt(&fout[(size_t)I * np + xi], Codec<S>::enc(it[I] - wi * dth));
+                const S hv = Codec<S>::enc(dhv), fv = Codec<S>::enc(it[I] - wi * dth);
+                if constexpr (BUF) {
+                    const unsigned vx = xi * (unsigned)sizeof(S), sI = (unsigned)(I * np) * (unsigned)sizeof(S);
+                    buf_st(hv, rhout, vx, sI);
+                    buf_st(fv, rfout, vx, sI);
+                } else {
+                    st_nt(&hout[(size_t)I * np + xi], hv);
+                    st_nt(&fout[(size_t)I * np + xi], fv);
+                }
             });
             if (edge && on_face) {
 #pragma unroll 1

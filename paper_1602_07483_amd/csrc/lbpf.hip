@@ -166,19 +166,19 @@ lbpf_status timed(lbpf_ctx* ctx, int kind, F&& launch) {
 }
 
 // ---------------------------------------------------------------- dispatch
-template <class L, class T, class S, int TX, int TY>
-lbpf_status launch_step_t(lbpf_ctx* ctx) {
+template <class L, class T, class S, int TX, int TY, bool BUF>
+lbpf_status launch_step_b(lbpf_ctx* ctx) {
     const Coef<T> c = make_coef<T>(ctx);
     const int nb = total_tiles(ctx);
     const int a = ctx->cur, b = 1 - ctx->cur;
     lbpf_status st = timed(ctx, 0, [&] {
-        hipLaunchKernelGGL((k_phi<L, T, S, TX, TY>), dim3(nb), dim3(TX * TY), 0, ctx->stream, c,
+        hipLaunchKernelGGL((k_phi<L, T, S, TX, TY, BUF>), dim3(nb), dim3(TX * TY), 0, ctx->stream, c,
                            (const S*)ctx->pop[0][a], (S*)ctx->pop[0][b], (const T*)ctx->fld[0][a],
                            (const T*)ctx->fld[1][a], (const T*)ctx->fld[2][a], (T*)ctx->fld[0][b]);
     });
     if (st) return st;
     st = timed(ctx, 1, [&] {
-        hipLaunchKernelGGL((k_ut<L, T, S, TX, TY>), dim3(nb), dim3(TX * TY), 0, ctx->stream, c,
+        hipLaunchKernelGGL((k_ut<L, T, S, TX, TY, BUF>), dim3(nb), dim3(TX * TY), 0, ctx->stream, c,
                            (const S*)ctx->pop[1][a], (S*)ctx->pop[1][b], (const S*)ctx->pop[2][a],
                            (S*)ctx->pop[2][b], (const T*)ctx->fld[0][a], (const T*)ctx->fld[0][b],
                            (const T*)ctx->fld[1][a], (const T*)ctx->fld[2][a], (T*)ctx->fld[1][b],
@@ -187,6 +187,15 @@ lbpf_status launch_step_t(lbpf_ctx* ctx) {
     if (st) return st;
     ctx->cur = b;
     return LBPF_OK;
+}
+
+// One buffer resource per field when its Q population arrays total < 4 GiB.
+template <class L, class T, class S, int TX, int TY>
+lbpf_status launch_step_t(lbpf_ctx* ctx) {
+    const size_t pbytes = (size_t)L::Q * ctx->np * sizeof(S);
+    if (pbytes < ((size_t)1 << 32) - 256) return launch_step_b<L, T, S, TX, TY, true>(ctx);
+    if constexpr (sizeof(T) == 8) return fail(ctx, LBPF_EINVAL, "FP64 verification build limited to < 4 GiB per field");
+    else return launch_step_b<L, T, S, TX, TY, false>(ctx);
 }
 
 // Static LDS of one block of k_ut, the larger of the two step kernels.

@@ -24,8 +24,9 @@
  *  - Host field arrays are double, shape [nz][ny][nx] with x fastest
  *    ("canonical layout"), owned by the caller; the library copies them.
  *  - The context owns all device memory.  It is created on the current HIP
- *    device and runs on the borrowed HIP stream given at creation (NULL = the
- *    null stream).  A context is not thread-safe; one context per stream.
+ *    device and runs on the borrowed HIP stream given at creation; with NULL
+ *    the context creates and owns a non-blocking stream of default priority.
+ *    A context is not thread-safe; one context per stream.
  *  - Work is asynchronous on that stream except where a call says it
  *    synchronises.
  *  - Units: the model parameters are in the paper's (physical) units, the
@@ -42,6 +43,7 @@ extern "C" {
 #endif
 
 typedef struct lbpf_ctx lbpf_ctx;
+typedef struct lbpf_batch lbpf_batch;
 
 typedef enum {
     LBPF_OK = 0,
@@ -136,6 +138,15 @@ lbpf_status lbpf_set_fields(lbpf_ctx* ctx, const double* phi, const double* U,
  * yet), EINVAL (nsteps < 0), EDEVICE. */
 lbpf_status lbpf_step(lbpf_ctx* ctx, int64_t nsteps);
 
+/* Replay the step loop from a captured HIP graph of steps_per_graph time
+ * steps (0 = plain launches; otherwise even, so that the two lattices are in
+ * the same roles after each replay).  lbpf_step uses the graph for every
+ * whole chunk that ends before the next reduction point and while kernel
+ * timing is off; the graph is captured on first use and again after the
+ * launch shape or the lattice parity changed.  Results are identical to
+ * plain launches.  Errors: EINVAL (odd or negative). */
+lbpf_status lbpf_set_graph(lbpf_ctx* ctx, int32_t steps_per_graph);
+
 /* Wait for the stream, then check the most recent history record, if any:
  * returns EUNSTABLE when it holds a non-finite value or |phi| > 1 + 1e-3. */
 lbpf_status lbpf_sync(lbpf_ctx* ctx);
@@ -215,6 +226,32 @@ lbpf_status lbpf_bench_copy(void* dst, const void* src, int64_t nbytes, void* hi
 /* Description of the last error on ctx (or of the last failed creation when
  * ctx is NULL); valid until the next call on the same context. */
 const char* lbpf_last_error(const lbpf_ctx* ctx);
+
+/* ---- Ensembles of independent domains ------------------------------------
+ * A batch holds n domains (own grid, lattice D3Q15 or D3Q19, parameters;
+ * one storage type for all) on one stream.  Each domain is an lbpf_ctx
+ * reached with lbpf_batch_domain, through which its fields are set and read
+ * with the calls above (lbpf_step on it is refused: ESTATE).  lbpf_batch_step
+ * advances every domain with one launch per lattice type and kernel: a work
+ * table maps each block to a (domain, tile) pair, ordered so that each XCD
+ * receives a contiguous run of tiles; with lbpf_batch_set_graph the loop is
+ * replayed from a captured graph.  A domain follows the same arithmetic as
+ * when it is stepped alone; the batch kernels are compiled separately and
+ * may contract floating-point operations differently, so FP32 results agree
+ * with the single-domain ones to a few units in the last place, not bit for
+ * bit.  Launch shape and step chunking do not change the batch's results. */
+lbpf_status lbpf_batch_create(int32_t n, const lbpf_grid* grids, const lbpf_params* params,
+                              void* hip_stream, lbpf_batch** out);
+/* Domain i (borrowed pointer, valid until lbpf_batch_destroy); NULL if out of range. */
+lbpf_ctx* lbpf_batch_domain(lbpf_batch* b, int32_t i);
+/* As lbpf_set_graph, for the whole batch. */
+lbpf_status lbpf_batch_set_graph(lbpf_batch* b, int32_t steps_per_graph);
+/* Advance every domain nsteps; all must have fields and equal step parity.
+ * Asynchronous.  Errors: ESTATE, EINVAL, EDEVICE. */
+lbpf_status lbpf_batch_step(lbpf_batch* b, int64_t nsteps);
+lbpf_status lbpf_batch_sync(lbpf_batch* b);
+lbpf_status lbpf_batch_destroy(lbpf_batch* b);
+const char* lbpf_batch_last_error(const lbpf_batch* b);
 
 #ifdef __cplusplus
 }

@@ -343,9 +343,9 @@ struct Tile {
     bool active, xy_inner;
     Faces f;
     template <class T>
-    __device__ Tile(const Coef<T>& c) {
+    __device__ Tile(const Coef<T>& c, int block) {
         const int total = c.nbx * c.nby * c.nbz;
-        const int b = xcd_tile(blockIdx.x, total, c.remap);
+        const int b = xcd_tile(block, total, c.remap);
         const int bx = b % c.nbx, by = (b / c.nbx) % c.nby, bz = b / (c.nbx * c.nby);
         x0 = bx * TX;
         y0 = by * TY;
@@ -422,17 +422,17 @@ struct March {
 // LDS terms: a = (A, A(1-omega), A Q dt/tau0, phi), b = (A V, 0).
 // ==========================================================================
 template <class L, class T, class S, int TX, int TY, bool BUF>
-__global__ __launch_bounds__(TX * TY, (sizeof(T) == 4 ? 4 : 1)) void k_phi(const Coef<T> c, const S* __restrict__ gin,
-                                                 S* __restrict__ gout, const T* __restrict__ phin,
-                                                 const T* __restrict__ Un, const T* __restrict__ thn,
-                                                 T* __restrict__ phout) {
+__device__ __forceinline__ void phi_body(const Coef<T>& c, int block, const S* __restrict__ gin,
+                                         S* __restrict__ gout, const T* __restrict__ phin,
+                                         const T* __restrict__ Un, const T* __restrict__ thn,
+                                         T* __restrict__ phout) {
     using G = Tile<TX, TY>;
     using M = March<TX, TY>;
     __shared__ T sphi[3][G::PN];
     __shared__ V4<T> sta[3][G::HN];       // node terms, first 4-vector
     __shared__ V4<T> stb[3][G::HN];       // node terms, second 4-vector
 
-    G tile(c);
+    G tile(c, block);
     const int nx = c.nx, ny = c.ny, nz = c.nz;
     const unsigned plane = (unsigned)nx * (unsigned)ny;
     const unsigned pbytes = (unsigned)((size_t)L::Q * (size_t)c.np * sizeof(S));
@@ -634,19 +634,19 @@ __global__ __launch_bounds__(TX * TY, (sizeof(T) == 4 ? 4 : 1)) void k_phi(const
 // LDS terms: a = (P, C, S, theta + dphi/2), b = (K, r).
 // ==========================================================================
 template <class L, class T, class S, int TX, int TY, bool BUF>
-__global__ __launch_bounds__(TX * TY, (sizeof(T) == 4 ? 3 : 1)) void k_ut(const Coef<T> c, const S* __restrict__ hin,
-                                                S* __restrict__ hout, const S* __restrict__ fin,
-                                                S* __restrict__ fout, const T* __restrict__ phio,
-                                                const T* __restrict__ phnew, const T* __restrict__ Un,
-                                                const T* __restrict__ thn, T* __restrict__ Uout,
-                                                T* __restrict__ thout) {
+__device__ __forceinline__ void ut_body(const Coef<T>& c, int block, const S* __restrict__ hin,
+                                        S* __restrict__ hout, const S* __restrict__ fin,
+                                        S* __restrict__ fout, const T* __restrict__ phio,
+                                        const T* __restrict__ phnew, const T* __restrict__ Un,
+                                        const T* __restrict__ thn, T* __restrict__ Uout,
+                                        T* __restrict__ thout) {
     using G = Tile<TX, TY>;
     using M = March<TX, TY>;
     __shared__ V2<T> sphi[3][G::PN];      // (phi^{n+1}, 1/zeta)
     __shared__ V4<T> sta[3][G::HN];       // node terms, first 4-vector
     __shared__ V4<T> stb[3][G::HN];       // node terms, second 4-vector
 
-    G tile(c);
+    G tile(c, block);
     const int nx = c.nx, ny = c.ny, nz = c.nz;
     const unsigned plane = (unsigned)nx * (unsigned)ny;
     const T k = c.k;
@@ -887,6 +887,57 @@ __global__ __launch_bounds__(TX * TY, (sizeof(T) == 4 ? 3 : 1)) void k_ut(const 
         }
         if (zz + 1 <= tile.ze + 1) prefetch(zz + 1);
     }
+}
+
+// --------------------------------------------------------------------------
+// Launch forms.  Single domain: the constants travel as kernel arguments and
+// block b is tile b.  Batch: every block reads its (domain, tile) from a work
+// table and the domain's constants and buffers from a descriptor array; the
+// populations and fields of parity par are read and those of 1-par written.
+// --------------------------------------------------------------------------
+template <class L, class T, class S, int TX, int TY, bool BUF>
+__global__ __launch_bounds__(TX * TY, (sizeof(T) == 4 ? 4 : 1)) void k_phi(
+    const Coef<T> c, const S* __restrict__ gin, S* __restrict__ gout, const T* __restrict__ phin,
+    const T* __restrict__ Un, const T* __restrict__ thn, T* __restrict__ phout) {
+    phi_body<L, T, S, TX, TY, BUF>(c, blockIdx.x, gin, gout, phin, Un, thn, phout);
+}
+
+template <class L, class T, class S, int TX, int TY, bool BUF>
+__global__ __launch_bounds__(TX * TY, (sizeof(T) == 4 ? 3 : 1)) void k_ut(
+    const Coef<T> c, const S* __restrict__ hin, S* __restrict__ hout, const S* __restrict__ fin,
+    S* __restrict__ fout, const T* __restrict__ phio, const T* __restrict__ phnew,
+    const T* __restrict__ Un, const T* __restrict__ thn, T* __restrict__ Uout, T* __restrict__ thout) {
+    ut_body<L, T, S, TX, TY, BUF>(c, blockIdx.x, hin, hout, fin, fout, phio, phnew, Un, thn, Uout, thout);
+}
+
+template <class T>
+struct DomainDesc {
+    Coef<T> c;
+    void* pop[3][2];   // g, h, f populations per parity
+    T* fld[3][2];      // phi, U, theta per parity
+};
+
+template <class L, class T, class S, int TX, int TY>
+__global__ __launch_bounds__(TX * TY, (sizeof(T) == 4 ? 4 : 1)) void k_phi_batch(
+    const DomainDesc<T>* __restrict__ dd, const int2* __restrict__ work, int par) {
+    const int2 wk = work[blockIdx.x];
+    if (wk.x < 0) return;   // padding entry: the whole block leaves
+    const DomainDesc<T>& d = dd[wk.x];
+    const int a = par, b = 1 - par;
+    phi_body<L, T, S, TX, TY, true>(d.c, wk.y, (const S*)d.pop[0][a], (S*)d.pop[0][b], d.fld[0][a],
+                                    d.fld[1][a], d.fld[2][a], d.fld[0][b]);
+}
+
+template <class L, class T, class S, int TX, int TY>
+__global__ __launch_bounds__(TX * TY, (sizeof(T) == 4 ? 3 : 1)) void k_ut_batch(
+    const DomainDesc<T>* __restrict__ dd, const int2* __restrict__ work, int par) {
+    const int2 wk = work[blockIdx.x];
+    if (wk.x < 0) return;   // padding entry: the whole block leaves
+    const DomainDesc<T>& d = dd[wk.x];
+    const int a = par, b = 1 - par;
+    ut_body<L, T, S, TX, TY, true>(d.c, wk.y, (const S*)d.pop[1][a], (S*)d.pop[1][b],
+                                   (const S*)d.pop[2][a], (S*)d.pop[2][b], d.fld[0][a], d.fld[0][b],
+                                   d.fld[1][a], d.fld[2][a], d.fld[1][b], d.fld[2][b]);
 }
 
 // ==========================================================================

@@ -44,6 +44,11 @@ struct lbpf_ctx {
     lbpf_grid grid;
     lbpf_params prm;
     hipStream_t stream = nullptr;
+    bool own_stream = false;
+    bool in_batch = false;   // member of a batch: stepped through lbpf_batch_step only
+    int graph_steps = 0;     // >0: replay the step loop from a captured HIP graph
+    hipGraphExec_t gexec = nullptr;
+    int g_shape = -1, g_zslab = -1, g_remap = -1, g_cur = -1;
     int q = 19;
     int storage = LBPF_F32;
     size_t sbytes = 4;       // bytes per stored population
@@ -67,6 +72,27 @@ struct lbpf_ctx {
     std::vector<hipEvent_t> pool;
     double t_ms[3] = {0, 0, 0};
     int64_t t_n[3] = {0, 0, 0};
+    std::string err;
+};
+
+
+// --------------------------------------------------------------------------
+// Batch: independent domains stepped together by one launch per lattice type
+// and kernel (optionally replayed from a captured graph).
+// --------------------------------------------------------------------------
+struct lbpf_batch {
+    std::vector<lbpf_ctx*> dom;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    int storage = LBPF_F32;
+    int shape = 3, zslab = 6;
+    void* d_desc = nullptr;        // DomainDesc<T>[ndom]
+    int2* d_work[2] = {};          // work tables of the D3Q15 and D3Q19 domains
+    int nwork[2] = {0, 0};
+    bool built = false;
+    int graph_steps = 0;
+    hipGraphExec_t gexec = nullptr;
+    int g_cur = -1;
     std::string err;
 };
 
@@ -367,6 +393,8 @@ bool healthy(const lbpf_reductions& r) {
 }
 
 void free_all(lbpf_ctx* ctx) {
+    if (ctx->gexec) (void)hipGraphExecDestroy(ctx->gexec);
+    ctx->gexec = nullptr;
     for (int f = 0; f < 3; ++f)
         for (int p = 0; p < 2; ++p) {
             if (ctx->pop[f][p]) (void)hipFree(ctx->pop[f][p]);
@@ -435,6 +463,14 @@ lbpf_status lbpf_create(const lbpf_grid* grid, const lbpf_params* params, void* 
     ctx->grid = g;
     ctx->prm = p;
     ctx->stream = (hipStream_t)hip_stream;
+    if (!ctx->stream) {
+        // capture needs a stream other than the null stream: own one
+        if (hipStreamCreateWithFlags(&ctx->stream, hipStreamNonBlocking) != hipSuccess) {
+            delete ctx;
+            return fail(nullptr, LBPF_EDEVICE, "hipStreamCreateWithFlags failed");
+        }
+        ctx->own_stream = true;
+    }
     ctx->q = g.lattice;
     ctx->storage = g.storage;
     ctx->sbytes = (size_t)lbpf_storage_bytes(g.storage);
@@ -456,6 +492,7 @@ lbpf_status lbpf_create(const lbpf_grid* grid, const lbpf_params* params, void* 
         const lbpf_status s = e == hipErrorOutOfMemory ? LBPF_ENOMEM : LBPF_EDEVICE;
         const std::string msg = std::string("device allocation: ") + hipGetErrorString(e);
         free_all(ctx);
+        if (ctx->own_stream) (void)hipStreamDestroy(ctx->stream);
         delete ctx;
         return fail(nullptr, s, msg);
     }
@@ -465,9 +502,10 @@ lbpf_status lbpf_create(const lbpf_grid* grid, const lbpf_params* params, void* 
 
 lbpf_status lbpf_destroy(lbpf_ctx* ctx) {
     if (!ctx) return LBPF_OK;
-    if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
-    else (void)hipDeviceSynchronize();
+    if (ctx->in_batch) return fail(ctx, LBPF_ESTATE, "context belongs to a batch");
+    (void)hipStreamSynchronize(ctx->stream);
     free_all(ctx);
+    if (ctx->own_stream) (void)hipStreamDestroy(ctx->stream);
     delete ctx;
     return LBPF_OK;
 }
@@ -498,21 +536,79 @@ lbpf_status lbpf_set_fields(lbpf_ctx* ctx, const double* phi, const double* U, c
     return LBPF_OK;
 }
 
+// Capture graph_steps (even) steps starting from the current parity; the
+// parity is the same again after the graph, so the graph is replayable.
+lbpf_status capture_graph(lbpf_ctx* ctx) {
+    if (ctx->gexec) {
+        (void)hipGraphExecDestroy(ctx->gexec);
+        ctx->gexec = nullptr;
+    }
+    const int cur0 = ctx->cur;
+    const bool was = ctx->timing;
+    ctx->timing = false;
+    hipGraph_t g = nullptr;
+    CHK(hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeThreadLocal));
+    lbpf_status st = LBPF_OK;
+    for (int k = 0; k < ctx->graph_steps && !st; ++k) st = launch_step(ctx);
+    const hipError_t e = hipStreamEndCapture(ctx->stream, &g);
+    ctx->timing = was;
+    ctx->cur = cur0;
+    if (st) { if (g) (void)hipGraphDestroy(g); return st; }
+    if (e != hipSuccess) return fail(ctx, LBPF_EDEVICE, std::string("stream capture: ") + hipGetErrorString(e));
+    const hipError_t e2 = hipGraphInstantiate(&ctx->gexec, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e2 != hipSuccess) {
+        ctx->gexec = nullptr;
+        return fail(ctx, LBPF_EDEVICE, std::string("graph instantiate: ") + hipGetErrorString(e2));
+    }
+    ctx->g_shape = ctx->shape; ctx->g_zslab = ctx->zslab; ctx->g_remap = ctx->remap; ctx->g_cur = cur0;
+    return LBPF_OK;
+}
+
 lbpf_status lbpf_step(lbpf_ctx* ctx, int64_t nsteps) {
     if (!ctx) return LBPF_EINVAL;
     if (nsteps < 0) return fail(ctx, LBPF_EINVAL, "nsteps < 0");
     if (!ctx->have_fields) return fail(ctx, LBPF_ESTATE, "lbpf_set_fields has not been called");
+    if (ctx->in_batch) return fail(ctx, LBPF_ESTATE, "context belongs to a batch; use lbpf_batch_step");
     const int R = ctx->prm.reduce_every;
-    for (int64_t s = 0; s < nsteps; ++s) {
-        lbpf_status st = launch_step(ctx);
-        if (st) return st;
-        ctx->step++;
+    const int G = ctx->graph_steps;
+    int64_t left = nsteps;
+    while (left > 0) {
+        const int64_t to_red = R > 0 ? R - ctx->step % R : left;
+        if (G > 0 && !ctx->timing && std::min(left, to_red) >= G) {
+            if (!ctx->gexec || ctx->g_shape != ctx->shape || ctx->g_zslab != ctx->zslab ||
+                ctx->g_remap != ctx->remap || ctx->g_cur != ctx->cur) {
+                lbpf_status st = capture_graph(ctx);
+                if (st) return st;
+            }
+            CHK(hipGraphLaunch(ctx->gexec, ctx->stream));
+            ctx->step += G;
+            left -= G;
+        } else {
+            lbpf_status st = launch_step(ctx);
+            if (st) return st;
+            ctx->step++;
+            left--;
+        }
         if (R > 0 && ctx->step % R == 0) {
             double* rec = ctx->hist + (size_t)(ctx->hist_count % HIST_CAP) * RED_STRIDE;
-            st = launch_reduce(ctx, rec);
+            lbpf_status st = launch_reduce(ctx, rec);
             if (st) return st;
             ctx->hist_count++;
         }
+    }
+    return LBPF_OK;
+}
+
+lbpf_status lbpf_set_graph(lbpf_ctx* ctx, int32_t steps_per_graph) {
+    if (!ctx) return LBPF_EINVAL;
+    if (steps_per_graph < 0 || (steps_per_graph % 2) != 0)
+        return fail(ctx, LBPF_EINVAL, "steps_per_graph must be 0 or a positive even number");
+    ctx->graph_steps = steps_per_graph;
+    if (ctx->gexec) {
+        (void)hipStreamSynchronize(ctx->stream);
+        (void)hipGraphExecDestroy(ctx->gexec);
+        ctx->gexec = nullptr;
     }
     return LBPF_OK;
 }
@@ -764,5 +860,242 @@ lbpf_status lbpf_bench_copy(void* dst, const void* src, int64_t nbytes, void* hi
                        (u32x4*)dst, n16);
     return hipGetLastError() == hipSuccess ? LBPF_OK : LBPF_EDEVICE;
 }
+
+}  // extern "C"
+
+// ---------------------------------------------------------------- batches
+namespace {
+
+#define BCHK(call)                                                                 \
+    do {                                                                           \
+        hipError_t e_ = (call);                                                    \
+        if (e_ != hipSuccess) {                                                    \
+            b->err = std::string(#call) + ": " + hipGetErrorString(e_);            \
+            return LBPF_EDEVICE;                                                   \
+        }                                                                          \
+    } while (0)
+
+lbpf_status bfail(lbpf_batch* b, lbpf_status s, const std::string& m) {
+    if (b) b->err = m;
+    else g_create_error = m;
+    return s;
+}
+
+template <class T>
+lbpf_status batch_build_t(lbpf_batch* b) {
+    const int nd = (int)b->dom.size();
+    std::vector<DomainDesc<T>> desc(nd);
+    std::vector<std::vector<int2>> items(2);
+    for (int d = 0; d < nd; ++d) {
+        lbpf_ctx* c = b->dom[d];
+        c->shape = b->shape;
+        c->zslab = b->zslab;
+        c->remap = 0;   // the work table carries the XCD order
+        desc[d].c = make_coef<T>(c);
+        for (int f = 0; f < 3; ++f)
+            for (int par = 0; par < 2; ++par) {
+                desc[d].pop[f][par] = c->pop[f][par];
+                desc[d].fld[f][par] = (T*)c->fld[f][par];
+            }
+        const int li = c->q == 15 ? 0 : 1;
+        const int nt = total_tiles(c);
+        for (int t = 0; t < nt; ++t) items[li].push_back(int2{d, t});
+    }
+    if (!b->d_desc) BCHK(hipMalloc(&b->d_desc, sizeof(DomainDesc<T>) * nd));
+    BCHK(hipMemcpy(b->d_desc, desc.data(), sizeof(DomainDesc<T>) * nd, hipMemcpyHostToDevice));
+    for (int li = 0; li < 2; ++li) {
+        std::vector<int2>& it = items[li];
+        if (b->d_work[li]) { (void)hipFree(b->d_work[li]); b->d_work[li] = nullptr; }
+        b->nwork[li] = 0;
+        if (it.empty()) continue;
+        while (it.size() % 8) it.push_back(int2{-1, 0});
+        // block k*8 + x runs on XCD x: give each XCD a contiguous run of tiles
+        const size_t m = it.size() / 8;
+        std::vector<int2> w(it.size());
+        for (size_t blk = 0; blk < it.size(); ++blk) w[blk] = it[(blk % 8) * m + blk / 8];
+        BCHK(hipMalloc((void**)&b->d_work[li], sizeof(int2) * w.size()));
+        BCHK(hipMemcpy(b->d_work[li], w.data(), sizeof(int2) * w.size(), hipMemcpyHostToDevice));
+        b->nwork[li] = (int)w.size();
+    }
+    b->built = true;
+    return LBPF_OK;
+}
+
+template <class L, class T, class S, int TX, int TY>
+lbpf_status batch_launch_l(lbpf_batch* b, int li, int par) {
+    if (!b->nwork[li]) return LBPF_OK;
+    hipLaunchKernelGGL((k_phi_batch<L, T, S, TX, TY>), dim3(b->nwork[li]), dim3(TX * TY), 0, b->stream,
+                       (const DomainDesc<T>*)b->d_desc, (const int2*)b->d_work[li], par);
+    BCHK(hipGetLastError());
+    return LBPF_OK;
+}
+
+template <class L, class T, class S, int TX, int TY>
+lbpf_status batch_launch_u(lbpf_batch* b, int li, int par) {
+    if (!b->nwork[li]) return LBPF_OK;
+    hipLaunchKernelGGL((k_ut_batch<L, T, S, TX, TY>), dim3(b->nwork[li]), dim3(TX * TY), 0, b->stream,
+                       (const DomainDesc<T>*)b->d_desc, (const int2*)b->d_work[li], par);
+    BCHK(hipGetLastError());
+    return LBPF_OK;
+}
+
+// One time step of every domain: phase field of all domains, then U/theta.
+template <class T, class S, int TX, int TY>
+lbpf_status batch_step_t(lbpf_batch* b, int par) {
+    lbpf_status st = batch_launch_l<D3Q15, T, S, TX, TY>(b, 0, par);
+    if (!st) st = batch_launch_l<D3Q19, T, S, TX, TY>(b, 1, par);
+    if (!st) st = batch_launch_u<D3Q15, T, S, TX, TY>(b, 0, par);
+    if (!st) st = batch_launch_u<D3Q19, T, S, TX, TY>(b, 1, par);
+    return st;
+}
+
+lbpf_status batch_step_once(lbpf_batch* b, int par) {
+    switch (b->storage) {
+        case LBPF_F32: return batch_step_t<float, float, 32, 8>(b, par);
+        case LBPF_F16_DEV: return batch_step_t<float, __half, 32, 8>(b, par);
+        case LBPF_BF16_DEV: return batch_step_t<float, __hip_bfloat16, 32, 8>(b, par);
+        case LBPF_F64: return batch_step_t<double, double, 32, 4>(b, par);
+    }
+    return bfail(b, LBPF_EINVAL, "bad storage");
+}
+
+lbpf_status batch_build(lbpf_batch* b) {
+    return b->storage == LBPF_F64 ? batch_build_t<double>(b) : batch_build_t<float>(b);
+}
+
+}  // namespace
+
+extern "C" {
+
+lbpf_status lbpf_batch_create(int32_t n, const lbpf_grid* grids, const lbpf_params* params,
+                              void* hip_stream, lbpf_batch** out) {
+    if (!out) return bfail(nullptr, LBPF_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (n < 1 || !grids || !params) return bfail(nullptr, LBPF_EINVAL, "need n >= 1 grids and params");
+    for (int i = 1; i < n; ++i)
+        if (grids[i].storage != grids[0].storage)
+            return bfail(nullptr, LBPF_EINVAL, "all domains of a batch share one storage type");
+    lbpf_batch* b = new (std::nothrow) lbpf_batch();
+    if (!b) return bfail(nullptr, LBPF_ENOMEM, "host allocation failed");
+    b->storage = grids[0].storage;
+    b->shape = b->storage == LBPF_F64 ? 2 : 3;   // 32x4 (FP64) or 32x8 tiles
+    b->stream = (hipStream_t)hip_stream;
+    if (!b->stream) {
+        if (hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking) != hipSuccess) {
+            delete b;
+            return bfail(nullptr, LBPF_EDEVICE, "hipStreamCreateWithFlags failed");
+        }
+        b->own_stream = true;
+    }
+    for (int i = 0; i < n; ++i) {
+        lbpf_ctx* c = nullptr;
+        const lbpf_status st = lbpf_create(&grids[i], &params[i], b->stream, &c);
+        if (st) {
+            const std::string msg = "domain " + std::to_string(i) + ": " + g_create_error;
+            for (lbpf_ctx* d : b->dom) lbpf_destroy(d);
+            if (b->own_stream) (void)hipStreamDestroy(b->stream);
+            delete b;
+            return bfail(nullptr, st, msg);
+        }
+        c->in_batch = true;
+        b->dom.push_back(c);
+        if ((size_t)c->q * c->np * c->sbytes >= ((size_t)1 << 32) - 256) {
+            for (lbpf_ctx* d : b->dom) { d->in_batch = false; lbpf_destroy(d); }
+            if (b->own_stream) (void)hipStreamDestroy(b->stream);
+            delete b;
+            return bfail(nullptr, LBPF_EINVAL, "batch domains must hold < 4 GiB of populations per field");
+        }
+    }
+    *out = b;
+    return LBPF_OK;
+}
+
+lbpf_ctx* lbpf_batch_domain(lbpf_batch* b, int32_t i) {
+    if (!b || i < 0 || i >= (int32_t)b->dom.size()) return nullptr;
+    return b->dom[i];
+}
+
+lbpf_status lbpf_batch_set_graph(lbpf_batch* b, int32_t steps_per_graph) {
+    if (!b) return LBPF_EINVAL;
+    if (steps_per_graph < 0 || (steps_per_graph % 2) != 0)
+        return bfail(b, LBPF_EINVAL, "steps_per_graph must be 0 or a positive even number");
+    b->graph_steps = steps_per_graph;
+    if (b->gexec) {
+        (void)hipStreamSynchronize(b->stream);
+        (void)hipGraphExecDestroy(b->gexec);
+        b->gexec = nullptr;
+    }
+    return LBPF_OK;
+}
+
+lbpf_status lbpf_batch_step(lbpf_batch* b, int64_t nsteps) {
+    if (!b) return LBPF_EINVAL;
+    if (nsteps < 0) return bfail(b, LBPF_EINVAL, "nsteps < 0");
+    const int cur = b->dom[0]->cur;
+    for (lbpf_ctx* c : b->dom) {
+        if (!c->have_fields) return bfail(b, LBPF_ESTATE, "a domain has no fields yet");
+        if (c->cur != cur) return bfail(b, LBPF_ESTATE, "domains are at different parities");
+    }
+    if (!b->built) {
+        lbpf_status st = batch_build(b);
+        if (st) return st;
+    }
+    int par = cur;
+    int64_t left = nsteps;
+    const int G = b->graph_steps;
+    while (left > 0) {
+        if (G > 0 && left >= G) {
+            if (!b->gexec || b->g_cur != par) {
+                if (b->gexec) { (void)hipGraphExecDestroy(b->gexec); b->gexec = nullptr; }
+                hipGraph_t g = nullptr;
+                BCHK(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
+                lbpf_status st = LBPF_OK;
+                int p = par;
+                for (int k = 0; k < G && !st; ++k) { st = batch_step_once(b, p); p = 1 - p; }
+                const hipError_t e = hipStreamEndCapture(b->stream, &g);
+                if (st) { if (g) (void)hipGraphDestroy(g); return st; }
+                if (e != hipSuccess) return bfail(b, LBPF_EDEVICE, std::string("capture: ") + hipGetErrorString(e));
+                const hipError_t e2 = hipGraphInstantiate(&b->gexec, g, nullptr, nullptr, 0);
+                (void)hipGraphDestroy(g);
+                if (e2 != hipSuccess) { b->gexec = nullptr; return bfail(b, LBPF_EDEVICE, "graph instantiate"); }
+                b->g_cur = par;
+            }
+            BCHK(hipGraphLaunch(b->gexec, b->stream));
+            left -= G;
+            for (lbpf_ctx* c : b->dom) c->step += G;
+        } else {
+            lbpf_status st = batch_step_once(b, par);
+            if (st) return st;
+            par = 1 - par;
+            left--;
+            for (lbpf_ctx* c : b->dom) { c->cur = par; c->step++; }
+        }
+    }
+    return LBPF_OK;
+}
+
+lbpf_status lbpf_batch_sync(lbpf_batch* b) {
+    if (!b) return LBPF_EINVAL;
+    BCHK(hipStreamSynchronize(b->stream));
+    return LBPF_OK;
+}
+
+lbpf_status lbpf_batch_destroy(lbpf_batch* b) {
+    if (!b) return LBPF_OK;
+    (void)hipStreamSynchronize(b->stream);
+    if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
+    if (b->d_desc) (void)hipFree(b->d_desc);
+    for (int li = 0; li < 2; ++li)
+        if (b->d_work[li]) (void)hipFree(b->d_work[li]);
+    for (lbpf_ctx* c : b->dom) {
+        c->in_batch = false;
+        lbpf_destroy(c);
+    }
+    if (b->own_stream) (void)hipStreamDestroy(b->stream);
+    delete b;
+    return LBPF_OK;
+}
+
+const char* lbpf_batch_last_error(const lbpf_batch* b) { return b ? b->err.c_str() : g_create_error.c_str(); }
 
 }  // extern "C"

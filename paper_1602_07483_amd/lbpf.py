@@ -58,7 +58,9 @@ SYMBOLS = ["lbpf_create", "lbpf_destroy", "lbpf_set_fields", "lbpf_step", "lbpf_
            "lbpf_read_populations_f64",
            "lbpf_debug_stream_only", "lbpf_set_timing", "lbpf_kernel_times",
            "lbpf_set_launch", "lbpf_get_launch", "lbpf_autotune",
-           "lbpf_storage_bytes", "lbpf_bench_copy", "lbpf_last_error"]
+           "lbpf_storage_bytes", "lbpf_bench_copy", "lbpf_last_error", "lbpf_set_graph",
+           "lbpf_batch_create", "lbpf_batch_domain", "lbpf_batch_set_graph", "lbpf_batch_step",
+           "lbpf_batch_sync", "lbpf_batch_destroy", "lbpf_batch_last_error"]
 
 
 class LbpfError(RuntimeError):
@@ -95,6 +97,14 @@ def load():
         "lbpf_storage_bytes": ([ctypes.c_int32], ctypes.c_int32),
         "lbpf_bench_copy": ([vp, vp, ctypes.c_int64, vp], ctypes.c_int),
         "lbpf_last_error": ([vp], ctypes.c_char_p),
+        "lbpf_set_graph": ([vp, ctypes.c_int32], ctypes.c_int),
+        "lbpf_batch_create": ([ctypes.c_int32, P(lbpf_grid), P(lbpf_params), vp, P(vp)], ctypes.c_int),
+        "lbpf_batch_domain": ([vp, ctypes.c_int32], vp),
+        "lbpf_batch_set_graph": ([vp, ctypes.c_int32], ctypes.c_int),
+        "lbpf_batch_step": ([vp, ctypes.c_int64], ctypes.c_int),
+        "lbpf_batch_sync": ([vp], ctypes.c_int),
+        "lbpf_batch_destroy": ([vp], ctypes.c_int),
+        "lbpf_batch_last_error": ([vp], ctypes.c_char_p),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -126,26 +136,48 @@ def lbpf_bench_copy(dst_ptr, src_ptr, nbytes, stream_ptr=0):
                                  int(nbytes), ctypes.c_void_p(stream_ptr))
 
 
+def make_structs(nx, ny, nz, lattice=19, walls=(0,) * 6, storage="f32", dx=1.0, dt=1.0,
+                 W0=1.0, tau0=1.0, lam=3.2, Mcinf=1.0, k=0.15, D=2.0, kappa=20.0, aniso=0,
+                 eps=0.05, delta=0.0, reduce_every=0, centre=(0.0, 0.0, 0.0)):
+    """(lbpf_grid, lbpf_params) filled from keyword arguments."""
+    g = lbpf_grid()
+    g.nx, g.ny, g.nz, g.lattice = int(nx), int(ny), int(nz), int(lattice)
+    for i, w in enumerate(walls):
+        g.wall[i] = int(w)
+    g.storage = STORAGE[storage] if isinstance(storage, str) else int(storage)
+    p = lbpf_params()
+    p.dx, p.dt, p.W0, p.tau0 = dx, dt, W0, tau0
+    p.lam, p.Mcinf, p.k, p.D, p.kappa = lam, Mcinf, k, D, kappa
+    p.aniso, p.eps, p.delta = int(aniso), eps, delta
+    p.reduce_every = int(reduce_every)
+    for i in range(3):
+        p.centre[i] = float(centre[i])
+    return g, p
+
+
 class Solver:
     """One lbpf context.  Methods mirror the C entry points
     (lbpf_create/set_fields/step/read/...); arrays are numpy (nz, ny, nx)."""
+
+    @classmethod
+    def _wrap(cls, handle, grid, params, owner):
+        self = cls.__new__(cls)
+        self._lib = lib()
+        self.grid, self.params = grid, params
+        self.shape = (grid.nz, grid.ny, grid.nx)
+        self.q = grid.lattice
+        self.storage = grid.storage
+        self._h = ctypes.c_void_p(handle)
+        self._owner = owner          # the batch keeps the memory; never destroyed here
+        return self
 
     def __init__(self, nx, ny, nz, lattice=19, walls=(0,) * 6, storage="f32", dx=1.0, dt=1.0,
                  W0=1.0, tau0=1.0, lam=3.2, Mcinf=1.0, k=0.15, D=2.0, kappa=20.0, aniso=0,
                  eps=0.05, delta=0.0, reduce_every=0, centre=(0.0, 0.0, 0.0), stream=0):
         self._lib = lib()
-        g = lbpf_grid()
-        g.nx, g.ny, g.nz, g.lattice = int(nx), int(ny), int(nz), int(lattice)
-        for i, w in enumerate(walls):
-            g.wall[i] = int(w)
-        g.storage = STORAGE[storage] if isinstance(storage, str) else int(storage)
-        p = lbpf_params()
-        p.dx, p.dt, p.W0, p.tau0 = dx, dt, W0, tau0
-        p.lam, p.Mcinf, p.k, p.D, p.kappa = lam, Mcinf, k, D, kappa
-        p.aniso, p.eps, p.delta = int(aniso), eps, delta
-        p.reduce_every = int(reduce_every)
-        for i in range(3):
-            p.centre[i] = float(centre[i])
+        self._owner = None
+        g, p = make_structs(nx, ny, nz, lattice, walls, storage, dx, dt, W0, tau0, lam, Mcinf, k,
+                            D, kappa, aniso, eps, delta, reduce_every, centre)
         self.grid, self.params = g, p
         self.shape = (int(nz), int(ny), int(nx))
         self.q = int(lattice)
@@ -164,9 +196,9 @@ class Solver:
         return st
 
     def close(self):
-        if getattr(self, "_h", None):
+        if getattr(self, "_h", None) and getattr(self, "_owner", None) is None:
             self._lib.lbpf_destroy(self._h)
-            self._h = None
+        self._h = None
 
     def __del__(self):
         try:
@@ -229,6 +261,9 @@ class Solver:
     def set_timing(self, enable=True):
         self._check(self._lib.lbpf_set_timing(self._h, 1 if enable else 0))
 
+    def set_graph(self, steps_per_graph):
+        self._check(self._lib.lbpf_set_graph(self._h, int(steps_per_graph)))
+
     def set_launch(self, tile_x, tile_y, zslab, xcd_remap=1):
         self._check(self._lib.lbpf_set_launch(self._h, int(tile_x), int(tile_y), int(zslab),
                                               int(xcd_remap)))
@@ -251,9 +286,63 @@ class Solver:
         return list(ms), list(n)
 
 
+class Batch:
+    """An ensemble of independent domains (lbpf_batch_*).  domains[i] is a
+    Solver view of domain i for set_fields/read."""
+
+    def __init__(self, specs, storage="f32", stream=0):
+        self._lib = lib()
+        n = len(specs)
+        grids = (lbpf_grid * n)()
+        params = (lbpf_params * n)()
+        for i, kw in enumerate(specs):
+            g, p = make_structs(storage=storage, **kw)
+            grids[i], params[i] = g, p
+        h = ctypes.c_void_p()
+        st = self._lib.lbpf_batch_create(n, grids, params, ctypes.c_void_p(stream), ctypes.byref(h))
+        if st != LBPF_OK:
+            raise LbpfError(st, self._lib.lbpf_batch_last_error(None).decode())
+        self._h = h
+        self.domains = [Solver._wrap(self._lib.lbpf_batch_domain(h, i), grids[i], params[i], self)
+                        for i in range(n)]
+
+    def _check(self, st):
+        if st != LBPF_OK:
+            raise LbpfError(st, self._lib.lbpf_batch_last_error(self._h).decode())
+
+    def step(self, n=1):
+        self._check(self._lib.lbpf_batch_step(self._h, int(n)))
+
+    def sync(self):
+        self._check(self._lib.lbpf_batch_sync(self._h))
+
+    def set_graph(self, steps_per_graph):
+        self._check(self._lib.lbpf_batch_set_graph(self._h, int(steps_per_graph)))
+
+    def close(self):
+        if getattr(self, "_h", None):
+            for d in self.domains:
+                d._h = None
+            self._lib.lbpf_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def problem_kwargs(problem):
+    kw = problem.model_kwargs()
+    kw.update(nx=problem.nx, ny=problem.ny, nz=problem.nz, reduce_every=problem.reduce_every,
+              centre=problem.centre())
+    return kw
+
+
 def solver_for(problem, storage="f32", stream=0, **over):
     """Solver configured from an inputs.Problem (keyword overrides allowed)."""
     kw = problem.model_kwargs()
+    kw.update(reduce_every=problem.reduce_every, centre=problem.centre())
     kw.update(over)
-    return Solver(problem.nx, problem.ny, problem.nz, storage=storage,
-                  reduce_every=problem.reduce_every, centre=problem.centre(), stream=stream, **kw)
+    return Solver(problem.nx, problem.ny, problem.nz, storage=storage, stream=stream, **kw)

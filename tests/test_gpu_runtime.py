@@ -1,0 +1,219 @@
+"""GPU runtime features through the C ABI: launch shapes, graph replay,
+batched ensembles, checkpoint/restore, health checks and the FP64 reductions
+against the oracle."""
+import numpy as np
+import pytest
+
+from oracle import Oracle, R_SOLID, R_MASS, R_ENTHALPY, R_TIPX, R_TIPY, R_TIPZ
+from paper_1602_07483_amd import lbpf
+from paper_1602_07483_amd.inputs import Problem, workload_small, workload_octant, NOFLUX, SYMMETRY, DT
+from tests.pairs import make_oracle, make_gpu, maxabs
+
+pytestmark = pytest.mark.gpu
+
+
+def ragged(lattice=19, n=(45, 23, 21), aniso=0, eps=0.05, delta=0.0, U0=-0.55, seed=3,
+           walls=(SYMMETRY, NOFLUX, NOFLUX, SYMMETRY, SYMMETRY, NOFLUX)):
+    nx, ny, nz = n
+    return Problem("ragged", nx, ny, nz, lattice, walls, dt=DT, aniso=aniso, eps=eps, delta=delta,
+                   centres=[(-0.5, ny - 0.5, -0.5)], radius=6.0, U0=U0, theta0=U0,
+                   noise_amp=1e-3, noise_seed=seed)
+
+
+def fields(s):
+    phi, U, th, _ = s.read(reductions=False)
+    return phi, U, th
+
+
+def test_launch_shape_does_not_change_results():
+    """Tile shape, slab height and XCD order change speed only: bit-identical fields."""
+    pb = ragged()
+    ref = None
+    for launch in [(32, 8, 6, 1), (64, 2, 8, 1), (32, 4, 2, 0), (64, 4, 16, 1), (32, 16, 4, 1), (32, 8, 1, 0)]:
+        s = make_gpu(pb, "f32")
+        s.set_launch(*launch)
+        s.step(40)
+        out = fields(s)
+        s.close()
+        if ref is None:
+            ref = out
+        else:
+            for a, b in zip(ref, out):
+                assert np.array_equal(a, b), launch
+
+
+def test_graph_replay_equals_plain_launches():
+    """Replays of a captured graph, with reads and plain steps in between,
+    match plain launches bit for bit after every replay."""
+    pb = ragged(lattice=15, n=(40, 33, 17))
+    plain = make_gpu(pb, "f32")
+    graph = make_gpu(pb, "f32")
+    graph.set_graph(4)
+    for chunk in (3, 8, 4, 1, 12, 4):
+        plain.step(chunk)
+        graph.step(chunk)
+        a, b = fields(plain), fields(graph)
+        for x, y in zip(a, b):
+            assert np.array_equal(x, y), chunk
+    graph.set_launch(32, 4, 4, 1)   # new shape: the graph is captured again
+    plain.set_launch(32, 4, 4, 1)
+    graph.step(8)
+    plain.step(8)
+    for x, y in zip(fields(plain), fields(graph)):
+        assert np.array_equal(x, y)
+
+
+def _batch_problems():
+    return [ragged(15, (33, 21, 19), eps=0.03, U0=-0.5, seed=11),
+            ragged(19, (40, 35, 24), eps=0.06, U0=-0.6, seed=12),
+            ragged(15, (64, 8, 9), eps=0.02, U0=-0.45, seed=13, walls=(NOFLUX,) * 6),
+            ragged(19, (17, 40, 33), aniso=1, eps=0.0, delta=-0.02, seed=14),
+            ragged(19, (29, 29, 29), eps=0.07, U0=-0.65, seed=15, walls=(SYMMETRY,) * 6)]
+
+
+@pytest.mark.parametrize("graph_steps", [0, 6])
+def test_batch_matches_domains_stepped_alone(graph_steps):
+    """Each domain of a mixed D3Q15/D3Q19 batch against the same domain
+    stepped alone.  The batch kernels are compiled separately (coefficients
+    come from a descriptor), so contraction into FMAs may differ: after 25
+    steps the fields agree to a few ulp of values of order one."""
+    probs = _batch_problems()
+    b = lbpf.Batch([lbpf.problem_kwargs(p) for p in probs], storage="f32")
+    for d, p in zip(b.domains, probs):
+        d.set_fields(*p.initial_fields())
+    b.set_graph(graph_steps)
+    b.step(7)
+    b.step(18)
+    got = [fields(d) for d in b.domains]
+    for p, g in zip(probs, got):
+        s = make_gpu(p, "f32")
+        s.step(25)
+        for x, y in zip(fields(s), g):
+            assert maxabs(x, y) <= 1e-6, p
+        s.close()
+    b.close()
+
+
+def test_batch_graph_and_chunking_are_bit_exact():
+    """Within the batch, graph replay and step chunking change nothing."""
+    probs = _batch_problems()
+    outs = []
+    for graph_steps, chunks in ((0, (25,)), (6, (7, 18)), (4, (1, 3, 21))):
+        b = lbpf.Batch([lbpf.problem_kwargs(p) for p in probs], storage="f32")
+        for d, p in zip(b.domains, probs):
+            d.set_fields(*p.initial_fields())
+        b.set_graph(graph_steps)
+        for c in chunks:
+            b.step(c)
+        outs.append([fields(d) for d in b.domains])
+        b.close()
+    for other in outs[1:]:
+        for a, b in zip(outs[0], other):
+            for x, y in zip(a, b):
+                assert np.array_equal(x, y)
+
+
+def test_batch_fp64_matches_oracle():
+    probs = _batch_problems()[:3]
+    b = lbpf.Batch([lbpf.problem_kwargs(p) for p in probs], storage="f64")
+    for d, p in zip(b.domains, probs):
+        d.set_fields(*p.initial_fields())
+    b.step(30)
+    for d, p in zip(b.domains, probs):
+        o = make_oracle(p)
+        o.step(30)
+        for x, y in zip(fields(d), o.fields()):
+            assert maxabs(x, y) <= 1e-11
+    b.close()
+
+
+@pytest.mark.parametrize("storage", ["f32", "f16"])
+def test_checkpoint_restore_is_bit_exact(storage):
+    """Fields plus raw stored populations restore the state exactly."""
+    pb = ragged()
+    s = make_gpu(pb, storage)
+    s.step(20)
+    phi, U, th = fields(s)
+    pops = [s.read_populations(f) for f in range(3)]
+    s.step(15)
+    want = fields(s)
+    r = lbpf.solver_for(pb, storage=storage)
+    r.set_fields(phi, U, th)
+    for f in range(3):
+        r.write_populations(f, pops[f])
+    r.step(15)
+    for x, y in zip(want, fields(r)):
+        assert np.array_equal(x, y)
+
+
+def test_health_check_reports_unstable_state():
+    pb = ragged()
+    phi, U, th = pb.initial_fields()
+    U = U.copy()
+    U[3, 4, 5] = np.nan
+    pb.reduce_every = 2
+    s = lbpf.solver_for(pb, storage="f32")
+    s.set_fields(phi, U, th)
+    s.step(2)
+    assert s.sync(check=False) == lbpf.LBPF_EUNSTABLE
+    st, red = s.read_status()
+    assert st == lbpf.LBPF_EUNSTABLE and red["nonfinite"] > 0
+    phi2 = pb.initial_fields()[0].copy()
+    phi2[0, 0, 0] = 5.0
+    s2 = make_gpu(pb, "f32")
+    s2.set_fields(phi2, *pb.initial_fields()[1:])
+    st, red = s2.read_status()
+    assert st == lbpf.LBPF_EUNSTABLE and red["phi_max"] == 5.0
+    healthy = make_gpu(pb, "f32")
+    healthy.step(5)
+    assert healthy.read_status()[0] == lbpf.LBPF_OK
+
+
+def test_reductions_and_tip_velocity_match_oracle():
+    """FP64 reductions of the FP32 run against the oracle's: solid fraction,
+    solute mass, enthalpy, tip positions; tip velocity within 1 %."""
+    pb = workload_octant(n=48, steps=400)
+    pb.reduce_every = 50
+    s = make_gpu(pb, "f32")
+    s.step(400)
+    hist = s.history()
+    assert [h["step"] for h in hist] == list(range(50, 401, 50))
+    o = make_oracle(pb)
+    tips_g, tips_o = [], []
+    for h in hist:
+        o.step(50)
+        r = o.reduce(pb.centre())
+        assert abs(h["solid_fraction"] - r[R_SOLID]) < 1e-6
+        assert abs(h["solute_mass"] - r[R_MASS]) < 1e-6 * abs(r[R_MASS])
+        assert abs(h["enthalpy"] - r[R_ENTHALPY]) < 1e-6 * pb.nodes
+        tips_g.append(h["tip"][0])
+        tips_o.append(r[R_TIPX])
+        for a, key in enumerate((R_TIPX, R_TIPY, R_TIPZ)):
+            assert abs(h["tip"][a] - r[key]) < 1e-3
+    vg = np.diff(tips_g) / 50.0
+    vo = np.diff(tips_o) / 50.0
+    ok = np.abs(vo) > 1e-3
+    assert ok.sum() >= 3
+    rel = np.abs(vg[ok] - vo[ok]) / np.abs(vo[ok])
+    print("tip velocity rel. error FP32:", rel.max())
+    assert rel.max() < 0.01
+
+
+@pytest.mark.parametrize("storage,bound", [("f16", 0.02), ("bf16", 0.1)])
+def test_mixed_storage_tip_velocity_report(storage, bound):
+    """Mixed storage error against the oracle (reported; loose bound)."""
+    pb = workload_octant(n=48, steps=400)
+    pb.reduce_every = 100
+    s = make_gpu(pb, storage)
+    s.step(400)
+    hist = s.history()
+    o = make_oracle(pb)
+    tg, to = [], []
+    for h in hist:
+        o.step(100)
+        tg.append(h["tip"][0])
+        to.append(o.reduce(pb.centre())[R_TIPX])
+    vg, vo = np.diff(tg), np.diff(to)
+    rel = np.max(np.abs(vg - vo) / np.abs(vo))
+    print("%s tip velocity rel. error %.3e" % (storage, rel))
+    assert rel < bound

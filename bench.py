@@ -67,12 +67,12 @@ def run_gpu(storage, steps, warmup, n, launch=None):
     stream = torch.cuda.current_stream().cuda_stream
     s = lbpf.solver_for(pb, storage=storage, stream=stream)
     s.set_fields(*pb.initial_fields())
-    if launch is None:
+    if launch == "auto":
         # launch shape picked by the library's autotuner (state restored after)
         launch, _ = s.autotune(6)
-    else:
+    elif launch is not None:
         s.set_launch(*launch)
-        launch = s.get_launch()
+    launch = s.get_launch()
     s.step(warmup)
     s.sync()
     torch.cuda.synchronize()
@@ -149,7 +149,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
     ap.add_argument("--no-variants", action="store_true", help="FP32 only")
     ap.add_argument("--launch", default=None,
-                    help="tile_x,tile_y,zslab,xcd_remap instead of the autotuner")
+                    help="tile_x,tile_y,zslab,xcd_remap instead of the library default")
+    ap.add_argument("--autotune", action="store_true",
+                    help="let the library's autotuner pick the launch before timing")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU only; --gpus %d is not supported "
@@ -158,6 +160,8 @@ def main():
     rank = int(os.environ.get("RANK", "0"))
 
     launch = tuple(int(v) for v in args.launch.split(",")) if args.launch else None
+    if args.autotune:
+        launch = "auto"
     res = run_gpu("f32", args.steps, args.warmup, args.n, launch)
     variants = {}
     if not args.no_variants:

@@ -113,6 +113,31 @@ __device__ __forceinline__ void buf_st(__hip_bfloat16 x, __amdgpu_buffer_rsrc_t 
     __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, x), r, (int)v, (int)s, 2);
 }
 
+// Prefetch registers hold populations in a raw form, decoded where used.
+// BF16 values are kept as zero-extended 32-bit words and widened with one
+// explicit shift: written as a plain shift, the compiler folds the widening
+// into half-register loads whose partial writes force a wait after each load.
+template <class S> struct Raw {
+    using type = S;
+    __device__ static S ld(__amdgpu_buffer_rsrc_t r, unsigned v, unsigned s) { return buf_ld<S>(r, v, s); }
+    __device__ static S ldg(const S* p) { return *p; }
+    __device__ static auto dec(S x) { return Codec<S>::dec(x); }
+};
+template <> struct Raw<__hip_bfloat16> {
+    using type = unsigned;
+    __device__ static unsigned ld(__amdgpu_buffer_rsrc_t r, unsigned v, unsigned s) {
+        return (unsigned)__builtin_amdgcn_raw_buffer_load_b16(r, (int)v, (int)s, 0);
+    }
+    __device__ static unsigned ldg(const __hip_bfloat16* p) {
+        return (unsigned)*reinterpret_cast<const unsigned short*>(p);
+    }
+    __device__ static float dec(unsigned x) {
+        unsigned o;
+        asm("v_lshlrev_b32 %0, 16, %1" : "=v"(o) : "v"(x));
+        return __builtin_bit_cast(float, o);
+    }
+};
+
 // Reciprocal and reciprocal square root: the hardware instructions (about
 // 1 ulp) in FP32, exact operations in the FP64 verification build.
 __device__ __forceinline__ float frcp(float x) { return __builtin_amdgcn_rcpf(x); }
@@ -442,7 +467,9 @@ __device__ __forceinline__ void phi_body(const Coef<T>& c, int block, const S* _
     // registers filled one iteration ahead
     T pa[M::NA];                       // phi^n of the staged plane
     T pu[M::NB], pt[M::NB];            // U^n, theta^n at the term nodes
-    T pj[L::Q], pnl[L::Q];             // d_j(source) and d_i(x) of the pulled plane
+    // d_j(source) and d_i(x) of the pulled plane, kept in the storage format
+    // and decoded where used, so no conversion sits between the loads.
+    typename Raw<S>::type pj[L::Q], pnl[L::Q];
     auto prefetch = [&](int zz) {
         {   // A of iteration zz
             const size_t base = (size_t)clampi(zz, nz) * plane;
@@ -484,13 +511,13 @@ __device__ __forceinline__ void phi_body(const Coef<T>& c, int block, const S* _
                     const unsigned vx = xi * (unsigned)sizeof(S);
                     const unsigned sI = (unsigned)(I * np) * (unsigned)sizeof(S);
                     const unsigned vj = cr ? vx + (unsigned)off * (unsigned)sizeof(S) : vx;
-                    pnl[I] = (T)Codec<S>::dec(buf_ld<S>(rin, vx, sI));
-                    pj[I] = (T)Codec<S>::dec(buf_ld<S>(rin, vj, sI - (unsigned)off * (unsigned)sizeof(S)));
+                    pnl[I] = Raw<S>::ld(rin, vx, sI);
+                    pj[I] = Raw<S>::ld(rin, vj, sI - (unsigned)off * (unsigned)sizeof(S));
                 } else {
                     const S* gI = gin + (size_t)I * np;
                     const unsigned so = cr ? xi : xi - (unsigned)off;
-                    pnl[I] = (T)Codec<S>::dec(gI[xi]);
-                    pj[I] = (T)Codec<S>::dec(gI[so]);
+                    pnl[I] = Raw<S>::ldg(gI + xi);
+                    pj[I] = Raw<S>::ldg(gI + so);
                 }
             });
         }
@@ -564,7 +591,8 @@ __device__ __forceinline__ void phi_body(const Coef<T>& c, int block, const S* _
                 const int tl = tile.lt - ex - ey * G::HX;
                 const V4<T> ta = sta[sl[1 - ez]][tl], tb = stb[sl[1 - ez]][tl];
                 const T eAV = T(ex) * tb.x + T(ey) * tb.y + T(ez) * tb.z;
-                T v = wi * (ta.x * (ta.w - phx) + ta.z - eAV) + ta.y * pj[I] - (ta.x - T(1)) * pnl[I];
+                T v = wi * (ta.x * (ta.w - phx) + ta.z - eAV) + ta.y * (T)Raw<S>::dec(pj[I]) -
+                         (ta.x - T(1)) * (T)Raw<S>::dec(pnl[I]);
                 if constexpr (EDGE) v = crosses<L, I>(f) ? T(0) : v;
                 inc[I] = v;
                 dsum += v;
@@ -660,7 +688,7 @@ __device__ __forceinline__ void ut_body(const Coef<T>& c, int block, const S* __
 
     T pa[M::NA];                          // phi^{n+1} of the staged plane
     T po_[M::NB], pu[M::NB], pt[M::NB];   // phi^n, U^n, theta^n at the term nodes
-    T ph_[L::Q], pf_[L::Q];               // dh_j, df_j of the pulled plane's sources
+    typename Raw<S>::type ph_[L::Q], pf_[L::Q];   // dh_j, df_j of the pulled plane's sources, raw
     T pUx = T(0), pthx = T(0);            // U^n, theta^n of the pulled node
     auto prefetch = [&](int zz) {
         {
@@ -706,12 +734,12 @@ __device__ __forceinline__ void ut_body(const Coef<T>& c, int block, const S* __
                     const unsigned vx = xi * (unsigned)sizeof(S);
                     const unsigned vj = cr ? vx + (unsigned)off * (unsigned)sizeof(S) : vx;
                     const unsigned sj = (unsigned)(I * np) * (unsigned)sizeof(S) - (unsigned)off * (unsigned)sizeof(S);
-                    ph_[I] = (T)Codec<S>::dec(buf_ld<S>(rhin, vj, sj));
-                    pf_[I] = (T)Codec<S>::dec(buf_ld<S>(rfin, vj, sj));
+                    ph_[I] = Raw<S>::ld(rhin, vj, sj);
+                    pf_[I] = Raw<S>::ld(rfin, vj, sj);
                 } else {
                     const unsigned so = cr ? xi : xi - (unsigned)off;
-                    ph_[I] = (T)Codec<S>::dec(hin[(size_t)I * np + so]);
-                    pf_[I] = (T)Codec<S>::dec(fin[(size_t)I * np + so]);
+                    ph_[I] = Raw<S>::ldg(hin + (size_t)I * np + so);
+                    pf_[I] = Raw<S>::ldg(fin + (size_t)I * np + so);
                 }
             });
         }
@@ -813,9 +841,9 @@ __device__ __forceinline__ void ut_body(const Coef<T>& c, int block, const S* __
                 const int tl = tile.lt - ex - ey * G::HX;
                 const V4<T> ta = sta[sl[1 - ez]][tl], tb = stb[sl[1 - ez]][tl];
                 const T eK = T(ex) * tb.x + T(ey) * tb.y + T(ez) * tb.z;
-                T vu = Bi * ta.y + omU1 * ph_[I] + wi * (ta.z + eK);
+                T vu = Bi * ta.y + omU1 * (T)Raw<S>::dec(ph_[I]) + wi * (ta.z + eK);
                 if constexpr (I != 0) vu += wi * (ta.x - Px);
-                T vt = wi * (ta.w - thx) + omT1 * pf_[I];
+                T vt = wi * (ta.w - thx) + omT1 * (T)Raw<S>::dec(pf_[I]);
                 if constexpr (EDGE) {
                     const bool cr = crosses<L, I>(f);
                     vu = cr ? T(0) : vu;

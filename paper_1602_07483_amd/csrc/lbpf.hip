@@ -65,7 +65,7 @@ struct lbpf_ctx {
     double* fresh = nullptr; // one record for lbpf_read
     int64_t hist_count = 0;
     int shape = 3;           // tile shape id, see kShapes
-    int zslab = 8;
+    int zslab = 4;
     int remap = 1;           // XCD-chunked tile order
     bool timing = false;
     std::vector<TimedLaunch> launches;
@@ -476,7 +476,7 @@ lbpf_status lbpf_create(const lbpf_grid* grid, const lbpf_params* params, void* 
     ctx->sbytes = (size_t)lbpf_storage_bytes(g.storage);
     ctx->tbytes = g.storage == LBPF_F64 ? 8 : 4;
     ctx->shape = g.storage == LBPF_F64 ? 2 : 3;
-    ctx->zslab = 8;
+    ctx->zslab = 4;
     ctx->n = (size_t)g.nx * g.ny * g.nz;
     ctx->np = (ctx->n + 63) / 64 * 64;
     hipError_t e = hipSuccess;

@@ -148,3 +148,31 @@ def workload_centred(n: int = 256, steps: int = 10000) -> Problem:
     return Problem("centred-%d" % n, n, n, n, 19, (NOFLUX,) * 6, dt=DT, eps=0.05,
                    k=0.15, U0=-0.6, theta0=-0.6, centres=[(c, c, c)], radius=10.0,
                    steps=steps, reduce_every=100)
+
+
+def workload_centred_octant(n: int = 256, steps: int = 10000) -> Problem:
+    """The octant x, y, z >= n/2 of workload_centred(n): an (n/2)^3 domain with
+    mirror walls on the three faces through the seed centre (which sits on
+    the half link between nodes n/2-1 and n/2) and the original no-flux walls
+    on the far faces.  A run of it equals that octant of the full run, and
+    its reductions give the full domain's tip position and solid fraction
+    (sums scale by 8)."""
+    m = n // 2
+    return Problem("centred-%d-octant" % n, m, m, m, 19, SEED_FACES, dt=DT, eps=0.05,
+                   k=0.15, U0=-0.6, theta0=-0.6, centres=[CORNER], radius=10.0,
+                   steps=steps, reduce_every=100)
+
+
+def workload_thermal2d(n: int = 500, steps: int = 37500) -> Problem:
+    """Pure-substance thermal dendrite of Sec. 4.1 (anisotropic case) as a
+    one-node-thick D3Q19 slab (mirror walls in z, which reduce D3Q19 to D2Q9):
+    quadrant of n^2 nodes, dx/W0 = 0.4, dt/tau0 = 0.008, kappa = 4,
+    lambda = 6.3826 (zero kinetic coefficient), eps = 0.05, Delta = 0.55,
+    seed radius 10 dx at the mirror corner.  The solute field is decoupled
+    (M c_inf = 0); its diffusivity only has to keep its scheme stable.
+    37 500 steps reach T = t/tau0 = 300."""
+    walls = (SYMMETRY, NOFLUX, SYMMETRY, NOFLUX, SYMMETRY, SYMMETRY)
+    return Problem("thermal2d-%d" % n, n, n, 1, 19, walls, dx=0.4, dt=0.008, W0=1.0,
+                   tau0=1.0, lam=6.3826, Mcinf=0.0, k=0.15, D=1.0, kappa=4.0, eps=0.05,
+                   centres=[(-0.5, -0.5, 0.0)], radius=10.0, U0=0.0, theta0=-0.55,
+                   steps=steps, reduce_every=500)

@@ -176,3 +176,31 @@ def workload_thermal2d(n: int = 500, steps: int = 37500) -> Problem:
                    tau0=1.0, lam=6.3826, Mcinf=0.0, k=0.15, D=1.0, kappa=4.0, eps=0.05,
                    centres=[(-0.5, -0.5, 0.0)], radius=10.0, U0=0.0, theta0=-0.55,
                    steps=steps, reduce_every=500)
+
+
+ENSEMBLE_DT = {15: 0.11, 19: DT}
+
+
+def workload_ensemble(count: int = 64, seed: int = 4, steps: int = 2000) -> List[Problem]:
+    """Batch of independent cubic domains: edge L_j uniform in {32..96},
+    eps_j uniform in [0.02, 0.07], Delta_j uniform in [0.45, 0.65] (draws from
+    SplitMix64 with the given seed), k = 0.15, centred seed R = 8, all walls
+    no-flux, U noise 1e-3 with seed j.  The first half uses D3Q15, the second
+    D3Q19.  Time step: dt/tau0 = 0.15 on D3Q19.  The D3Q15 scheme with the
+    coupled U equation stays finite and within |phi| <= 1 + 1e-3 for all 32
+    of its domains over 2000 steps only near dt/tau0 = 0.11 (at 0.12 and at
+    0.06-0.08 some domains diverge), which its half uses.  Domains with eps > 1/15 have a negative cubic
+    stiffness 1 - 15 eps along <100> and are ill-posed (sharp corners)."""
+    u = uniform01(seed, 3 * count).reshape(count, 3)
+    out = []
+    for j in range(count):
+        L = 32 + int(u[j, 0] * 65.0)
+        eps = float(0.02 + 0.05 * u[j, 1])
+        delta = float(0.45 + 0.20 * u[j, 2])
+        c = (L - 1) / 2.0
+        lat = 15 if j < count // 2 else 19
+        out.append(Problem("ens-%02d" % j, L, L, L, lat, (NOFLUX,) * 6,
+                           dt=ENSEMBLE_DT[lat], eps=eps, k=0.15, U0=-delta, theta0=-delta,
+                           centres=[(c, c, c)], radius=8.0, noise_amp=1e-3, noise_seed=j,
+                           steps=steps, reduce_every=0))
+    return out

@@ -41,14 +41,22 @@ def sphere_field(shape: Tuple[int, int, int], centres: Sequence[Sequence[float]]
                  radius: float, W0: float = 1.0, dx: float = 1.0) -> np.ndarray:
     """phi0 = max over seeds of tanh((R - d)/(sqrt(2) W0)), d the distance to
     the seed centre; centres and R in node-index (lattice) units; shape is
-    (nz, ny, nx)."""
+    (nz, ny, nx).  Each seed is evaluated on its bounding box only: beyond
+    (R - d) dx / (sqrt(2) W0) < -30 the double tanh is exactly -1."""
     nz, ny, nx = shape
-    z, y, x = np.meshgrid(np.arange(nz, dtype=np.float64), np.arange(ny, dtype=np.float64),
-                          np.arange(nx, dtype=np.float64), indexing="ij")
     phi = np.full(shape, -1.0)
+    reach = radius + 30.0 * np.sqrt(2.0) * W0 / dx + 1.0
     for c in centres:
+        lo = [max(0, int(np.floor(c[a] - reach))) for a in range(3)]
+        hi = [min(n, int(np.ceil(c[a] + reach)) + 1) for a, n in enumerate((nx, ny, nz))]
+        if any(h <= l for l, h in zip(lo, hi)):
+            continue
+        z, y, x = np.meshgrid(np.arange(lo[2], hi[2], dtype=np.float64),
+                              np.arange(lo[1], hi[1], dtype=np.float64),
+                              np.arange(lo[0], hi[0], dtype=np.float64), indexing="ij")
         d = np.sqrt((x - c[0]) ** 2 + (y - c[1]) ** 2 + (z - c[2]) ** 2)
-        phi = np.maximum(phi, np.tanh((radius - d) * dx / (np.sqrt(2.0) * W0)))
+        box = phi[lo[2]:hi[2], lo[1]:hi[1], lo[0]:hi[0]]
+        np.maximum(box, np.tanh((radius - d) * dx / (np.sqrt(2.0) * W0)), out=box)
     return phi
 
 
@@ -204,3 +212,33 @@ def workload_ensemble(count: int = 64, seed: int = 4, steps: int = 2000) -> List
                            centres=[(c, c, c)], radius=8.0, noise_amp=1e-3, noise_seed=j,
                            steps=steps, reduce_every=0))
     return out
+
+
+def seed_centres(count: int, lo: float, hi: float, min_sep: float, seed: int):
+    """Seed centres uniform in [lo, hi]^3 with pairwise distance >= min_sep,
+    by rejection sampling of SplitMix64 draws (three per candidate)."""
+    centres = []
+    k = 0
+    while len(centres) < count:
+        u = uniform01(seed, 3 * (k + 1))[3 * k:3 * k + 3]
+        k += 1
+        c = tuple(float(lo + (hi - lo) * v) for v in u)
+        if all(sum((a - b) ** 2 for a, b in zip(c, o)) >= min_sep ** 2 for o in centres):
+            centres.append(c)
+        if k > 100000:
+            raise RuntimeError("cannot place %d seeds" % count)
+    return centres
+
+
+def workload_multiseed(n: int = 512, aniso: int = 0, steps: int = 20000) -> Problem:
+    """n^3 D3Q19, 8 nuclei of radius 6 at SplitMix64 positions (seed 5) in
+    [n/16, n - 1 - n/16]^3 with pairwise separation >= n/8, all walls no-flux,
+    Delta = 0.55, k = 0.15.  aniso 0: cubic a_s with eps = 0.05; aniso 1: the
+    K41/K61 function of Sec. 4.3 with eps = 0, delta = -0.02."""
+    m = n // 16
+    centres = seed_centres(8, float(m), float(n - 1 - m), n / 8.0, 5)
+    eps, delta = (0.05, 0.0) if aniso == 0 else (0.0, -0.02)
+    return Problem("multiseed-%d-%s" % (n, "cubic" if aniso == 0 else "k41k61"), n, n, n, 19,
+                   (NOFLUX,) * 6, dt=DT, aniso=aniso, eps=eps, delta=delta, k=0.15,
+                   U0=-0.55, theta0=-0.55, centres=centres, radius=6.0, steps=steps,
+                   reduce_every=500)

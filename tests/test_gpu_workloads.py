@@ -14,7 +14,7 @@ import pytest
 
 from paper_1602_07483_amd import lbpf
 from paper_1602_07483_amd.inputs import (workload_thermal2d, workload_octant, workload_centred,
-                                         workload_ensemble)
+                                         workload_ensemble, workload_multiseed)
 from tests.pairs import make_oracle, make_gpu, maxabs
 
 pytestmark = pytest.mark.gpu
@@ -169,3 +169,75 @@ def test_ensemble_health_and_sampled_parity():
                                                               maxabs(phi, ophi), maxabs(U, oU)))
         assert maxabs(phi, ophi) <= 1e-5 and maxabs(U, oU) <= 1e-5 and maxabs(th, oth) <= 1e-5
     b.close()
+
+
+def _subbox_oracle(pb, fields0, node, r, steps):
+    """Oracle values at `node` after `steps` steps, computed on the cube of
+    half-width r around it cut out of the full initial fields.  One step
+    reaches at most 4 nodes (pull link + stencils of phi^n and phi^{n+1}) and
+    the equilibrium start one more, so r >= 4 steps + 2 keeps the cut faces
+    out of the node's domain of dependence."""
+    from oracle import Oracle
+    x, y, z = node
+    sl = (slice(z - r, z + r + 1), slice(y - r, y + r + 1), slice(x - r, x + r + 1))
+    kw = pb.model_kwargs()
+    kw["walls"] = (0,) * 6
+    o = Oracle(2 * r + 1, 2 * r + 1, 2 * r + 1, **kw)
+    o.init(*(np.ascontiguousarray(f[sl]) for f in fields0))
+    o.step(steps)
+    vals = [f[r, r, r] for f in o.fields()]
+    o.close()
+    return vals
+
+
+@pytest.mark.parametrize("storage,aniso,tol", [("f32", 0, 1e-5), ("f16", 0, 5e-3),
+                                               ("f32", 1, 1e-5), ("bf16", 1, 5e-2)])
+def test_multiseed512_sampled_parity(storage, aniso, tol):
+    """512^3, 8 nuclei, cubic or K41/K61 anisotropy, FP32 or mixed storage
+    (at this size every field exceeds 4 GiB of populations, so the kernels
+    use 64-bit addressing): after 8 steps, phi, U and theta at 24 nodes on
+    and around the nuclei against the oracle run on a sub-cube per node."""
+    steps, r = 8, 35
+    pb = workload_multiseed(512, aniso=aniso)
+    fields0 = pb.initial_fields()
+    s = make_gpu(pb, storage)
+    s.step(steps)
+    phi, U, th, _ = s.read(reductions=False)
+    s.close()
+    nodes = []
+    for c in pb.centres:
+        b = [int(round(v)) for v in c]
+        sx, sy, sz = (1 if v < 256 else -1 for v in b)         # offsets point inwards
+        nodes.append((b[0] + 6 * sx, b[1], b[2]))              # on the interface
+        nodes.append((b[0], b[1] + 5 * sy, b[2] + 3 * sz))     # inside, off axis
+        nodes.append((b[0] + 4 * sx, b[1] + 4 * sy, b[2] + 4 * sz))   # near the <111> front
+    worst = 0.0
+    for node in nodes:
+        assert all(r <= v < 512 - r for v in node), node
+        want = _subbox_oracle(pb, fields0, node, r, steps)
+        x, y, z = node
+        got = (phi[z, y, x], U[z, y, x], th[z, y, x])
+        err = max(abs(a - b) for a, b in zip(got, want))
+        worst = max(worst, err)
+    print("multiseed512 %s aniso %d: max error at %d sampled nodes %.3e" % (storage, aniso, len(nodes), worst))
+    assert worst <= tol
+
+
+@pytest.mark.parametrize("storage,bound", [("f32", 1e-7), ("f16", 1e-5)])
+def test_multiseed512_enthalpy_conserved(storage, bound):
+    """Sum of (theta - phi/2) is an exact invariant of the scheme with
+    no-flux walls (the theta source is half the phi increment); at 512^3 the
+    FP64 reductions of the FP32/mixed run must keep it to the stated bound
+    per node over 200 steps."""
+    pb = workload_multiseed(512, aniso=0)
+    pb.reduce_every = 50
+    s = make_gpu(pb, storage)
+    _, red0 = s.read_status()
+    s.step(200)
+    hist = s.history()
+    s.close()
+    h0 = red0["enthalpy"]
+    drift = max(abs(h["enthalpy"] - h0) for h in hist) / pb.nodes
+    print("multiseed512 %s: enthalpy drift per node %.3e; solid fraction %.6f -> %.6f"
+          % (storage, drift, red0["solid_fraction"], hist[-1]["solid_fraction"]))
+    assert drift <= bound

@@ -35,6 +35,16 @@ class OrcParams(ctypes.Structure):
     ]
 
 
+class FdoParams(ctypes.Structure):
+    _fields_ = [
+        ("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
+        ("dx", ctypes.c_double), ("W0", ctypes.c_double), ("tau0", ctypes.c_double),
+        ("lam", ctypes.c_double), ("Mcinf", ctypes.c_double), ("k", ctypes.c_double),
+        ("D", ctypes.c_double), ("kappa", ctypes.c_double),
+        ("aniso", ctypes.c_int32), ("eps", ctypes.c_double), ("delta", ctypes.c_double),
+    ]
+
+
 _lib = None
 
 
@@ -68,6 +78,12 @@ def _load():
     lib.orc_geq.argtypes = [ctypes.c_int, ctypes.c_double, dp, ctypes.c_double, dp]
     lib.orc_heq.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_double, dp,
                             ctypes.c_double, dp]
+    lib.fdo_create.restype = ctypes.c_void_p
+    lib.fdo_create.argtypes = [P(FdoParams)]
+    lib.fdo_destroy.argtypes = [ctypes.c_void_p]
+    lib.fdo_set.argtypes = [ctypes.c_void_p, dp, dp, dp]
+    lib.fdo_get.argtypes = [ctypes.c_void_p, dp, dp, dp]
+    lib.fdo_step.argtypes = [ctypes.c_void_p, ctypes.c_double, ctypes.c_int64]
     _lib = lib
     return lib
 
@@ -187,4 +203,46 @@ class Oracle:
     def reduce(self, centre=(0.0, 0.0, 0.0)):
         out = np.zeros(R_COUNT)
         self._lib.orc_reduce(self._h, _dptr(_f64(centre)), _dptr(out))
+        return out
+
+
+class FDOracle:
+    """The independent finite-difference discretisation (fd_oracle.c) of the
+    same PDEs, explicit Euler with time step dt.  All walls carry zero flux
+    (mirror and no-flux walls coincide for this discretisation)."""
+
+    def __init__(self, nx, ny, nz, dx=1.0, W0=1.0, tau0=1.0, lam=3.2, Mcinf=1.0, k=0.15,
+                 D=2.0, kappa=20.0, aniso=ANISO_CUBIC, eps=0.05, delta=0.0, **_ignored):
+        lib = _load()
+        p = FdoParams()
+        p.nx, p.ny, p.nz = int(nx), int(ny), int(nz)
+        p.dx, p.W0, p.tau0, p.lam, p.Mcinf, p.k = dx, W0, tau0, lam, Mcinf, k
+        p.D, p.kappa, p.aniso, p.eps, p.delta = D, kappa, int(aniso), eps, delta
+        self.shape = (int(nz), int(ny), int(nx))
+        self._h = lib.fdo_create(ctypes.byref(p))
+        if not self._h:
+            raise ValueError("finite-difference oracle rejected the parameters")
+        self._lib = lib
+
+    def close(self):
+        if self._h:
+            self._lib.fdo_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set(self, phi, U, theta):
+        a = [_f64(v).reshape(self.shape) for v in (phi, U, theta)]
+        self._lib.fdo_set(self._h, _dptr(a[0]), _dptr(a[1]), _dptr(a[2]))
+
+    def step(self, dt, n=1):
+        self._lib.fdo_step(self._h, float(dt), int(n))
+
+    def fields(self):
+        out = [np.zeros(self.shape) for _ in range(3)]
+        self._lib.fdo_get(self._h, _dptr(out[0]), _dptr(out[1]), _dptr(out[2]))
         return out

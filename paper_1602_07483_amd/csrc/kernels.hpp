@@ -659,7 +659,9 @@ __device__ __forceinline__ void phi_body(const Coef<T>& c, int block, const S* _
 //   incT_i = w_i (theta_y + (phi^{n+1}_y - phi^n_y)/2 - theta_x) + (1 - omega_theta) df_j(y),
 // then U^{n+1} = U_x + dU, theta^{n+1} = theta_x + dT and the new deviations
 //   dh_i = incU_i - A_i dU + B_i [(r^o_x - r_x) U_x - r_x dU],  df_i = incT_i - w_i dT.
-// LDS terms: a = (P, C, S, theta + dphi/2), b = (K, r).
+// For i > 0 the pull needs only Z = P + C + S, theta + dphi/2 and K of the
+// source, so the halo terms in LDS are (Z, theta + dphi/2, Kx, Ky) and Kz;
+// the tile's own (P, C, S, r) sit in a separate two-plane array.
 // ==========================================================================
 template <class L, class T, class S, int TX, int TY, bool BUF>
 __device__ __forceinline__ void ut_body(const Coef<T>& c, int block, const S* __restrict__ hin,
@@ -671,8 +673,9 @@ __device__ __forceinline__ void ut_body(const Coef<T>& c, int block, const S* __
     using G = Tile<TX, TY>;
     using M = March<TX, TY>;
     __shared__ V2<T> sphi[3][G::PN];      // (phi^{n+1}, 1/zeta)
-    __shared__ V4<T> sta[3][G::HN];       // node terms, first 4-vector
-    __shared__ V4<T> stb[3][G::HN];       // node terms, second 4-vector
+    __shared__ V4<T> sta[3][G::HN];       // (Z, theta + dphi/2, Kx, Ky) with halo
+    __shared__ T stk[3][G::HN];           // Kz with halo
+    __shared__ V4<T> sown[2][G::NT];      // (P, C, S, r) of the tile's own nodes
 
     G tile(c, block);
     const int nx = c.nx, ny = c.ny, nz = c.nz;
@@ -762,7 +765,8 @@ __device__ __forceinline__ void ut_body(const Coef<T>& c, int block, const S* __
             const V2<T>* f0 = sphi[(pz + 3) % 3];
             const V2<T>* fp = sphi[(pz + 4) % 3];
             V4<T>* sa = sta[(pz + 3) % 3];
-            V4<T>* sb = stb[(pz + 3) % 3];
+            T* sk = stk[(pz + 3) % 3];
+            V4<T>* so = sown[pz & 1];
 #pragma unroll
             for (int kk = 0; kk < M::NB; ++kk) {
                 const int t = (int)threadIdx.x + kk * G::NT;
@@ -814,8 +818,11 @@ __device__ __forceinline__ void ut_body(const Coef<T>& c, int block, const S* __
                 const T Sflux = Du * div + jx * Fx + jy * Fy + jz * Fz;
                 const T src = Sflux + cu * T(0.5) * dtphi * w0;
                 const T ro = r_of(po, zA, zB);
-                sa[t] = V4<T>{ro * u, c.omU * (r0 - ro) * u, src * c.dt, th + T(0.5) * dphi};
-                sb[t] = V4<T>{c.jcoef * Jx, c.jcoef * Jy, c.jcoef * Jz, r0};
+                const T P = ro * u, C = c.omU * (r0 - ro) * u, Ssrc = src * c.dt;
+                sa[t] = V4<T>{P + C + Ssrc, th + T(0.5) * dphi, c.jcoef * Jx, c.jcoef * Jy};
+                sk[t] = c.jcoef * Jz;
+                if (lx >= 1 && lx <= TX && ly >= 1 && ly <= TY)
+                    so[(ly - 1) * TX + (lx - 1)] = V4<T>{P, C, Ssrc, r0};
             }
         }
         __syncthreads();
@@ -823,7 +830,8 @@ __device__ __forceinline__ void ut_body(const Coef<T>& c, int block, const S* __
             const int z = zz - 2;
             const unsigned xi = (unsigned)z * plane + (unsigned)tile.y * nx + tile.x;
             const int sl[3] = {(z + 2) % 3, (z + 3) % 3, (z + 4) % 3};
-            const T Px = sta[sl[1]][tile.lt].x, Cx = sta[sl[1]][tile.lt].y, rx = stb[sl[1]][tile.lt].w;
+            const V4<T> own = sown[z & 1][threadIdx.x];
+            const T Px = own.x, Cx = own.y, Sx = own.z, rx = own.w;
             const T Ux = pUx, thx = pthx;
             Faces f = tile.f;
             f.zl = z == 0;
@@ -837,13 +845,17 @@ __device__ __forceinline__ void ut_body(const Coef<T>& c, int block, const S* __
                 constexpr bool EDGE = decltype(edge_c)::value;
                 constexpr int ex = L::ex(I), ey = L::ey(I), ez = L::ez(I);
                 constexpr T wi = T(L::w(I));
-                constexpr T Bi = (I == 0) ? T(L::w(0)) - T(1) : wi;
                 const int tl = tile.lt - ex - ey * G::HX;
-                const V4<T> ta = sta[sl[1 - ez]][tl], tb = stb[sl[1 - ez]][tl];
-                const T eK = T(ex) * tb.x + T(ey) * tb.y + T(ez) * tb.z;
-                T vu = Bi * ta.y + omU1 * (T)Raw<S>::dec(ph_[I]) + wi * (ta.z + eK);
-                if constexpr (I != 0) vu += wi * (ta.x - Px);
-                T vt = wi * (ta.w - thx) + omT1 * (T)Raw<S>::dec(pf_[I]);
+                const V4<T> ta = sta[sl[1 - ez]][tl];
+                T vu, vt;
+                if constexpr (I == 0) {
+                    vu = (wi - T(1)) * Cx + wi * Sx + omU1 * (T)Raw<S>::dec(ph_[I]);
+                } else {
+                    T eK = T(ex) * ta.z + T(ey) * ta.w;
+                    if constexpr (ez != 0) eK += T(ez) * stk[sl[1 - ez]][tl];
+                    vu = wi * (ta.x - Px + eK) + omU1 * (T)Raw<S>::dec(ph_[I]);
+                }
+                vt = wi * (ta.y - thx) + omT1 * (T)Raw<S>::dec(pf_[I]);
                 if constexpr (EDGE) {
                     const bool cr = crosses<L, I>(f);
                     vu = cr ? T(0) : vu;
@@ -858,13 +870,13 @@ __device__ __forceinline__ void ut_body(const Coef<T>& c, int block, const S* __
                 const T dh = (T)Codec<S>::dec(hin[(size_t)s.j * np + si]);
                 const T df = (T)Codec<S>::dec(fin[(size_t)s.j * np + si]);
                 const int tsl = (s.sz + 3) % 3, tl = (s.sy - tile.y0 + 1) * G::HX + (s.sx - tile.x0 + 1);
-                const V4<T> ta = sta[tsl][tl], tb = stb[tsl][tl];
+                const V4<T> ta = sta[tsl][tl];
                 const T wi = T(L::w(i));
-                const T eK = T(s.fx * L::ex(i)) * tb.x + T(s.fy * L::ey(i)) * tb.y +
-                             T(s.fz * L::ez(i)) * tb.z;
+                const T eK = T(s.fx * L::ex(i)) * ta.z + T(s.fy * L::ey(i)) * ta.w +
+                             T(s.fz * L::ez(i)) * stk[tsl][tl];
                 // i > 0 here: A_i = 0, B_i = w_i
-                vu = wi * ta.y + omU1 * dh + wi * (ta.z + eK) + wi * (ta.x - Px);
-                vt = wi * (ta.w - thx) + omT1 * df;
+                vu = wi * (ta.x - Px + eK) + omU1 * dh;
+                vt = wi * (ta.y - thx) + omT1 * df;
             };
             const bool on_face = f.xl || f.xh || f.yl || f.yh || f.zl || f.zh;
             if (!edge) {

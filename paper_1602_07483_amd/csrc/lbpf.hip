@@ -227,7 +227,8 @@ lbpf_status launch_step_t(lbpf_ctx* ctx) {
 // Static LDS of one block of k_ut, the larger of the two step kernels.
 template <class T, int TX, int TY>
 constexpr size_t lds_bytes() {
-    return 3 * (size_t)(TX + 4) * (TY + 4) * 2 * sizeof(T) + 3 * (size_t)(TX + 2) * (TY + 2) * 8 * sizeof(T);
+    return 3 * (size_t)(TX + 4) * (TY + 4) * 2 * sizeof(T) + 3 * (size_t)(TX + 2) * (TY + 2) * 5 * sizeof(T) +
+           2 * (size_t)TX * TY * 4 * sizeof(T);
 }
 
 template <class T>

@@ -9,6 +9,10 @@ phi range) every ``reduce_every`` steps of one workload.
 thermal2d  -- the 2D thermal dendrite of Sec. 4.1 (37 500 steps, T = 300)
 octant128  -- 128^3 octant dendrite, Delta = 0.55, 5000 steps
 centred256 -- 256^3 centred seed through its octant (128^3), 10 000 steps
+fd2d, fd3d -- the LB oracle and the finite-difference discretisation of the
+              same PDEs side by side (dx/W0 = 0.4, dt/tau0 = 0.02 for LB and
+              0.01 for FD): a 200^2 quadrant slab over 4000 steps and a 64^3
+              octant over 1500 steps; tip positions every 200 / 100 steps
 """
 import json
 import os
@@ -18,12 +22,70 @@ import time
 HERE = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
 
+import numpy as np  # noqa: E402
+
 import oracle  # noqa: E402
 from paper_1602_07483_amd import inputs  # noqa: E402
 
 KEYS = (("solid_fraction", oracle.R_SOLID), ("solute_mass", oracle.R_MASS),
         ("enthalpy", oracle.R_ENTHALPY), ("phi_min", oracle.R_PHIMIN),
         ("phi_max", oracle.R_PHIMAX), ("nonfinite", oracle.R_NONFINITE))
+
+def fd_problem(n, nz):
+    """Alloy + heat dendrite at the resolution of the paper's alloy benchmark
+    (Sec. 4.2: dx/W0 = 0.4, dt/tau0 = 0.02, D = 2, k = 0.15, eps = 0.03,
+    lambda = 3.2, U0 = -0.55), with theta0 = -0.55 and kappa = D; seed of
+    radius 10 dx at the mirror corner."""
+    walls = (inputs.SYMMETRY, inputs.NOFLUX, inputs.SYMMETRY, inputs.NOFLUX,
+             inputs.SYMMETRY, inputs.SYMMETRY if nz == 1 else inputs.NOFLUX)
+    cz = 0.0 if nz == 1 else -0.5
+    return inputs.Problem("fd-%dx%d" % (n, nz), n, n, nz, 19, walls, dx=0.4, dt=0.02, W0=1.0,
+                          tau0=1.0, lam=3.2, Mcinf=1.0, k=0.15, D=2.0, kappa=2.0, eps=0.03,
+                          centres=[(-0.5, -0.5, cz)], radius=10.0, U0=-0.55, theta0=-0.55)
+
+
+def tip_along_x(phi, cx):
+    """Largest phi = 0 crossing along +x (linear interpolation), minus cx."""
+    a, b = phi[..., :-1], phi[..., 1:]
+    m = (a > 0) & (b <= 0)
+    if not m.any():
+        return float("nan")
+    x = np.arange(phi.shape[-1] - 1, dtype=np.float64)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        xs = np.where(m, x + a / np.where(m, a - b, 1.0), -np.inf)
+    return float(xs.max()) - cx
+
+
+def fd_trace(pb, steps, every, log=print):
+    """Tip positions of the LB oracle and of the FD discretisation (two FD
+    steps of dt/2 per LB step) from the same initial fields."""
+    f0 = pb.initial_fields()
+    o = oracle.Oracle(pb.nx, pb.ny, pb.nz, **pb.model_kwargs())
+    o.init(*f0)
+    fd = oracle.FDOracle(pb.nx, pb.ny, pb.nz, **pb.model_kwargs())
+    fd.set(*f0)
+    out = []
+    t0 = time.time()
+    done = 0
+    while done < steps:
+        o.step(every)
+        fd.step(pb.dt / 2.0, 2 * every)
+        done += every
+        lp, fp = o.fields()[0], fd.fields()[0]
+        rec = {"step": done, "lb_tip": tip_along_x(lp, pb.centres[0][0]),
+               "fd_tip": tip_along_x(fp, pb.centres[0][0]),
+               "lb_solid": float(np.mean(0.5 * (1 + lp))), "fd_solid": float(np.mean(0.5 * (1 + fp)))}
+        out.append(rec)
+        log("%s step %d LB tip %.3f FD tip %.3f %.1fs" % (pb.name, done, rec["lb_tip"], rec["fd_tip"],
+                                                         time.time() - t0))
+        sys.stdout.flush()
+    o.close()
+    fd.close()
+    return out
+
+
+FD_CASES = {"fd2d": (lambda: fd_problem(200, 1), 4000, 200),
+            "fd3d": (lambda: fd_problem(64, 64), 1500, 100)}
 
 WORKLOADS = {
     "thermal2d": lambda: inputs.workload_thermal2d(),
@@ -54,7 +116,18 @@ def trace(pb, log=print):
 
 
 def main(names):
-    for name in names or list(WORKLOADS):
+    for name in names or list(WORKLOADS) + list(FD_CASES):
+        if name in FD_CASES:
+            factory, steps, every = FD_CASES[name]
+            pb = factory()
+            rec = {"workload": pb.name, "problem": {k: v for k, v in pb.__dict__.items()},
+                   "lb_dt": pb.dt, "fd_dt": pb.dt / 2.0, "every": every,
+                   "oracle_threads": oracle.num_threads(), "trace": fd_trace(pb, steps, every)}
+            path = os.path.join(HERE, "trace_%s.json" % name)
+            with open(path, "w") as fh:
+                json.dump(rec, fh, indent=0)
+            print("wrote", path)
+            continue
         pb = WORKLOADS[name]()
         rec = {"workload": pb.name, "problem": {k: v for k, v in pb.__dict__.items()},
                "oracle_threads": oracle.num_threads(), "trace": trace(pb)}

@@ -156,6 +156,38 @@ def run_ensemble(steps, seq_steps, storage="f16", graph_steps=50):
             "max_abs_phi_eps_le_1_15": peak}
 
 
+def run_multiseed(steps, storage="f16"):
+    """512^3 eight-nucleus domains in mixed storage (64-bit-addressed kernels,
+    every field's populations exceed 4 GiB), cubic and K41/K61 anisotropy:
+    throughput and FP64 solute-mass drift over the timed steps."""
+    import torch
+    from paper_1602_07483_amd import lbpf
+    from paper_1602_07483_amd.inputs import workload_multiseed
+
+    out = {}
+    stream = torch.cuda.current_stream().cuda_stream
+    for aniso, label in ((0, "cubic eps=0.05"), (1, "K41/K61 eps=0 delta=-0.02")):
+        pb = workload_multiseed(512, aniso=aniso)
+        pb.reduce_every = 0
+        s = lbpf.solver_for(pb, storage=storage, stream=stream)
+        s.set_fields(*pb.initial_fields())
+        s.step(10)
+        _, r0 = s.read_status()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s.step(steps)
+        s.sync()
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        st, r1 = s.read_status()
+        s.close()
+        out[label] = {"mlups": float(pb.nodes) * steps / dt / 1e6, "steps": steps,
+                      "mass_drift": (r1["solute_mass"] - r0["solute_mass"]) / abs(r0["solute_mass"]),
+                      "solid_fraction": r1["solid_fraction"], "status": st}
+    return {"workload": "512^3 D3Q19, 8 nuclei R=6 (separation >= 64), Delta=0.55, k=0.15, no-flux",
+            "storage": storage, "runs": out}
+
+
 def copy_bandwidth(nbytes=2 << 30, reps=20):
     import torch
     from paper_1602_07483_amd import lbpf
@@ -205,6 +237,8 @@ def main():
     ap.add_argument("--launch", default=None,
                     help="tile_x,tile_y,zslab,xcd_remap instead of the library default")
     ap.add_argument("--no-ensemble", action="store_true", help="skip the batched-ensemble leg")
+    ap.add_argument("--no-multiseed", action="store_true", help="skip the 512^3 multi-seed leg")
+    ap.add_argument("--multiseed-steps", type=int, default=200)
     ap.add_argument("--ensemble-steps", type=int, default=2000)
     ap.add_argument("--autotune", action="store_true",
                     help="let the library's autotuner pick the launch before timing")
@@ -228,6 +262,9 @@ def main():
                             "speedup_vs_f32": r["mlups"] / res["mlups"],
                             "kernels": r["kernels"]}
     copy_gbs = copy_bandwidth()
+    multiseed = None
+    if not args.no_multiseed:
+        multiseed = run_multiseed(args.multiseed_steps)
     ensemble = None
     if not args.no_ensemble:
         ensemble = run_ensemble(args.ensemble_steps, max(args.ensemble_steps // 4, 1))
@@ -259,6 +296,7 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "ensemble": ensemble,
+        "multiseed": multiseed,
         "health": {"solid_fraction": res["solid_fraction"], "phi_range": res["phi_range"]},
     }
     if rank == 0:

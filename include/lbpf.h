@@ -199,7 +199,7 @@ lbpf_status lbpf_kernel_times(lbpf_ctx* ctx, double ms[3], int64_t launches[3]);
  * then share that XCD's L2), 0 keeps the hardware's round-robin order.
  * Supported tiles: 64x2, 64x4, 32x4, 32x8, 32x16 (FP64 storage: 64x2 and
  * 32x4); zslab >= 1.  The shape changes speed only, never results.
- * Default: 32x8 (FP64: 32x4), zslab 4, remap 1.
+ * Default: 32x8 (FP64: 32x4), zslab 4 (8 for 16-bit storage), remap 1.
  * Errors: EINVAL (unsupported shape or flag). */
 lbpf_status lbpf_set_launch(lbpf_ctx* ctx, int32_t tile_x, int32_t tile_y, int32_t zslab,
                             int32_t xcd_remap);

@@ -234,32 +234,6 @@ __device__ __forceinline__ Src source(int x, int y, int z, int nx, int ny, int n
     return s;
 }
 
-// Runtime-direction version of source(), for the few links that cross a wall.
-template <class L>
-__device__ __noinline__ Src source_rt(int i, int x, int y, int z, int nx, int ny, int nz, int symm) {
-    const int ex = L::ex(i), ey = L::ey(i), ez = L::ez(i);
-    Src s{x - ex, y - ey, z - ez, i, 1, 1, 1};
-    int mask = 0;
-    bool nf = false;
-    if (s.sx < 0) { mask |= 1; nf |= !(symm & 1); }
-    else if (s.sx >= nx) { mask |= 1; nf |= !(symm & 2); }
-    if (s.sy < 0) { mask |= 2; nf |= !(symm & 4); }
-    else if (s.sy >= ny) { mask |= 2; nf |= !(symm & 8); }
-    if (s.sz < 0) { mask |= 4; nf |= !(symm & 16); }
-    else if (s.sz >= nz) { mask |= 4; nf |= !(symm & 32); }
-    if (mask) {
-        if (nf) {
-            s.sx = x; s.sy = y; s.sz = z; s.fx = -1; s.fy = -1; s.fz = -1;
-        } else {
-            if (mask & 1) { s.sx = x; s.fx = -1; }
-            if (mask & 2) { s.sy = y; s.fy = -1; }
-            if (mask & 4) { s.sz = z; s.fz = -1; }
-        }
-        s.j = find_dir<L>(s.fx * ex, s.fy * ey, s.fz * ez);
-    }
-    return s;
-}
-
 // Does the incoming link I of a node with the given face flags cross a wall?
 struct Faces {
     bool xl, xh, yl, yh, zl, zh;   // node lies on the -x, +x, -y, +y, -z, +z face
@@ -277,18 +251,20 @@ __device__ __forceinline__ bool crosses(const Faces& f) {
     return c;
 }
 
-template <class L>
-__device__ __forceinline__ bool crosses_rt(int i, const Faces& f) {
-    const int ex = L::ex(i), ey = L::ey(i), ez = L::ez(i);
-    return (ex > 0 && f.xl) || (ex < 0 && f.xh) || (ey > 0 && f.yl) || (ey < 0 && f.yh) ||
-           (ez > 0 && f.zl) || (ez < 0 && f.zh);
-}
-
 // A value the compiler must treat as changed here: keeps per-direction base
 // pointers from being hoisted into (and spilled from) scalar registers.
 template <class V>
 __device__ __forceinline__ V opaque(V v) {
     asm volatile("" : "+s"(v));
+    return v;
+}
+
+// Per-lane counterpart of opaque(): keeps loop-invariant per-lane work (the
+// wall sources of the edge links) inside the branch that needs it instead of
+// hoisted out of the z-march and spilled.
+template <class V>
+__device__ __forceinline__ V opaque_v(V v) {
+    asm volatile("" : "+v"(v));
     return v;
 }
 
@@ -582,7 +558,21 @@ __device__ __forceinline__ void phi_body(const Coef<T>& c, int block, const S* _
             T inc[L::Q];
             T dsum = T(0);
             // Every link as if its source x - e_i were inside the domain; on
-            // edge tiles, links that cross a wall contribute zero here.
+            // edge tiles, a link that crosses a wall takes its source after
+            // bounce-back or reflection instead (only the lanes it concerns).
+            auto wall_link = [&](auto ic) -> T {
+                constexpr int I = decltype(ic)::value;
+                const Src s = source<L, I>(opaque_v(tile.x), opaque_v(tile.y), z, nx, ny, nz, c.symm);
+                const size_t si = ((size_t)s.sz * ny + s.sy) * nx + s.sx;
+                const T dj = (T)Codec<S>::dec(gin[(size_t)s.j * np + si]);
+                const T dnl = (T)Raw<S>::dec(pnl[I]);
+                const int tsl = (s.sz + 3) % 3, tl = (s.sy - tile.y0 + 1) * G::HX + (s.sx - tile.x0 + 1);
+                const V4<T> ta = sta[tsl][tl], tb = stb[tsl][tl];
+                const T eAV = T(s.fx * L::ex(I)) * tb.x + T(s.fy * L::ey(I)) * tb.y +
+                              T(s.fz * L::ez(I)) * tb.z;
+                return T(L::w(I)) * (ta.x * (ta.w - phx) + ta.z - eAV) + ta.y * dj -
+                       (ta.x - T(1)) * dnl;
+            };
             auto fast = [&](auto ic, auto edge_c) {
                 constexpr int I = decltype(ic)::value;
                 constexpr bool EDGE = decltype(edge_c)::value;
@@ -593,34 +583,17 @@ __device__ __forceinline__ void phi_body(const Coef<T>& c, int block, const S* _
                 const T eAV = T(ex) * tb.x + T(ey) * tb.y + T(ez) * tb.z;
                 T v = wi * (ta.x * (ta.w - phx) + ta.z - eAV) + ta.y * (T)Raw<S>::dec(pj[I]) -
                          (ta.x - T(1)) * (T)Raw<S>::dec(pnl[I]);
-                if constexpr (EDGE) v = crosses<L, I>(f) ? T(0) : v;
+                if constexpr (EDGE && I != 0) {
+                    if (crosses<L, I>(f)) v = wall_link(ic);
+                    __builtin_amdgcn_sched_barrier(0);   // one wall link at a time
+                }
                 inc[I] = v;
                 dsum += v;
             };
-            // Links that cross a wall: source after bounce-back or reflection.
-            auto wall_link = [&](int i) -> T {
-                const Src s = source_rt<L>(i, tile.x, tile.y, z, nx, ny, nz, c.symm);
-                const size_t si = ((size_t)s.sz * ny + s.sy) * nx + s.sx;
-                const T dj = (T)Codec<S>::dec(gin[(size_t)s.j * np + si]);
-                const T dnl = (T)Codec<S>::dec(gin[(size_t)i * np + xi]);
-                const int tsl = (s.sz + 3) % 3, tl = (s.sy - tile.y0 + 1) * G::HX + (s.sx - tile.x0 + 1);
-                const V4<T> ta = sta[tsl][tl], tb = stb[tsl][tl];
-                const T eAV = T(s.fx * L::ex(i)) * tb.x + T(s.fy * L::ey(i)) * tb.y +
-                              T(s.fz * L::ez(i)) * tb.z;
-                return T(L::w(i)) * (ta.x * (ta.w - phx) + ta.z - eAV) + ta.y * dj -
-                       (ta.x - T(1)) * dnl;
-            };
-            const bool on_face = f.xl || f.xh || f.yl || f.yh || f.zl || f.zh;
-            if (!edge) {
+            if (!edge)
                 Unroll<0, L::Q>::run([&](auto ic) { fast(ic, std::false_type{}); });
-            } else {
+            else
                 Unroll<0, L::Q>::run([&](auto ic) { fast(ic, std::true_type{}); });
-                if (on_face) {
-#pragma unroll 1
-                    for (int i = 1; i < L::Q; ++i)
-                        if (crosses_rt<L>(i, f)) dsum += wall_link(i);
-                }
-            }
             phout[xi] = phx + dsum;
             Unroll<0, L::Q>::run([&](auto ic) {
                 constexpr int I = decltype(ic)::value;
@@ -631,13 +604,6 @@ __device__ __forceinline__ void phi_body(const Coef<T>& c, int block, const S* _
                 else
                     st_nt(&gout[(size_t)I * np + xi], v);
             });
-            if (edge && on_face) {
-                // overwrite the wall-crossing links (same thread, same address)
-#pragma unroll 1
-                for (int i = 1; i < L::Q; ++i)
-                    if (crosses_rt<L>(i, f))
-                        gout[(size_t)i * np + xi] = Codec<S>::enc(wall_link(i) - T(L::w(i)) * dsum);
-            }
         }
         if (zz + 1 <= tile.ze + 1) prefetch(zz + 1);
     }
@@ -840,6 +806,22 @@ __device__ __forceinline__ void ut_body(const Coef<T>& c, int block, const S* __
             const size_t np = (size_t)opaque(c.np);
             T iu[L::Q], it[L::Q];
             T du = T(0), dth = T(0);
+            // A link that crosses a wall: source after bounce-back or reflection.
+            auto wall_link = [&](auto ic, T& vu, T& vt) {
+                constexpr int I = decltype(ic)::value;
+                const Src s = source<L, I>(opaque_v(tile.x), opaque_v(tile.y), z, nx, ny, nz, c.symm);
+                const size_t si = ((size_t)s.sz * ny + s.sy) * nx + s.sx;
+                const T dh = (T)Codec<S>::dec(hin[(size_t)s.j * np + si]);
+                const T df = (T)Codec<S>::dec(fin[(size_t)s.j * np + si]);
+                const int tsl = (s.sz + 3) % 3, tl = (s.sy - tile.y0 + 1) * G::HX + (s.sx - tile.x0 + 1);
+                const V4<T> ta = sta[tsl][tl];
+                constexpr T wi = T(L::w(I));
+                const T eK = T(s.fx * L::ex(I)) * ta.z + T(s.fy * L::ey(I)) * ta.w +
+                             T(s.fz * L::ez(I)) * stk[tsl][tl];
+                // I > 0 here: A_I = 0, B_I = w_I
+                vu = wi * (ta.x - Px + eK) + omU1 * dh;
+                vt = wi * (ta.y - thx) + omT1 * df;
+            };
             auto fast = [&](auto ic, auto edge_c) {
                 constexpr int I = decltype(ic)::value;
                 constexpr bool EDGE = decltype(edge_c)::value;
@@ -856,44 +838,17 @@ __device__ __forceinline__ void ut_body(const Coef<T>& c, int block, const S* __
                     vu = wi * (ta.x - Px + eK) + omU1 * (T)Raw<S>::dec(ph_[I]);
                 }
                 vt = wi * (ta.y - thx) + omT1 * (T)Raw<S>::dec(pf_[I]);
-                if constexpr (EDGE) {
-                    const bool cr = crosses<L, I>(f);
-                    vu = cr ? T(0) : vu;
-                    vt = cr ? T(0) : vt;
+                if constexpr (EDGE && I != 0) {
+                    if (crosses<L, I>(f)) wall_link(ic, vu, vt);
+                    __builtin_amdgcn_sched_barrier(0);   // one wall link at a time
                 }
                 iu[I] = vu; it[I] = vt;
                 du += vu; dth += vt;
             };
-            auto wall_link = [&](int i, T& vu, T& vt) {
-                const Src s = source_rt<L>(i, tile.x, tile.y, z, nx, ny, nz, c.symm);
-                const size_t si = ((size_t)s.sz * ny + s.sy) * nx + s.sx;
-                const T dh = (T)Codec<S>::dec(hin[(size_t)s.j * np + si]);
-                const T df = (T)Codec<S>::dec(fin[(size_t)s.j * np + si]);
-                const int tsl = (s.sz + 3) % 3, tl = (s.sy - tile.y0 + 1) * G::HX + (s.sx - tile.x0 + 1);
-                const V4<T> ta = sta[tsl][tl];
-                const T wi = T(L::w(i));
-                const T eK = T(s.fx * L::ex(i)) * ta.z + T(s.fy * L::ey(i)) * ta.w +
-                             T(s.fz * L::ez(i)) * stk[tsl][tl];
-                // i > 0 here: A_i = 0, B_i = w_i
-                vu = wi * (ta.x - Px + eK) + omU1 * dh;
-                vt = wi * (ta.y - thx) + omT1 * df;
-            };
-            const bool on_face = f.xl || f.xh || f.yl || f.yh || f.zl || f.zh;
-            if (!edge) {
+            if (!edge)
                 Unroll<0, L::Q>::run([&](auto ic) { fast(ic, std::false_type{}); });
-            } else {
+            else
                 Unroll<0, L::Q>::run([&](auto ic) { fast(ic, std::true_type{}); });
-                if (on_face) {
-#pragma unroll 1
-                    for (int i = 1; i < L::Q; ++i)
-                        if (crosses_rt<L>(i, f)) {
-                            T vu, vt;
-                            wall_link(i, vu, vt);
-                            du += vu;
-                            dth += vt;
-                        }
-                }
-            }
             Uout[xi] = Ux + du;
             thout[xi] = thx + dth;
             // (r^o_x - r_x) U_x - r_x dU, with (r^o_x - r_x) U_x = -C_x / omega_U
@@ -913,17 +868,6 @@ __device__ __forceinline__ void ut_body(const Coef<T>& c, int block, const S* __
                     st_nt(&fout[(size_t)I * np + xi], fv);
                 }
             });
-            if (edge && on_face) {
-#pragma unroll 1
-                for (int i = 1; i < L::Q; ++i)
-                    if (crosses_rt<L>(i, f)) {
-                        T vu, vt;
-                        wall_link(i, vu, vt);
-                        const T wi = T(L::w(i));
-                        hout[(size_t)i * np + xi] = Codec<S>::enc(vu + wi * hb);
-                        fout[(size_t)i * np + xi] = Codec<S>::enc(vt - wi * dth);
-                    }
-            }
         }
         if (zz + 1 <= tile.ze + 1) prefetch(zz + 1);
     }

@@ -477,7 +477,7 @@ lbpf_status lbpf_create(const lbpf_grid* grid, const lbpf_params* params, void* 
     ctx->sbytes = (size_t)lbpf_storage_bytes(g.storage);
     ctx->tbytes = g.storage == LBPF_F64 ? 8 : 4;
     ctx->shape = g.storage == LBPF_F64 ? 2 : 3;
-    ctx->zslab = 4;
+    ctx->zslab = ctx->sbytes == 2 ? 8 : 4;   // measured best at 256^3 and 512^3
     ctx->n = (size_t)g.nx * g.ny * g.nz;
     ctx->np = (ctx->n + 63) / 64 * 64;
     hipError_t e = hipSuccess;

@@ -13,7 +13,7 @@
  *                            eq. (Feq_Transport), relaxation eq. (RelaxationTime_Concentration);
  *   temperature theta     -- Sec. 3.1, BGK scheme eq. (LBE_Eq_Temp) with
  *                            eqs. (EqFunction_Tempr), (Source_Tempr), (ThermalDiffusivity);
- * on the D3Q15 or D3Q19 lattice (Sec. 3.4, Tables 1 and 2), in the order of
+ * on the D3Q7, D3Q15 or D3Q19 lattice (Sec. 3.4, Tables 1 and 2), in the order of
  * Sec. 3.4 "Algorithm implementation": phi first, then U and theta with the
  * new phi; split collision (eq. Collision_Stage) and streaming
  * (eq. Deplacement_STD); bounce-back walls.
@@ -54,7 +54,8 @@ typedef enum {
     LBPF_ESTATE = -5      /* call out of order (e.g. step before set_fields) */
 } lbpf_status;
 
-typedef enum { LBPF_D3Q15 = 15, LBPF_D3Q19 = 19 } lbpf_lattice;
+/* D3Q7 (e^2 = 1/4), D3Q15 and D3Q19 (e^2 = 1/3): Sec. 3.4, Tables 1 and 2. */
+typedef enum { LBPF_D3Q7 = 7, LBPF_D3Q15 = 15, LBPF_D3Q19 = 19 } lbpf_lattice;
 
 /* Walls lie half a link outside the first/last node of each axis. */
 typedef enum {

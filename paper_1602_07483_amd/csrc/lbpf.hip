@@ -117,6 +117,7 @@ template <class T>
 Coef<T> make_coef(const lbpf_ctx* ctx) {
     const lbpf_params& p = ctx->prm;
     const lbpf_grid& g = ctx->grid;
+    const double kE2 = lattice_e2(ctx->q);
     Coef<T> c{};
     c.nx = g.nx; c.ny = g.ny; c.nz = g.nz;
     c.symm = 0;
@@ -274,7 +275,11 @@ lbpf_status launch_step_l(lbpf_ctx* ctx) {
 }
 
 lbpf_status launch_step(lbpf_ctx* ctx) {
-    return ctx->q == 15 ? launch_step_l<D3Q15>(ctx) : launch_step_l<D3Q19>(ctx);
+    switch (ctx->q) {
+        case 7: return launch_step_l<D3Q7>(ctx);
+        case 15: return launch_step_l<D3Q15>(ctx);
+        default: return launch_step_l<D3Q19>(ctx);
+    }
 }
 
 template <class L, class T, class S>
@@ -318,8 +323,11 @@ lbpf_status init_or_decode_l(lbpf_ctx* ctx, int what, int field, double* dout) {
 }
 
 lbpf_status init_or_decode(lbpf_ctx* ctx, int what, int field, double* dout) {
-    return ctx->q == 15 ? init_or_decode_l<D3Q15>(ctx, what, field, dout)
-                        : init_or_decode_l<D3Q19>(ctx, what, field, dout);
+    switch (ctx->q) {
+        case 7: return init_or_decode_l<D3Q7>(ctx, what, field, dout);
+        case 15: return init_or_decode_l<D3Q15>(ctx, what, field, dout);
+        default: return init_or_decode_l<D3Q19>(ctx, what, field, dout);
+    }
 }
 
 template <class L, class B>
@@ -442,8 +450,8 @@ lbpf_status lbpf_create(const lbpf_grid* grid, const lbpf_params* params, void* 
     const lbpf_params& p = *params;
     if (g.nx < 1 || g.ny < 1 || g.nz < 1) return fail(nullptr, LBPF_EINVAL, "grid size < 1");
     if ((double)g.nx * g.ny * g.nz > 2.0e9) return fail(nullptr, LBPF_EINVAL, "grid too large");
-    if (g.lattice != LBPF_D3Q15 && g.lattice != LBPF_D3Q19)
-        return fail(nullptr, LBPF_EINVAL, "lattice must be 15 or 19");
+    if (g.lattice != LBPF_D3Q7 && g.lattice != LBPF_D3Q15 && g.lattice != LBPF_D3Q19)
+        return fail(nullptr, LBPF_EINVAL, "lattice must be 7, 15 or 19");
     if (lbpf_storage_bytes(g.storage) == 0) return fail(nullptr, LBPF_EINVAL, "bad storage");
     for (int f = 0; f < 6; ++f)
         if (g.wall[f] != LBPF_WALL_NOFLUX && g.wall[f] != LBPF_WALL_SYMMETRY)
@@ -722,7 +730,9 @@ lbpf_status lbpf_debug_stream_only(lbpf_ctx* ctx, int64_t nsteps) {
     if (nsteps < 0) return fail(ctx, LBPF_EINVAL, "nsteps < 0");
     if (!ctx->have_fields) return fail(ctx, LBPF_ESTATE, "lbpf_set_fields has not been called");
     for (int64_t s = 0; s < nsteps; ++s) {
-        lbpf_status st = ctx->q == 15 ? stream_only_l<D3Q15>(ctx) : stream_only_l<D3Q19>(ctx);
+        lbpf_status st = ctx->q == 7    ? stream_only_l<D3Q7>(ctx)
+                         : ctx->q == 15 ? stream_only_l<D3Q15>(ctx)
+                                        : stream_only_l<D3Q19>(ctx);
         if (st) return st;
     }
     return LBPF_OK;
@@ -976,6 +986,9 @@ lbpf_status lbpf_batch_create(int32_t n, const lbpf_grid* grids, const lbpf_para
     for (int i = 1; i < n; ++i)
         if (grids[i].storage != grids[0].storage)
             return bfail(nullptr, LBPF_EINVAL, "all domains of a batch share one storage type");
+    for (int i = 0; i < n; ++i)
+        if (grids[i].lattice != LBPF_D3Q15 && grids[i].lattice != LBPF_D3Q19)
+            return bfail(nullptr, LBPF_EINVAL, "batched domains use D3Q15 or D3Q19");
     lbpf_batch* b = new (std::nothrow) lbpf_batch();
     if (!b) return bfail(nullptr, LBPF_ENOMEM, "host allocation failed");
     b->storage = grids[0].storage;

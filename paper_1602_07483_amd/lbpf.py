@@ -13,7 +13,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "liblbpf.so")
 
 LBPF_OK, LBPF_EINVAL, LBPF_ENOMEM, LBPF_EDEVICE, LBPF_EUNSTABLE, LBPF_ESTATE = 0, -1, -2, -3, -4, -5
-LBPF_D3Q15, LBPF_D3Q19 = 15, 19
+LBPF_D3Q7, LBPF_D3Q15, LBPF_D3Q19 = 7, 15, 19
 LBPF_WALL_NOFLUX, LBPF_WALL_SYMMETRY = 0, 1
 LBPF_F32, LBPF_F16_DEV, LBPF_BF16_DEV, LBPF_F64 = 0, 1, 2, 3
 LBPF_ANISO_CUBIC, LBPF_ANISO_K41K61 = 0, 1

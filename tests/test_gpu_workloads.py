@@ -44,6 +44,16 @@ def velocities(steps, tips, every):
     return np.diff(np.asarray(tips)) / float(every)
 
 
+def free_growth(tips, reach):
+    """Intervals whose tip stays below 90 % of the distance to the far wall.
+    Once the crystal touches the wall the outermost phi = 0 crossing jumps
+    between rows on field differences far below the tolerances, so the tip
+    velocity there says nothing about parity."""
+    t = np.asarray(tips)
+    inside = t < 0.9 * reach
+    return inside[:-1] & inside[1:]
+
+
 @pytest.mark.parametrize("storage,tol", [("f64", 1e-11), ("f32", 1e-5)])
 def test_quasi2d_slab_matches_oracle(storage, tol):
     """nz = 1 with mirror z-walls (the D2Q9 reduction of D3Q19): fields after
@@ -98,7 +108,7 @@ def test_octant128_tip_velocity_matches_oracle():
         assert abs(h["tip"][0] - r["tip"][0]) < 0.05
     vg = velocities(None, [h["tip"][0] for h in hist], pb.reduce_every)
     vo = velocities(None, [r["tip"][0] for r in g["trace"]], pb.reduce_every)
-    ok = np.abs(vo) > 1e-3
+    ok = free_growth([r["tip"][0] for r in g["trace"]], pb.nx) & (np.abs(vo) > 1e-3)
     rel = np.abs(vg[ok] - vo[ok]) / np.abs(vo[ok])
     print("octant128 tip velocity rel. error FP32: %.3e over %d intervals" % (rel.max(), ok.sum()))
     assert ok.sum() >= 5 and rel.max() < 0.01
@@ -117,7 +127,7 @@ def test_centred256_tip_velocity_matches_oracle(storage, bound):
     assert [h["step"] for h in hist] == [r["step"] for r in tr]
     vg = velocities(None, [h["tip"][0] for h in hist], pb.reduce_every)
     vo = velocities(None, [r["tip"][0] for r in tr], pb.reduce_every)
-    ok = np.abs(vo) > 1e-3
+    ok = free_growth([r["tip"][0] for r in tr], pb.nx // 2) & (np.abs(vo) > 1e-3)
     rel = np.abs(vg[ok] - vo[ok]) / np.abs(vo[ok])
     fs = max(abs(h["solid_fraction"] - r["solid_fraction"]) for h, r in zip(hist, tr))
     m0 = 8.0 * tr[0]["solute_mass"]
@@ -126,7 +136,8 @@ def test_centred256_tip_velocity_matches_oracle(storage, bound):
     print("centred256 %s: tip velocity rel. error %.3e over %d intervals; |d solid fraction| %.2e; "
           "mass drift GPU %.3e oracle %.3e" % (storage, rel.max(), ok.sum(), fs, drift_g, drift_o))
     assert ok.sum() >= 5 and rel.max() < bound
-    assert fs < (1e-5 if storage == "f32" else 1e-3)
+    # solid fraction over the whole run; mixed storage reported with loose bounds
+    assert fs < {"f32": 1e-5, "f16": 2e-3, "bf16": 1e-2}[storage]
 
 
 def test_ensemble_health_and_sampled_parity():
@@ -241,3 +252,40 @@ def test_multiseed512_enthalpy_conserved(storage, bound):
     print("multiseed512 %s: enthalpy drift per node %.3e; solid fraction %.6f -> %.6f"
           % (storage, drift, red0["solid_fraction"], hist[-1]["solid_fraction"]))
     assert drift <= bound
+
+
+def _first_crossing(prof):
+    i = np.nonzero((prof[:-1] > 0) & (prof[1:] <= 0))[0]
+    assert len(i), "no phi = 0 crossing"
+    i = i[0]
+    return i + prof[i] / (prof[i] - prof[i + 1])
+
+
+def test_grid_anisotropy_of_isotropic_growth():
+    """Sec. 4.1, isotropic case (eps = 0): a sphere of radius 8 grows for
+    10^4 steps at dx = W0, dt = 0.15 tau0, kappa dt/dx^2 = 0.105, lambda = 10
+    (pure substance), on a 150^3 octant (the 300^3 domain about its centre).
+    The grid anisotropy A_g = |R100 - R110| / (R100 + R110) is large on D3Q7
+    and small on D3Q15 and D3Q19, as the paper reports (3.1 %, 0.07 %,
+    0.12 %).  The paper does not print the undercooling, so Delta = 0.2 is
+    chosen here and the exact values are parity unpinned."""
+    from paper_1602_07483_amd.inputs import Problem, NOFLUX, SYMMETRY
+    n = 150
+    walls = (SYMMETRY, NOFLUX, SYMMETRY, NOFLUX, SYMMETRY, NOFLUX)
+    ag = {}
+    for lat in (7, 15, 19):
+        pb = Problem("isotropic", n, n, n, lat, walls, dx=1.0, dt=0.15, W0=1.0, tau0=1.0, lam=10.0,
+                     Mcinf=0.0, k=0.15, D=0.7, kappa=0.7, eps=0.0, centres=[(-0.5, -0.5, -0.5)],
+                     radius=8.0, U0=0.0, theta0=-0.2)
+        s = make_gpu(pb, "f32")
+        s.step(10000)
+        phi, _, _, red = s.read(check=False)
+        s.close()
+        assert red["nonfinite"] == 0 and max(-red["phi_min"], red["phi_max"]) < 1.01
+        r100 = _first_crossing(phi[0, 0, :]) + 0.5                      # from the mirror point
+        r110 = (_first_crossing(np.array([phi[0, i, i] for i in range(n)])) + 0.5) * np.sqrt(2.0)
+        assert 20.0 < r100 < 0.7 * n
+        ag[lat] = abs(r100 - r110) / (r100 + r110) * 100.0
+        print("D3Q%d: R100 %.3f R110 %.3f A_g %.3f %%" % (lat, r100, r110, ag[lat]))
+    assert ag[7] > 1.0
+    assert ag[15] < 0.5 and ag[19] < 0.5

@@ -68,7 +68,8 @@ def test_trace_start_reproduces(name, factory, steps):
     o.step(steps)
     r = o.reduce(pb.centre())
     for a, key in enumerate((oracle.R_TIPX, oracle.R_TIPY, oracle.R_TIPZ)):
-        assert abs(r[key] - rec["tip"][a]) < 1e-10
+        # no crossing along an axis (the slab's z) is NaN on both sides
+        assert np.isclose(r[key], rec["tip"][a], rtol=0, atol=1e-10, equal_nan=True)
     assert abs(r[oracle.R_SOLID] - rec["solid_fraction"]) < 1e-12
     assert abs(r[oracle.R_MASS] - rec["solute_mass"]) < 1e-10 * abs(rec["solute_mass"])
     assert abs(r[oracle.R_ENTHALPY] - rec["enthalpy"]) < 1e-9 * max(1.0, abs(rec["enthalpy"]))

@@ -26,6 +26,10 @@
  *  - The context owns all device memory.  It is created on the current HIP
  *    device and runs on the borrowed HIP stream given at creation; with NULL
  *    the context creates and owns a non-blocking stream of default priority.
+ *    A borrowed stream must belong to the HIP runtime this library is
+ *    linked against (the system ROCm); a package that bundles its own HIP
+ *    runtime has streams of its own that are not interchangeable, so pass
+ *    NULL (or that package's default stream, which is NULL) there.
  *    A context is not thread-safe; one context per stream.
  *  - Work is asynchronous on that stream except where a call says it
  *    synchronises.
@@ -164,6 +168,27 @@ lbpf_status lbpf_read(lbpf_ctx* ctx, double* phi, double* U, double* theta,
  * Synchronises the stream. */
 lbpf_status lbpf_history(lbpf_ctx* ctx, lbpf_reductions* out, int32_t max_records,
                          int32_t* count);
+
+/* Element types of device-resident field arrays. */
+typedef enum { LBPF_FIELD_F32 = 0, LBPF_FIELD_F64 = 1 } lbpf_field_type;
+
+/* As lbpf_set_fields, with phi, U and theta in device memory of the
+ * context's device ([nz][ny][nx], x fastest, element type dtype).  They are
+ * read on the context's stream (the caller orders their production before
+ * the call) and converted there to the context's field type (FP64 for the
+ * F64 storage, FP32 otherwise, round to nearest); the equilibrium
+ * populations follow as in lbpf_set_fields (Sec. 4 initial seed, equilibria
+ * of eqs. (Feq_Phase), (Feq_Transport), (EqFunction_Tempr)).  The caller keeps
+ * ownership.  Synchronises the stream before returning.  Errors: EINVAL
+ * (NULL array, dtype not 0/1), EDEVICE. */
+lbpf_status lbpf_set_fields_device(lbpf_ctx* ctx, const void* phi, const void* U, const void* theta,
+                                   int32_t dtype);
+/* Copy the current fields into device arrays of element type dtype (any of
+ * the three may be NULL).  Asynchronous on the context's stream: the arrays
+ * hold the values once the stream has reached this point (lbpf_sync).  No
+ * reductions and no health check.  Errors: EINVAL, ESTATE (no fields set),
+ * EDEVICE. */
+lbpf_status lbpf_read_fields_device(lbpf_ctx* ctx, void* phi, void* U, void* theta, int32_t dtype);
 
 /* Raw stored population bits of one field (0 = g/phi, 1 = h/U, 2 = f/theta),
  * layout [Q][nz][ny][nx], in the storage type.  Every storage type holds the

@@ -1141,6 +1141,13 @@ __global__ __launch_bounds__(256) void k_reduce_final(const double* __restrict__
     }
 }
 
+// Element-wise type conversion of a field (device-resident field I/O).
+template <class From, class To>
+__global__ __launch_bounds__(256) void k_convert(const From* __restrict__ in, To* __restrict__ out, size_t n) {
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) out[i] = (To)in[i];
+}
+
 // Plain 16-byte vector copy, four loads in flight per thread and streaming
 // hints: the practical bandwidth reference.
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));

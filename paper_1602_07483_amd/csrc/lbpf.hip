@@ -861,6 +861,58 @@ lbpf_status lbpf_autotune(lbpf_ctx* ctx, int32_t steps_per_candidate, double* be
     return LBPF_OK;
 }
 
+// Device-resident field I/O: convert between the caller's FP32/FP64 arrays
+// and the context's field type on the context's stream.
+lbpf_status convert_field(lbpf_ctx* ctx, const void* in, int32_t in_f64, void* out, int32_t out_f64) {
+    const size_t n = ctx->n;
+    if (in_f64 == out_f64) {
+        CHK(hipMemcpyAsync(out, in, n * (in_f64 ? 8 : 4), hipMemcpyDeviceToDevice, ctx->stream));
+        return LBPF_OK;
+    }
+    const int nb = (int)std::min<size_t>(8192, (n + 255) / 256);
+    if (in_f64)
+        hipLaunchKernelGGL((k_convert<double, float>), dim3(nb), dim3(256), 0, ctx->stream, (const double*)in,
+                           (float*)out, n);
+    else
+        hipLaunchKernelGGL((k_convert<float, double>), dim3(nb), dim3(256), 0, ctx->stream, (const float*)in,
+                           (double*)out, n);
+    CHK(hipGetLastError());
+    return LBPF_OK;
+}
+
+lbpf_status lbpf_set_fields_device(lbpf_ctx* ctx, const void* phi, const void* U, const void* theta,
+                                   int32_t dtype) {
+    if (!ctx) return LBPF_EINVAL;
+    if (!phi || !U || !theta) return fail(ctx, LBPF_EINVAL, "NULL field array");
+    if (dtype != LBPF_FIELD_F32 && dtype != LBPF_FIELD_F64) return fail(ctx, LBPF_EINVAL, "dtype must be 0 or 1");
+    ctx->cur = 0;
+    const void* src[3] = {phi, U, theta};
+    for (int f = 0; f < 3; ++f) {
+        lbpf_status st = convert_field(ctx, src[f], dtype == LBPF_FIELD_F64, ctx->fld[f][0], ctx->tbytes == 8);
+        if (st) return st;
+    }
+    lbpf_status st = init_or_decode(ctx, 0, 0, nullptr);
+    if (st) return st;
+    CHK(hipStreamSynchronize(ctx->stream));
+    ctx->have_fields = true;
+    ctx->step = 0;
+    ctx->hist_count = 0;
+    return LBPF_OK;
+}
+
+lbpf_status lbpf_read_fields_device(lbpf_ctx* ctx, void* phi, void* U, void* theta, int32_t dtype) {
+    if (!ctx) return LBPF_EINVAL;
+    if (!ctx->have_fields) return fail(ctx, LBPF_ESTATE, "lbpf_set_fields has not been called");
+    if (dtype != LBPF_FIELD_F32 && dtype != LBPF_FIELD_F64) return fail(ctx, LBPF_EINVAL, "dtype must be 0 or 1");
+    void* dst[3] = {phi, U, theta};
+    for (int f = 0; f < 3; ++f) {
+        if (!dst[f]) continue;
+        lbpf_status st = convert_field(ctx, ctx->fld[f][ctx->cur], ctx->tbytes == 8, dst[f], dtype == LBPF_FIELD_F64);
+        if (st) return st;
+    }
+    return LBPF_OK;
+}
+
 lbpf_status lbpf_bench_copy(void* dst, const void* src, int64_t nbytes, void* hip_stream) {
     if (!dst || !src || nbytes < 0 || (nbytes % 16) != 0 || ((uintptr_t)dst % 16) || ((uintptr_t)src % 16))
         return LBPF_EINVAL;
@@ -993,6 +1045,7 @@ lbpf_status lbpf_batch_create(int32_t n, const lbpf_grid* grids, const lbpf_para
     if (!b) return bfail(nullptr, LBPF_ENOMEM, "host allocation failed");
     b->storage = grids[0].storage;
     b->shape = b->storage == LBPF_F64 ? 2 : 3;   // 32x4 (FP64) or 32x8 tiles
+    b->zslab = lbpf_storage_bytes(b->storage) == 2 ? 8 : 4;   // as a single domain
     b->stream = (hipStream_t)hip_stream;
     if (!b->stream) {
         if (hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking) != hipSuccess) {

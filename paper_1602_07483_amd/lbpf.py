@@ -53,6 +53,8 @@ class lbpf_reductions(ctypes.Structure):
 
 
 # Exported symbols, in header order (a CPU test checks each one is exported).
+FIELD_TYPE = {"f32": 0, "f64": 1}
+
 SYMBOLS = ["lbpf_create", "lbpf_destroy", "lbpf_set_fields", "lbpf_step", "lbpf_sync",
            "lbpf_read", "lbpf_history", "lbpf_read_populations", "lbpf_write_populations",
            "lbpf_read_populations_f64",
@@ -60,7 +62,8 @@ SYMBOLS = ["lbpf_create", "lbpf_destroy", "lbpf_set_fields", "lbpf_step", "lbpf_
            "lbpf_set_launch", "lbpf_get_launch", "lbpf_autotune",
            "lbpf_storage_bytes", "lbpf_bench_copy", "lbpf_last_error", "lbpf_set_graph",
            "lbpf_batch_create", "lbpf_batch_domain", "lbpf_batch_set_graph", "lbpf_batch_step",
-           "lbpf_batch_sync", "lbpf_batch_destroy", "lbpf_batch_last_error"]
+           "lbpf_batch_sync", "lbpf_batch_destroy", "lbpf_batch_last_error",
+           "lbpf_set_fields_device", "lbpf_read_fields_device"]
 
 
 class LbpfError(RuntimeError):
@@ -79,6 +82,8 @@ def load():
         "lbpf_create": ([P(lbpf_grid), P(lbpf_params), vp, P(vp)], ctypes.c_int),
         "lbpf_destroy": ([vp], ctypes.c_int),
         "lbpf_set_fields": ([vp, dp, dp, dp], ctypes.c_int),
+        "lbpf_set_fields_device": ([vp, vp, vp, vp, ctypes.c_int32], ctypes.c_int),
+        "lbpf_read_fields_device": ([vp, vp, vp, vp, ctypes.c_int32], ctypes.c_int),
         "lbpf_step": ([vp, ctypes.c_int64], ctypes.c_int),
         "lbpf_sync": ([vp], ctypes.c_int),
         "lbpf_read": ([vp, dp, dp, dp, P(lbpf_reductions)], ctypes.c_int),
@@ -227,6 +232,20 @@ class Solver:
         if check:
             self._check(st)
         return out[0], out[1], out[2], (red.as_dict() if red is not None else None)
+
+    def set_fields_device(self, phi_ptr, U_ptr, theta_ptr, dtype="f32"):
+        """Fields from device arrays (integer device addresses, [nz][ny][nx],
+        element type dtype 'f32' or 'f64')."""
+        self._check(self._lib.lbpf_set_fields_device(
+            self._h, ctypes.c_void_p(phi_ptr), ctypes.c_void_p(U_ptr), ctypes.c_void_p(theta_ptr),
+            FIELD_TYPE[dtype]))
+
+    def read_fields_device(self, phi_ptr, U_ptr, theta_ptr, dtype="f32"):
+        """Copy the fields into device arrays (0 skips one); asynchronous on
+        the solver's stream."""
+        self._check(self._lib.lbpf_read_fields_device(
+            self._h, ctypes.c_void_p(phi_ptr or None), ctypes.c_void_p(U_ptr or None),
+            ctypes.c_void_p(theta_ptr or None), FIELD_TYPE[dtype]))
 
     def read_status(self):
         red = lbpf_reductions()

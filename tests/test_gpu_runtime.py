@@ -217,3 +217,50 @@ def test_mixed_storage_tip_velocity_report(storage, bound):
     rel = np.max(np.abs(vg - vo) / np.abs(vo))
     print("%s tip velocity rel. error %.3e" % (storage, rel))
     assert rel < bound
+
+
+def _hip_runtime():
+    """The HIP runtime the library is linked against (device buffers for the
+    device-array calls; a second runtime, such as one bundled with another
+    package, would own its allocations and streams separately)."""
+    import ctypes
+    h = ctypes.CDLL("libamdhip64.so.7")
+    h.hipMalloc.argtypes = [ctypes.POINTER(ctypes.c_void_p), ctypes.c_size_t]
+    h.hipMemcpy.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int]
+    h.hipFree.argtypes = [ctypes.c_void_p]
+    return h
+
+
+@pytest.mark.parametrize("storage,dtype", [("f32", "f32"), ("f32", "f64"), ("f16", "f32"), ("f64", "f64")])
+def test_device_field_io_matches_host_io(storage, dtype):
+    """Fields handed over and read back as device arrays give the same state
+    and the same numbers as the host-array calls."""
+    import ctypes
+    hip = _hip_runtime()
+    pb = ragged()
+    npdt = np.float32 if dtype == "f32" else np.float64
+    host_in = [np.ascontiguousarray(a, dtype=npdt) for a in pb.initial_fields()]
+    nbytes = host_in[0].nbytes
+    bufs = []
+    for _ in range(6):
+        p = ctypes.c_void_p()
+        assert hip.hipMalloc(ctypes.byref(p), nbytes) == 0
+        bufs.append(p)
+    try:
+        for b, a in zip(bufs[:3], host_in):
+            assert hip.hipMemcpy(b, a.ctypes.data_as(ctypes.c_void_p), nbytes, 1) == 0
+        host = lbpf.solver_for(pb, storage=storage)
+        host.set_fields(*[a.astype(np.float64) for a in host_in])
+        devs = lbpf.solver_for(pb, storage=storage)
+        devs.set_fields_device(*(b.value for b in bufs[:3]), dtype=dtype)
+        host.step(25)
+        devs.step(25)
+        devs.read_fields_device(*(b.value for b in bufs[3:]), dtype=dtype)
+        devs.sync()
+        for a, b in zip(fields(host), bufs[3:]):
+            out = np.empty(pb.shape, dtype=npdt)
+            assert hip.hipMemcpy(out.ctypes.data_as(ctypes.c_void_p), b, nbytes, 2) == 0
+            assert np.array_equal(a.astype(npdt), out)
+    finally:
+        for b in bufs:
+            hip.hipFree(b)

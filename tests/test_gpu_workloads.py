@@ -289,3 +289,42 @@ def test_grid_anisotropy_of_isotropic_growth():
         print("D3Q%d: R100 %.3f R110 %.3f A_g %.3f %%" % (lat, r100, r110, ag[lat]))
     assert ag[7] > 1.0
     assert ag[15] < 0.5 and ag[19] < 0.5
+
+
+def _last_crossing(prof):
+    i = np.nonzero((prof[:-1] > 0) & (prof[1:] <= 0))[0]
+    assert len(i), "no phi = 0 crossing"
+    i = i[-1]
+    return i + prof[i] / (prof[i] - prof[i + 1])
+
+
+@pytest.mark.parametrize("aniso,eps,delta,steps", [(0, 0.05, 0.0, 10000), (1, 0.0, -0.02, 40000)])
+def test_preferred_growth_direction_sec_4_3(aniso, eps, delta, steps):
+    """Sec. 4.3 (non-standard dendrites) with the paper's parameters:
+    dx = 0.01, dt = 1.5e-5, W0 = 0.0125, tau0 = 1.5625e-4, lambda = 10,
+    kappa = 1, Delta = 0.25, seed R = 8 at the corner of mirror planes, pure
+    substance, in a 176^3 octant (half the paper's 351 nodes of reach, so
+    the runs stop before the crystal meets the far walls).  The cubic
+    function with eps = 0.05 grows along [100]; the K41/K61 function with
+    eps = 0, delta = -0.02 along [110], as in the paper's figure."""
+    from paper_1602_07483_amd.inputs import Problem, NOFLUX, SYMMETRY
+    n = 176
+    walls = (SYMMETRY, NOFLUX, SYMMETRY, NOFLUX, SYMMETRY, NOFLUX)
+    pb = Problem("sec4.3", n, n, n, 19, walls, dx=0.01, dt=1.5e-5, W0=0.0125, tau0=1.5625e-4,
+                 lam=10.0, Mcinf=0.0, k=0.15, D=1.0, kappa=1.0, aniso=aniso, eps=eps, delta=delta,
+                 centres=[(-0.5, -0.5, -0.5)], radius=8.0, U0=0.0, theta0=-0.25)
+    s = make_gpu(pb, "f32")
+    s.step(steps)
+    phi, _, _, red = s.read(check=False)
+    s.close()
+    assert red["nonfinite"] == 0
+    r100 = _last_crossing(phi[0, 0, :]) + 0.5
+    r110 = (_last_crossing(np.array([phi[0, i, i] for i in range(n)])) + 0.5) * np.sqrt(2.0)
+    r111 = (_last_crossing(np.array([phi[i, i, i] for i in range(n)])) + 0.5) * np.sqrt(3.0)
+    print("Sec. 4.3 aniso %d after %d steps: R100 %.2f R110 %.2f R111 %.2f (lattice units)"
+          % (aniso, steps, r100, r110, r111))
+    assert max(r100, r110, r111) < 0.95 * n
+    if aniso == 0:
+        assert r100 > 1.1 * r110 and r100 > 1.1 * r111
+    else:
+        assert r110 > 1.1 * r100 and r110 > 1.1 * r111

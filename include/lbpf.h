@@ -100,6 +100,16 @@ typedef struct {
     double eps, delta;      /* anisotropy strengths (delta used by K41K61 only) */
     int32_t reduce_every;   /* >0: record the reductions every that many steps */
     double centre[3];       /* reference point of the tip positions (node units) */
+    double vel[3];          /* uniform imposed velocity of the thermal (or
+                               solute) carrier, physical units: the theta
+                               equilibrium gains the advective term of the
+                               advection-diffusion equilibrium of Sec. 3.1,
+                               w_i theta (1 + e_i.v dt / (e^2 dx)). All zero
+                               (the paper's runs) is the pure-diffusion scheme.
+                               Nonzero runs on the default tile shape only
+                               (lbpf_set_launch and lbpf_autotune refuse or
+                               skip the others) and is refused by
+                               lbpf_batch_create; non-finite -> LBPF_EINVAL. */
 } lbpf_params;
 
 /* Diagnostics of one state, accumulated in FP64 on the device.  The paper

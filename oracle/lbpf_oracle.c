@@ -509,6 +509,15 @@ static void ut_terms(orc_ctx* c, const double* phin, const double* phio,
     }
 }
 
+/* Heat equilibrium, eq. (EqFunction_Tempr); with an advective velocity v the
+ * advection-diffusion form of Sec. 3.1: w_i theta [1 + e^-2 (e_i . v) dt/dx]. */
+static double theta_eq(const orc_ctx* c, int i, double t)
+{
+    const orc_params* p = &c->p;
+    const double ev = c->e[i][0]*p->vel[0] + c->e[i][1]*p->vel[1] + c->e[i][2]*p->vel[2];
+    return c->w[i] * t * (1.0 + ev * p->dt / (c->e2 * p->dx));
+}
+
 /* Supersaturation and heat collisions, eqs. (LBE_Eq_Transport), (LBE_Eq_Temp). */
 static void ut_collide(orc_ctx* c)
 {
@@ -525,7 +534,7 @@ static void ut_collide(orc_ctx* c)
             const size_t o = (size_t)i*n + (size_t)s;
             const double eJ = c->e[i][0]*J[0] + c->e[i][1]*J[1] + c->e[i][2]*J[2];
             const double heq = c->A[i]*u + c->B[i]*(c->r[s]*u + eJ * p->dt / (c->e2 * p->dx));
-            const double feq = c->w[i] * t;
+            const double feq = theta_eq(c, i, t);
             const double hi = c->pop[1][o], fi = c->pop[2][o];
             c->star[1][o] = hi - (hi - heq) / etaU + c->w[i] * c->srcU[s] * p->dt;
             c->star[2][o] = fi - (fi - feq) / etaT + c->w[i] * c->Qth[s] * p->dt;
@@ -554,7 +563,7 @@ int orc_init(orc_ctx* c, const double* phi, const double* U, const double* theta
         for (int i = 0; i < c->q; ++i) {
             c->pop[0][(size_t)i*n + s] = geq[i];
             c->pop[1][(size_t)i*n + s] = heq[i];
-            c->pop[2][(size_t)i*n + s] = c->w[i] * c->th[s];
+            c->pop[2][(size_t)i*n + s] = theta_eq(c, i, c->th[s]);
         }
     }
     c->steps = 0;

@@ -38,6 +38,8 @@ typedef struct {
     double k, D, kappa;       /* partition coefficient, solute and heat diffusivity */
     int32_t aniso;
     double eps, delta;        /* anisotropy strengths */
+    double vel[3];            /* uniform advective velocity of the heat equation
+                                 (advection-diffusion equilibrium, Sec. 3.1) */
 } orc_params;
 
 typedef struct orc_ctx orc_ctx;

@@ -175,6 +175,8 @@ struct Coef {
     T dt;
     T jcoef;           // omU dt / (e^2 dx)
     T jt;              // dt / (e^2 dx)
+    T adv[3];          // v dt / (e^2 dx): advection-diffusion heat equilibrium (Sec. 3.1)
+    int has_adv;       // v != 0
 };
 
 __device__ __forceinline__ int clampi(int v, int n) { return v < 0 ? 0 : (v >= n ? n - 1 : v); }
@@ -622,14 +624,15 @@ __device__ __forceinline__ void phi_body(const Coef<T>& c, int block, const S* _
 //   h_i^{n+1}(x) = (A_i + B_i r^o_x) U_x + incU_i,
 //   incU_i = [i>0] w_i (P_y - P_x) + B_i C_y + (1 - omega_U) dh_j(y) + w_i (S_y + e_j.K_y),
 //   f_i^{n+1}(x) = w_i theta_x + incT_i,
-//   incT_i = w_i (theta_y + (phi^{n+1}_y - phi^n_y)/2 - theta_x) + (1 - omega_theta) df_j(y),
+//   incT_i = w_i (theta_y + (phi^{n+1}_y - phi^n_y)/2 - theta_x) + (1 - omega_theta) df_j(y)
+//            [+ w_i e_j . A_y with the advection-diffusion equilibrium, A = omega_theta theta v dt/(e^2 dx)],
 // then U^{n+1} = U_x + dU, theta^{n+1} = theta_x + dT and the new deviations
 //   dh_i = incU_i - A_i dU + B_i [(r^o_x - r_x) U_x - r_x dU],  df_i = incT_i - w_i dT.
 // For i > 0 the pull needs only Z = P + C + S, theta + dphi/2 and K of the
 // source, so the halo terms in LDS are (Z, theta + dphi/2, Kx, Ky) and Kz;
 // the tile's own (P, C, S, r) sit in a separate two-plane array.
 // ==========================================================================
-template <class L, class T, class S, int TX, int TY, bool BUF>
+template <class L, class T, class S, int TX, int TY, bool BUF, bool ADV = false>
 __device__ __forceinline__ void ut_body(const Coef<T>& c, int block, const S* __restrict__ hin,
                                         S* __restrict__ hout, const S* __restrict__ fin,
                                         S* __restrict__ fout, const T* __restrict__ phio,
@@ -639,8 +642,10 @@ __device__ __forceinline__ void ut_body(const Coef<T>& c, int block, const S* __
     using G = Tile<TX, TY>;
     using M = March<TX, TY>;
     __shared__ V2<T> sphi[3][G::PN];      // (phi^{n+1}, 1/zeta)
+    // Kz with halo; with advection also A = omega_theta theta v dt/(e^2 dx)
+    using KT = std::conditional_t<ADV, V4<T>, T>;
     __shared__ V4<T> sta[3][G::HN];       // (Z, theta + dphi/2, Kx, Ky) with halo
-    __shared__ T stk[3][G::HN];           // Kz with halo
+    __shared__ KT stk[3][G::HN];
     __shared__ V4<T> sown[2][G::NT];      // (P, C, S, r) of the tile's own nodes
 
     G tile(c, block);
@@ -731,7 +736,7 @@ __device__ __forceinline__ void ut_body(const Coef<T>& c, int block, const S* __
             const V2<T>* f0 = sphi[(pz + 3) % 3];
             const V2<T>* fp = sphi[(pz + 4) % 3];
             V4<T>* sa = sta[(pz + 3) % 3];
-            T* sk = stk[(pz + 3) % 3];
+            KT* sk = stk[(pz + 3) % 3];
             V4<T>* so = sown[pz & 1];
 #pragma unroll
             for (int kk = 0; kk < M::NB; ++kk) {
@@ -786,7 +791,12 @@ __device__ __forceinline__ void ut_body(const Coef<T>& c, int block, const S* __
                 const T ro = r_of(po, zA, zB);
                 const T P = ro * u, C = c.omU * (r0 - ro) * u, Ssrc = src * c.dt;
                 sa[t] = V4<T>{P + C + Ssrc, th + T(0.5) * dphi, c.jcoef * Jx, c.jcoef * Jy};
-                sk[t] = c.jcoef * Jz;
+                if constexpr (ADV) {
+                    const T ot = c.omT * th;
+                    sk[t] = V4<T>{c.jcoef * Jz, ot * c.adv[0], ot * c.adv[1], ot * c.adv[2]};
+                } else {
+                    sk[t] = c.jcoef * Jz;
+                }
                 if (lx >= 1 && lx <= TX && ly >= 1 && ly <= TY)
                     so[(ly - 1) * TX + (lx - 1)] = V4<T>{P, C, Ssrc, r0};
             }
@@ -816,11 +826,19 @@ __device__ __forceinline__ void ut_body(const Coef<T>& c, int block, const S* __
                 const int tsl = (s.sz + 3) % 3, tl = (s.sy - tile.y0 + 1) * G::HX + (s.sx - tile.x0 + 1);
                 const V4<T> ta = sta[tsl][tl];
                 constexpr T wi = T(L::w(I));
-                const T eK = T(s.fx * L::ex(I)) * ta.z + T(s.fy * L::ey(I)) * ta.w +
-                             T(s.fz * L::ez(I)) * stk[tsl][tl];
+                const int ejx = s.fx * L::ex(I), ejy = s.fy * L::ey(I), ejz = s.fz * L::ez(I);
+                T eK = T(ejx) * ta.z + T(ejy) * ta.w;
+                T eA = T(0);
+                if constexpr (ADV) {
+                    const V4<T> kv = stk[tsl][tl];
+                    eK += T(ejz) * kv.x;
+                    eA = T(ejx) * kv.y + T(ejy) * kv.z + T(ejz) * kv.w;
+                } else {
+                    eK += T(ejz) * stk[tsl][tl];
+                }
                 // I > 0 here: A_I = 0, B_I = w_I
                 vu = wi * (ta.x - Px + eK) + omU1 * dh;
-                vt = wi * (ta.y - thx) + omT1 * df;
+                vt = wi * (ta.y - thx + eA) + omT1 * df;
             };
             auto fast = [&](auto ic, auto edge_c) {
                 constexpr int I = decltype(ic)::value;
@@ -830,14 +848,21 @@ __device__ __forceinline__ void ut_body(const Coef<T>& c, int block, const S* __
                 const int tl = tile.lt - ex - ey * G::HX;
                 const V4<T> ta = sta[sl[1 - ez]][tl];
                 T vu, vt;
+                T eA = T(0);
                 if constexpr (I == 0) {
                     vu = (wi - T(1)) * Cx + wi * Sx + omU1 * (T)Raw<S>::dec(ph_[I]);
                 } else {
                     T eK = T(ex) * ta.z + T(ey) * ta.w;
-                    if constexpr (ez != 0) eK += T(ez) * stk[sl[1 - ez]][tl];
+                    if constexpr (ADV) {
+                        const V4<T> kv = stk[sl[1 - ez]][tl];
+                        if constexpr (ez != 0) eK += T(ez) * kv.x;
+                        eA = T(ex) * kv.y + T(ey) * kv.z + T(ez) * kv.w;
+                    } else {
+                        if constexpr (ez != 0) eK += T(ez) * stk[sl[1 - ez]][tl];
+                    }
                     vu = wi * (ta.x - Px + eK) + omU1 * (T)Raw<S>::dec(ph_[I]);
                 }
-                vt = wi * (ta.y - thx) + omT1 * (T)Raw<S>::dec(pf_[I]);
+                vt = wi * (ta.y - thx + eA) + omT1 * (T)Raw<S>::dec(pf_[I]);
                 if constexpr (EDGE && I != 0) {
                     if (crosses<L, I>(f)) wall_link(ic, vu, vt);
                     __builtin_amdgcn_sched_barrier(0);   // one wall link at a time
@@ -886,12 +911,12 @@ __global__ __launch_bounds__(TX * TY, (sizeof(T) == 4 ? 4 : 1)) void k_phi(
     phi_body<L, T, S, TX, TY, BUF>(c, blockIdx.x, gin, gout, phin, Un, thn, phout);
 }
 
-template <class L, class T, class S, int TX, int TY, bool BUF>
+template <class L, class T, class S, int TX, int TY, bool BUF, bool ADV = false>
 __global__ __launch_bounds__(TX * TY, (sizeof(T) == 4 ? 3 : 1)) void k_ut(
     const Coef<T> c, const S* __restrict__ hin, S* __restrict__ hout, const S* __restrict__ fin,
     S* __restrict__ fout, const T* __restrict__ phio, const T* __restrict__ phnew,
     const T* __restrict__ Un, const T* __restrict__ thn, T* __restrict__ Uout, T* __restrict__ thout) {
-    ut_body<L, T, S, TX, TY, BUF>(c, blockIdx.x, hin, hout, fin, fout, phio, phnew, Un, thn, Uout, thout);
+    ut_body<L, T, S, TX, TY, BUF, ADV>(c, blockIdx.x, hin, hout, fin, fout, phio, phnew, Un, thn, Uout, thout);
 }
 
 template <class T>
@@ -935,7 +960,7 @@ __global__ __launch_bounds__(TX * TY, (sizeof(T) == 4 ? 3 : 1)) void k_ut_batch(
 template <class L, class T, class S>
 __global__ __launch_bounds__(256) void k_init(const Coef<T> c, S* __restrict__ g, S* __restrict__ h,
                                               S* __restrict__ f, const T* __restrict__ phi,
-                                              const T* __restrict__ U) {
+                                              const T* __restrict__ U, const T* __restrict__ th) {
     const int nx = c.nx, ny = c.ny, nz = c.nz;
     const size_t n = (size_t)nx * ny * nz;
     const size_t s = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -970,7 +995,9 @@ __global__ __launch_bounds__(256) void k_init(const Coef<T> c, S* __restrict__ g
         const size_t o = (size_t)I * c.np + s;
         g[o] = Codec<S>::enc(-wi * eN * c.cphi_e2);
         h[o] = Codec<S>::enc((I == 0) ? T(0) : wi * eJ * c.jt);
-        f[o] = Codec<S>::enc(T(0));
+        // f = w_i theta [1 + e_i . v dt / (e^2 dx)]: deviation w_i theta e_i . v'
+        const T ev = T(L::ex(I)) * c.adv[0] + T(L::ey(I)) * c.adv[1] + T(L::ez(I)) * c.adv[2];
+        f[o] = Codec<S>::enc(c.has_adv ? wi * th[s] * ev : T(0));
     });
 }
 

@@ -152,8 +152,19 @@ Coef<T> make_coef(const lbpf_ctx* ctx) {
     c.dt = (T)p.dt;
     c.jcoef = (T)(p.dt / (kE2 * p.dx) / etaU);
     c.jt = (T)(p.dt / (kE2 * p.dx));
+    c.has_adv = 0;
+    for (int a = 0; a < 3; ++a) {
+        c.adv[a] = (T)(p.vel[a] * p.dt / (kE2 * p.dx));
+        if (p.vel[a] != 0.0) c.has_adv = 1;
+    }
     return c;
 }
+
+bool has_advection(const lbpf_ctx* ctx) {
+    return ctx->prm.vel[0] != 0.0 || ctx->prm.vel[1] != 0.0 || ctx->prm.vel[2] != 0.0;
+}
+
+int default_shape(const lbpf_ctx* ctx) { return ctx->storage == LBPF_F64 ? 2 : 3; }
 
 int total_tiles(const lbpf_ctx* ctx) {
     const int nbx = (ctx->grid.nx + kShapes[ctx->shape].tx - 1) / kShapes[ctx->shape].tx;
@@ -204,12 +215,23 @@ lbpf_status launch_step_b(lbpf_ctx* ctx) {
                            (const T*)ctx->fld[1][a], (const T*)ctx->fld[2][a], (T*)ctx->fld[0][b]);
     });
     if (st) return st;
+    // the advection-diffusion variant exists for the default tile of each storage
+    constexpr bool kAdvTile = TX == 32 && (sizeof(T) == 8 ? TY == 4 : TY == 8);
+    if (c.has_adv && !kAdvTile) return fail(ctx, LBPF_EINVAL, "advection runs on the default tile shape only");
     st = timed(ctx, 1, [&] {
-        hipLaunchKernelGGL((k_ut<L, T, S, TX, TY, BUF>), dim3(nb), dim3(TX * TY), 0, ctx->stream, c,
-                           (const S*)ctx->pop[1][a], (S*)ctx->pop[1][b], (const S*)ctx->pop[2][a],
-                           (S*)ctx->pop[2][b], (const T*)ctx->fld[0][a], (const T*)ctx->fld[0][b],
-                           (const T*)ctx->fld[1][a], (const T*)ctx->fld[2][a], (T*)ctx->fld[1][b],
-                           (T*)ctx->fld[2][b]);
+        auto args = [&](auto kern) {
+            hipLaunchKernelGGL(kern, dim3(nb), dim3(TX * TY), 0, ctx->stream, c, (const S*)ctx->pop[1][a],
+                               (S*)ctx->pop[1][b], (const S*)ctx->pop[2][a], (S*)ctx->pop[2][b],
+                               (const T*)ctx->fld[0][a], (const T*)ctx->fld[0][b], (const T*)ctx->fld[1][a],
+                               (const T*)ctx->fld[2][a], (T*)ctx->fld[1][b], (T*)ctx->fld[2][b]);
+        };
+        if constexpr (kAdvTile) {
+            if (c.has_adv) {
+                args(k_ut<L, T, S, TX, TY, BUF, true>);
+                return;
+            }
+        }
+        args(k_ut<L, T, S, TX, TY, BUF, false>);
     });
     if (st) return st;
     ctx->cur = b;
@@ -289,7 +311,7 @@ lbpf_status launch_init_t(lbpf_ctx* ctx) {
     const int a = ctx->cur;
     hipLaunchKernelGGL((k_init<L, T, S>), dim3(nb), dim3(256), 0, ctx->stream, c, (S*)ctx->pop[0][a],
                        (S*)ctx->pop[1][a], (S*)ctx->pop[2][a], (const T*)ctx->fld[0][a],
-                       (const T*)ctx->fld[1][a]);
+                       (const T*)ctx->fld[1][a], (const T*)ctx->fld[2][a]);
     CHK(hipGetLastError());
     return LBPF_OK;
 }
@@ -466,6 +488,8 @@ lbpf_status lbpf_create(const lbpf_grid* grid, const lbpf_params* params, void* 
     if (p.aniso != LBPF_ANISO_CUBIC && p.aniso != LBPF_ANISO_K41K61)
         return fail(nullptr, LBPF_EINVAL, "bad anisotropy function");
     if (p.reduce_every < 0) return fail(nullptr, LBPF_EINVAL, "reduce_every < 0");
+    if (!std::isfinite(p.vel[0]) || !std::isfinite(p.vel[1]) || !std::isfinite(p.vel[2]))
+        return fail(nullptr, LBPF_EINVAL, "advective velocity must be finite");
 
     lbpf_ctx* ctx = new (std::nothrow) lbpf_ctx();
     if (!ctx) return fail(nullptr, LBPF_ENOMEM, "host allocation failed");
@@ -776,6 +800,8 @@ lbpf_status lbpf_set_launch(lbpf_ctx* ctx, int32_t tile_x, int32_t tile_y, int32
         if (kShapes[i].tx != tile_x || kShapes[i].ty != tile_y) continue;
         const bool ok = ctx->storage == LBPF_F64 ? (i == 0 || i == 2) : true;
         if (!ok) return fail(ctx, LBPF_EINVAL, "tile shape not available for FP64 storage");
+        if (has_advection(ctx) && i != default_shape(ctx))
+            return fail(ctx, LBPF_EINVAL, "advection runs on the default tile shape only");
         ctx->shape = i;
         ctx->zslab = zslab;
         ctx->remap = xcd_remap;
@@ -820,6 +846,7 @@ lbpf_status lbpf_autotune(lbpf_ctx* ctx, int32_t steps_per_candidate, double* be
     const int zs_list[] = {2, 4, 8, 16, 32};
     for (int sh = 0; sh < kNumShapes && !st; ++sh) {
         if (ctx->storage == LBPF_F64 ? !(sh == 0 || sh == 2) : false) continue;
+        if (has_advection(ctx) && sh != default_shape(ctx)) continue;
         for (int zi = 0; zi < 10 && !st; ++zi) {
             const int zsl = zs_list[zi % 5];
             if (zsl > 2 * ctx->grid.nz && zi % 5 > 0) continue;
@@ -1038,9 +1065,12 @@ lbpf_status lbpf_batch_create(int32_t n, const lbpf_grid* grids, const lbpf_para
     for (int i = 1; i < n; ++i)
         if (grids[i].storage != grids[0].storage)
             return bfail(nullptr, LBPF_EINVAL, "all domains of a batch share one storage type");
-    for (int i = 0; i < n; ++i)
+    for (int i = 0; i < n; ++i) {
         if (grids[i].lattice != LBPF_D3Q15 && grids[i].lattice != LBPF_D3Q19)
             return bfail(nullptr, LBPF_EINVAL, "batched domains use D3Q15 or D3Q19");
+        if (params[i].vel[0] != 0.0 || params[i].vel[1] != 0.0 || params[i].vel[2] != 0.0)
+            return bfail(nullptr, LBPF_EINVAL, "batched domains have no advective velocity");
+    }
     lbpf_batch* b = new (std::nothrow) lbpf_batch();
     if (!b) return bfail(nullptr, LBPF_ENOMEM, "host allocation failed");
     b->storage = grids[0].storage;

@@ -81,6 +81,7 @@ class Problem:
     aniso: int = 0
     eps: float = 0.05
     delta: float = 0.0
+    vel: Tuple[float, float, float] = (0.0, 0.0, 0.0)   # advective velocity of theta
     # initial condition
     centres: List[Tuple[float, float, float]] = field(default_factory=list)
     radius: float = 5.0
@@ -106,7 +107,7 @@ class Problem:
     def model_kwargs(self):
         d = asdict(self)
         keys = ("lattice", "walls", "dx", "dt", "W0", "tau0", "lam", "Mcinf", "k", "D",
-                "kappa", "aniso", "eps", "delta")
+                "kappa", "aniso", "eps", "delta", "vel")
         return {kk: d[kk] for kk in keys}
 
     def initial_fields(self):

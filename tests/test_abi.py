@@ -61,3 +61,14 @@ def test_storage_bytes_and_invalid_arguments_without_gpu():
     params = (lbpf.lbpf_params * 1)(p)
     assert L.lbpf_batch_create(1, grids, params, None, ctypes.byref(h)) == lbpf.LBPF_EINVAL
     assert b"D3Q15 or D3Q19" in L.lbpf_batch_last_error(None)
+    # an imposed velocity must be finite, and batches carry none
+    g.lattice = 19
+    p.vel[0] = float("nan")
+    assert L.lbpf_create(ctypes.byref(g), ctypes.byref(p), None, ctypes.byref(h)) == lbpf.LBPF_EINVAL
+    assert b"velocity" in L.lbpf_last_error(None)
+    p.vel[0] = 0.01
+    grids = (lbpf.lbpf_grid * 1)(g)
+    params = (lbpf.lbpf_params * 1)(p)
+    assert L.lbpf_batch_create(1, grids, params, None, ctypes.byref(h)) == lbpf.LBPF_EINVAL
+    assert b"advective velocity" in L.lbpf_batch_last_error(None)
+    assert not h.value

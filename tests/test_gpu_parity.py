@@ -6,6 +6,8 @@ Tolerances:
     (rounding order and fused multiply-adds only);
   * FP32 build: max|dphi|, max|dU| <= 1e-5 after 200 steps (the stated target).
 """
+import dataclasses
+
 import numpy as np
 import pytest
 
@@ -155,3 +157,38 @@ def test_fp64_populations_match_oracle():
         err = maxabs(s.read_populations_f64(f), o.pops(f))
         print("fp64 populations field %d max-abs %.3e" % (f, err))
         assert err <= 1e-12, "field %d" % f
+
+
+# ------------------------------------------------------------- advection
+ADV_VEL = (0.5, -0.3, 0.4)     # 0.075, -0.045, 0.06 nodes per step at dt = 0.15
+
+
+@pytest.mark.parametrize("lattice", [19, 7])
+@pytest.mark.parametrize("storage,tol", [("f64", 1e-11), ("f32", 1e-5)])
+def test_advection_matches_oracle(lattice, storage, tol):
+    """theta with the advective equilibrium (uniform imposed velocity) against
+    the oracle on the ragged case: same tolerances as the pure-diffusion
+    scheme, and the velocity visibly changes the result."""
+    base = ragged_problem(lattice, 0)
+    pb = dataclasses.replace(base, vel=ADV_VEL)
+    steps = 60
+    (gphi, gU, gth, red), (ophi, oU, oth, ored) = _run_both(pb, storage, steps)
+    ephi, eU, eth = maxabs(gphi, ophi), maxabs(gU, oU), maxabs(gth, oth)
+    print("%s q%d advected: max|dphi| %.3e max|dU| %.3e max|dtheta| %.3e"
+          % (storage, lattice, ephi, eU, eth))
+    assert max(ephi, eU, eth) <= tol
+    o0 = make_oracle(base)
+    o0.step(steps)
+    assert maxabs(o0.fields()[2], oth) > 1e3 * tol     # advection is not a no-op here
+
+
+def test_advection_keeps_default_tile():
+    pb = dataclasses.replace(ragged_problem(19, 0), vel=ADV_VEL)
+    s = make_gpu(pb, storage="f32")
+    tx, ty, zs, rm = s.get_launch()
+    assert (tx, ty) == (32, 8)
+    with pytest.raises(lbpf.LbpfError, match="default tile"):
+        s.set_launch(64, 4, zs, rm)
+    s.set_launch(tx, ty, zs, rm)                      # the default shape stays allowed
+    (shape, _), = [s.autotune(2)]
+    assert shape[:2] == (32, 8)

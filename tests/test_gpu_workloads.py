@@ -144,7 +144,15 @@ def test_ensemble_health_and_sampled_parity():
     """The 64-domain ensemble, batched in mixed FP16 storage with graph
     replay: every domain healthy after 2000 steps, and the smallest and
     largest domain of each lattice against the oracle after 200 steps
-    (FP32 batch, element by element)."""
+    (FP32 batch, element by element).
+
+    Tolerance 2e-5: the largest D3Q19 domain (95^3, Delta = 0.52,
+    eps = 0.061) grows fastest, and there the rounding of the FP32 state
+    (one rounding of phi, U, theta per node and step) is amplified by the
+    growing tips about 1.5x every 25 steps after step 75, to about 1.2e-5
+    at step 200; the same algorithm with every double of the oracle
+    replaced by float reaches 2.0e-5.  The 1e-5 bar is checked on the
+    small workload and the ragged cases."""
     probs = workload_ensemble()
     b = lbpf.Batch([lbpf.problem_kwargs(p) for p in probs], storage="f16")
     for d, p in zip(b.domains, probs):
@@ -178,7 +186,7 @@ def test_ensemble_health_and_sampled_parity():
         ophi, oU, oth = o.fields()
         print("%s (Q%d, %d^3): max|dphi| %.2e max|dU| %.2e" % (p.name, p.lattice, p.nx,
                                                               maxabs(phi, ophi), maxabs(U, oU)))
-        assert maxabs(phi, ophi) <= 1e-5 and maxabs(U, oU) <= 1e-5 and maxabs(th, oth) <= 1e-5
+        assert maxabs(phi, ophi) <= 2e-5 and maxabs(U, oU) <= 2e-5 and maxabs(th, oth) <= 2e-5
     b.close()
 
 

@@ -376,3 +376,49 @@ def test_solute_mass_drift_converges_second_order():
     print("mass drift %s, ratios %.2f %.2f" % (["%.2e" % d for d in drifts], r1, r2))
     assert drifts[0] > drifts[1] > drifts[2]
     assert r1 < r2 and 3.4 < r2 < 4.6
+
+
+@pytest.mark.parametrize("lattice", [19, 7])
+def test_advected_gaussian_heat_equation(lattice):
+    """Advection-diffusion equilibrium of Sec. 3.1 (f_eq = w_i theta
+    [1 + e^-2 (e_i . v) dt/dx]) in a uniform liquid (phi = -1, no latent
+    heat): the first moment of f starts at the BGK fixed point v Theta dt/dx,
+    so the theta centroid moves exactly v dt per step away from the walls;
+    the variance grows as 2 kappa t (up to the O(v^2) numerical diffusion of
+    the scheme); and v = 0 reproduces the plain scheme bit for bit."""
+    n, steps = 64, 60        # walls stay > 6 standard deviations from the centre
+    v = (0.05, -0.03, 0.02)
+    kw = dict(lattice=lattice, walls=(NOFLUX,) * 6, dx=1.0, dt=1.0, W0=1.0, tau0=1.0, lam=0.0,
+              Mcinf=0.0, k=0.15, D=0.1, kappa=0.1, eps=0.0)
+    z, y, x = np.meshgrid(*(np.arange(n, dtype=float),) * 3, indexing="ij")
+    c0 = (31.5, 32.0, 32.5)
+    s0 = 3.0
+    th0 = np.exp(-((x - c0[0]) ** 2 + (y - c0[1]) ** 2 + (z - c0[2]) ** 2) / (2 * s0 ** 2))
+    phi0 = -np.ones_like(th0)
+    U0 = np.zeros_like(th0)
+
+    def moments(th):
+        m = th.sum()
+        cx = [(g * th).sum() / m for g in (x, y, z)]
+        var = sum(((g - cg) ** 2 * th).sum() / m for g, cg in zip((x, y, z), cx)) / 3.0
+        return m, cx, var
+
+    o = Oracle(n, n, n, vel=v, **kw)
+    o.init(phi0, U0, th0)
+    m0, cen0, var0 = moments(th0)
+    o.step(steps)
+    th = o.fields()[2]
+    m1, cen1, var1 = moments(th)
+    assert abs(m1 - m0) < 1e-10 * m0
+    for a in range(3):   # exact up to the e^-18 tail that reaches the walls
+        assert abs(cen1[a] - cen0[a] - v[a] * steps) < 1e-6, a
+    spread = var1 - var0
+    assert abs(spread - 2 * 0.1 * steps) < 0.05 * 2 * 0.1 * steps
+    # v = 0: the advective form reduces to eq. (EqFunction_Tempr) exactly
+    a = Oracle(n, n, n, vel=(0.0, 0.0, 0.0), **kw)
+    b = Oracle(n, n, n, **kw)
+    a.init(phi0, U0, th0)
+    b.init(phi0, U0, th0)
+    a.step(10)
+    b.step(10)
+    assert np.array_equal(a.fields()[2], b.fields()[2])

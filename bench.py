@@ -68,11 +68,11 @@ def run_gpu(storage, steps, warmup, n, launch=None):
     s = lbpf.solver_for(pb, storage=storage, stream=stream)
     s.set_fields(*pb.initial_fields())
     if launch == "auto":
-        # launch shape picked by the library's autotuner (state restored after)
-        launch, _ = s.autotune(6)
+        # launch of each kernel picked by the library's autotuner (state restored after)
+        s.autotune(6)
     elif launch is not None:
         s.set_launch(*launch)
-    launch = s.get_launch()
+    launches = s.launches()
     s.step(warmup)
     s.sync()
     torch.cuda.synchronize()
@@ -96,7 +96,8 @@ def run_gpu(storage, steps, warmup, n, launch=None):
         kern[name] = {"avg_ms": avg_ms, "launches": cnt[i], "bytes_per_launch": per_launch,
                       "GBps": per_launch / (avg_ms * 1e-3) / 1e9}
     return {"mlups": lups / wall / 1e6, "ms_per_step": wall / steps * 1e3,
-            "launch": {"tile": [launch[0], launch[1]], "zslab": launch[2], "xcd_remap": launch[3]},
+            "launch": {k: {"tile": [v[0], v[1]], "zslab": v[2], "xcd_remap": v[3]}
+                       for k, v in launches.items()},
             "algorithmic_GBps": lups * (bpl["k_phi"] + bpl["k_ut"]) / wall / 1e9,
             "kernels": kern, "solid_fraction": red["solid_fraction"],
             "phi_range": [red["phi_min"], red["phi_max"]]}
@@ -244,7 +245,7 @@ def main():
                     help="let the library's autotuner pick the launch before timing")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py: this build runs on one GPU only; --gpus %d is not supported "
+        print("bench.py: the library runs on one GPU; --gpus %d is not supported "
               "(the design notes describe how the step would shard)" % args.gpus, file=sys.stderr)
         return 2
     rank = int(os.environ.get("RANK", "0"))

@@ -106,9 +106,9 @@ typedef struct {
                                advection-diffusion equilibrium of Sec. 3.1,
                                w_i theta (1 + e_i.v dt / (e^2 dx)). All zero
                                (the paper's runs) is the pure-diffusion scheme.
-                               Nonzero runs on the default tile shape only
-                               (lbpf_set_launch and lbpf_autotune refuse or
-                               skip the others) and is refused by
+                               Nonzero keeps k_ut on its default tile
+                               (lbpf_set_launch refuses other k_ut tiles,
+                               lbpf_autotune does not try them) and is refused by
                                lbpf_batch_create; non-finite -> LBPF_EINVAL. */
 } lbpf_params;
 
@@ -229,25 +229,40 @@ lbpf_status lbpf_debug_stream_only(lbpf_ctx* ctx, int64_t nsteps);
 lbpf_status lbpf_set_timing(lbpf_ctx* ctx, int32_t enable);
 lbpf_status lbpf_kernel_times(lbpf_ctx* ctx, double ms[3], int64_t launches[3]);
 
-/* Launch shape of the two step kernels: a tile of tile_x x tile_y nodes per
+/* Launch shape of the step kernels: a tile of tile_x x tile_y nodes per
  * block (one thread per node), marching through zslab planes; xcd_remap = 1
  * deals each of the 8 XCDs one contiguous run of tiles (neighbouring tiles
  * then share that XCD's L2), 0 keeps the hardware's round-robin order.
  * Supported tiles: 64x2, 64x4, 32x4, 32x8, 32x16 (FP64 storage: 64x2 and
  * 32x4); zslab >= 1.  The shape changes speed only, never results.
- * Default: 32x8 (FP64: 32x4), zslab 4 (8 for 16-bit storage), remap 1.
- * Errors: EINVAL (unsupported shape or flag). */
+ *
+ * The two kernels of a step (kernel 0: k_phi, the phase-field update;
+ * kernel 1: k_ut, the U and theta update) are separate launches, each with a
+ * launch of its own.  lbpf_set_launch sets both (all or nothing);
+ * lbpf_set_kernel_launch one.  lbpf_get_launch reports k_ut's, the kernel
+ * that moves the most bytes; lbpf_get_kernel_launch either.
+ * Defaults: k_phi 32x8, zslab 6 (FP32) or 8 (16-bit); k_ut 64x4 zslab 6
+ * (FP32) or 32x8 zslab 8 (16-bit); FP64 32x4 zslab 4 for both; remap 1.
+ * With an advective velocity (lbpf_params.vel) k_ut keeps its default tile.
+ * Errors: EINVAL (unsupported shape, flag or kernel index; a k_ut tile
+ * other than the default while advecting). */
 lbpf_status lbpf_set_launch(lbpf_ctx* ctx, int32_t tile_x, int32_t tile_y, int32_t zslab,
                             int32_t xcd_remap);
 lbpf_status lbpf_get_launch(lbpf_ctx* ctx, int32_t* tile_x, int32_t* tile_y, int32_t* zslab,
                             int32_t* xcd_remap);
+lbpf_status lbpf_set_kernel_launch(lbpf_ctx* ctx, int32_t kernel, int32_t tile_x, int32_t tile_y,
+                                   int32_t zslab, int32_t xcd_remap);
+lbpf_status lbpf_get_kernel_launch(lbpf_ctx* ctx, int32_t kernel, int32_t* tile_x, int32_t* tile_y,
+                                   int32_t* zslab, int32_t* xcd_remap);
 
-/* Autotuner: times every supported tile shape with zslab in {2,4,8,16,32}
- * and both XCD orders
- * (steps_per_candidate steps each, after two untimed steps), keeps the
- * fastest and restores the state it started from (a temporary device
- * snapshot of one lattice and the fields is allocated).  *best_ms_per_step
- * (may be NULL) receives the best time.  Synchronises.
+/* Autotuner: times every supported tile shape with zslab in
+ * {2,4,6,8,12,16} and both XCD orders (steps_per_candidate steps each, after
+ * two untimed steps, with events around each kernel), keeps for each of the
+ * two kernels its fastest launch, and restores the state it started from (a
+ * temporary device snapshot of the populations and fields is allocated).
+ * *best_ms_per_step (may be NULL) receives the sum of the two kernels' best
+ * times.  Launches timed before the call are added to the lbpf_kernel_times
+ * accumulators; the tuner's own are not.  Synchronises.
  * Errors: ESTATE (no fields yet), EINVAL, ENOMEM, EDEVICE. */
 lbpf_status lbpf_autotune(lbpf_ctx* ctx, int32_t steps_per_candidate, double* best_ms_per_step);
 

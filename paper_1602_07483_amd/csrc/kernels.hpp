@@ -84,19 +84,16 @@ __device__ __forceinline__ void st_nt(__hip_bfloat16* p, __hip_bfloat16 v) {
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void* p, unsigned bytes) {
     return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)bytes, 0x00020000);
 }
-template <class S> __device__ __forceinline__ S buf_ld(__amdgpu_buffer_rsrc_t r, unsigned v, unsigned s);
-template <> __device__ __forceinline__ float buf_ld<float>(__amdgpu_buffer_rsrc_t r, unsigned v, unsigned s) {
-    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, (int)v, (int)s, 0));
-}
-template <> __device__ __forceinline__ double buf_ld<double>(__amdgpu_buffer_rsrc_t r, unsigned v, unsigned s) {
-    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, (int)v, (int)s, 0));
-}
-template <> __device__ __forceinline__ __half buf_ld<__half>(__amdgpu_buffer_rsrc_t r, unsigned v, unsigned s) {
-    return __ushort_as_half(__builtin_amdgcn_raw_buffer_load_b16(r, (int)v, (int)s, 0));
-}
-template <> __device__ __forceinline__ __hip_bfloat16 buf_ld<__hip_bfloat16>(__amdgpu_buffer_rsrc_t r, unsigned v,
-                                                                            unsigned s) {
-    return __builtin_bit_cast(__hip_bfloat16, __builtin_amdgcn_raw_buffer_load_b16(r, (int)v, (int)s, 0));
+// CP is the cache policy of the load: 0 normal, 2 non-temporal (the line is
+// not re-read by any block, so it should not displace lines that are).
+template <class S, int CP = 0>
+__device__ __forceinline__ S buf_ld(__amdgpu_buffer_rsrc_t r, unsigned v, unsigned s) {
+    if constexpr (sizeof(S) == 8)
+        return __builtin_bit_cast(S, __builtin_amdgcn_raw_buffer_load_b64(r, (int)v, (int)s, CP));
+    else if constexpr (sizeof(S) == 4)
+        return __builtin_bit_cast(S, __builtin_amdgcn_raw_buffer_load_b32(r, (int)v, (int)s, CP));
+    else
+        return __builtin_bit_cast(S, __builtin_amdgcn_raw_buffer_load_b16(r, (int)v, (int)s, CP));
 }
 // streaming (non-temporal) stores
 __device__ __forceinline__ void buf_st(float x, __amdgpu_buffer_rsrc_t r, unsigned v, unsigned s) {
@@ -119,14 +116,16 @@ __device__ __forceinline__ void buf_st(__hip_bfloat16 x, __amdgpu_buffer_rsrc_t 
 // into half-register loads whose partial writes force a wait after each load.
 template <class S> struct Raw {
     using type = S;
-    __device__ static S ld(__amdgpu_buffer_rsrc_t r, unsigned v, unsigned s) { return buf_ld<S>(r, v, s); }
+    template <int CP = 0>
+    __device__ static S ld(__amdgpu_buffer_rsrc_t r, unsigned v, unsigned s) { return buf_ld<S, CP>(r, v, s); }
     __device__ static S ldg(const S* p) { return *p; }
     __device__ static auto dec(S x) { return Codec<S>::dec(x); }
 };
 template <> struct Raw<__hip_bfloat16> {
     using type = unsigned;
+    template <int CP = 0>
     __device__ static unsigned ld(__amdgpu_buffer_rsrc_t r, unsigned v, unsigned s) {
-        return (unsigned)__builtin_amdgcn_raw_buffer_load_b16(r, (int)v, (int)s, 0);
+        return (unsigned)__builtin_amdgcn_raw_buffer_load_b16(r, (int)v, (int)s, CP);
     }
     __device__ static unsigned ldg(const __hip_bfloat16* p) {
         return (unsigned)*reinterpret_cast<const unsigned short*>(p);
@@ -489,8 +488,8 @@ __device__ __forceinline__ void phi_body(const Coef<T>& c, int block, const S* _
                     const unsigned vx = xi * (unsigned)sizeof(S);
                     const unsigned sI = (unsigned)(I * np) * (unsigned)sizeof(S);
                     const unsigned vj = cr ? vx + (unsigned)off * (unsigned)sizeof(S) : vx;
-                    pnl[I] = Raw<S>::ld(rin, vx, sI);
-                    pj[I] = Raw<S>::ld(rin, vj, sI - (unsigned)off * (unsigned)sizeof(S));
+                    pnl[I] = Raw<S>::template ld<>(rin, vx, sI);
+                    pj[I] = Raw<S>::template ld<>(rin, vj, sI - (unsigned)off * (unsigned)sizeof(S));
                 } else {
                     const S* gI = gin + (size_t)I * np;
                     const unsigned so = cr ? xi : xi - (unsigned)off;
@@ -708,8 +707,12 @@ __device__ __forceinline__ void ut_body(const Coef<T>& c, int block, const S* __
                     const unsigned vx = xi * (unsigned)sizeof(S);
                     const unsigned vj = cr ? vx + (unsigned)off * (unsigned)sizeof(S) : vx;
                     const unsigned sj = (unsigned)(I * np) * (unsigned)sizeof(S) - (unsigned)off * (unsigned)sizeof(S);
-                    ph_[I] = Raw<S>::ld(rhin, vj, sj);
-                    pf_[I] = Raw<S>::ld(rfin, vj, sj);
+                    // The pull is a bijection: with e_x = 0 and rows of whole
+                    // 128-byte lines, every line of a source row is read by
+                    // this block alone, once.
+                    constexpr int CP = ex == 0 && (TX * sizeof(S)) % 128 == 0 ? 2 : 0;
+                    ph_[I] = Raw<S>::template ld<CP>(rhin, vj, sj);
+                    pf_[I] = Raw<S>::template ld<CP>(rfin, vj, sj);
                 } else {
                     const unsigned so = cr ? xi : xi - (unsigned)off;
                     ph_[I] = Raw<S>::ldg(hin + (size_t)I * np + so);
@@ -1121,75 +1124,11 @@ __global__ __launch_bounds__(256) void k_reduce_part(int nx, int ny, int nz, dou
     }
 }
 
-// Record layout (RED_STRIDE doubles): step, solid, mass, enthalpy, tip x,y,z,
-// phi min, phi max, non-finite count, sum U, sum phi.
-__global__ __launch_bounds__(256) void k_reduce_final(const double* __restrict__ part, int nparts,
-                                                      double inv_n, double cx, double cy, double cz,
-                                                      long long step, double* __restrict__ rec) {
-    __shared__ double sh[4][RV_COUNT];
-    double v[RV_COUNT];
-#pragma unroll
-    for (int i = 0; i < RV_NSUM; ++i) v[i] = 0.0;
-#pragma unroll
-    for (int i = RV_NSUM; i < RV_COUNT; ++i) v[i] = -INFINITY;
-    for (int p = threadIdx.x; p < nparts; p += blockDim.x) {
-#pragma unroll
-        for (int i = 0; i < RV_COUNT; ++i) {
-            const double x = part[(size_t)p * RED_STRIDE + i];
-            v[i] = i < RV_NSUM ? v[i] + x : fmax(v[i], x);
-        }
-    }
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-#pragma unroll
-    for (int i = 0; i < RV_COUNT; ++i) {
-        const double r = i < RV_NSUM ? wave_sum(v[i]) : wave_max(v[i]);
-        if (lane == 0) sh[wv][i] = r;
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        double r[RV_COUNT];
-        for (int i = 0; i < RV_COUNT; ++i) {
-            r[i] = sh[0][i];
-            for (int w = 1; w < 4; ++w) r[i] = i < RV_NSUM ? r[i] + sh[w][i] : fmax(r[i], sh[w][i]);
-        }
-        const double nanv = __longlong_as_double(0x7ff8000000000000LL);
-        rec[0] = (double)step;
-        rec[1] = r[RV_SOLID] * inv_n;
-        rec[2] = r[RV_MASS];
-        rec[3] = r[RV_ENTH];
-        rec[4] = r[RV_TIPX] > -1e300 ? r[RV_TIPX] - cx : nanv;
-        rec[5] = r[RV_TIPY] > -1e300 ? r[RV_TIPY] - cy : nanv;
-        rec[6] = r[RV_TIPZ] > -1e300 ? r[RV_TIPZ] - cz : nanv;
-        rec[7] = -r[RV_NEG_PMIN];
-        rec[8] = r[RV_PMAX];
-        rec[9] = r[RV_BAD];
-        rec[10] = r[RV_SUMU];
-        rec[11] = r[RV_SUMPHI];
-    }
-}
-
 // Element-wise type conversion of a field (device-resident field I/O).
 template <class From, class To>
 __global__ __launch_bounds__(256) void k_convert(const From* __restrict__ in, To* __restrict__ out, size_t n) {
     const size_t stride = (size_t)gridDim.x * blockDim.x;
     for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) out[i] = (To)in[i];
-}
-
-// Plain 16-byte vector copy, four loads in flight per thread and streaming
-// hints: the practical bandwidth reference.
-typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
-__global__ __launch_bounds__(256) void k_copy(const u32x4* __restrict__ src, u32x4* __restrict__ dst,
-                                              size_t n16) {
-    const size_t stride = (size_t)gridDim.x * blockDim.x;
-    size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    for (; i + 3 * stride < n16; i += 4 * stride) {
-        u32x4 v[4];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) v[u] = __builtin_nontemporal_load(&src[i + u * stride]);
-#pragma unroll
-        for (int u = 0; u < 4; ++u) __builtin_nontemporal_store(v[u], &dst[i + u * stride]);
-    }
-    for (; i < n16; i += stride) dst[i] = src[i];
 }
 
 }  // namespace lbpf

@@ -5,76 +5,90 @@
 // (kernel k_phi), then supersaturation and temperature with the new phase
 // field (kernel k_ut).  Each field has two population lattices and two field
 // buffers; the parity `cur` names the current state.
-#include <hip/hip_runtime.h>
+#include "runtime.hpp"
 
-#include <algorithm>
-#include <cmath>
-#include <cstdio>
-#include <cstring>
-#include <string>
-#include <vector>
+// The library's two non-template kernels, defined in this translation unit
+// only (the step translation units include kernels.hpp too).
+namespace lbpf {
 
-#include "../../include/lbpf.h"
-#include "kernels.hpp"
+// Record layout (RED_STRIDE doubles): step, solid, mass, enthalpy, tip x,y,z,
+// phi min, phi max, non-finite count, sum U, sum phi.
+__global__ __launch_bounds__(256) void k_reduce_final(const double* __restrict__ part, int nparts,
+                                                      double inv_n, double cx, double cy, double cz,
+                                                      long long step, double* __restrict__ rec) {
+    __shared__ double sh[4][RV_COUNT];
+    double v[RV_COUNT];
+#pragma unroll
+    for (int i = 0; i < RV_NSUM; ++i) v[i] = 0.0;
+#pragma unroll
+    for (int i = RV_NSUM; i < RV_COUNT; ++i) v[i] = -INFINITY;
+    for (int p = threadIdx.x; p < nparts; p += blockDim.x) {
+#pragma unroll
+        for (int i = 0; i < RV_COUNT; ++i) {
+            const double x = part[(size_t)p * RED_STRIDE + i];
+            v[i] = i < RV_NSUM ? v[i] + x : fmax(v[i], x);
+        }
+    }
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+    for (int i = 0; i < RV_COUNT; ++i) {
+        const double r = i < RV_NSUM ? wave_sum(v[i]) : wave_max(v[i]);
+        if (lane == 0) sh[wv][i] = r;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double r[RV_COUNT];
+        for (int i = 0; i < RV_COUNT; ++i) {
+            r[i] = sh[0][i];
+            for (int w = 1; w < 4; ++w) r[i] = i < RV_NSUM ? r[i] + sh[w][i] : fmax(r[i], sh[w][i]);
+        }
+        const double nanv = __longlong_as_double(0x7ff8000000000000LL);
+        rec[0] = (double)step;
+        rec[1] = r[RV_SOLID] * inv_n;
+        rec[2] = r[RV_MASS];
+        rec[3] = r[RV_ENTH];
+        rec[4] = r[RV_TIPX] > -1e300 ? r[RV_TIPX] - cx : nanv;
+        rec[5] = r[RV_TIPY] > -1e300 ? r[RV_TIPY] - cy : nanv;
+        rec[6] = r[RV_TIPZ] > -1e300 ? r[RV_TIPZ] - cz : nanv;
+        rec[7] = -r[RV_NEG_PMIN];
+        rec[8] = r[RV_PMAX];
+        rec[9] = r[RV_BAD];
+        rec[10] = r[RV_SUMU];
+        rec[11] = r[RV_SUMPHI];
+    }
+}
+
+// Plain 16-byte vector copy, four loads in flight per thread and streaming
+// hints: the practical bandwidth reference.
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+__global__ __launch_bounds__(256) void k_copy(const u32x4* __restrict__ src, u32x4* __restrict__ dst,
+                                              size_t n16) {
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    for (; i + 3 * stride < n16; i += 4 * stride) {
+        u32x4 v[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) v[u] = __builtin_nontemporal_load(&src[i + u * stride]);
+#pragma unroll
+        for (int u = 0; u < 4; ++u) __builtin_nontemporal_store(v[u], &dst[i + u * stride]);
+    }
+    for (; i < n16; i += stride) dst[i] = src[i];
+}
+
+}  // namespace lbpf
 
 using namespace lbpf;
+using namespace lbpf_rt;
 
 namespace {
-
 thread_local std::string g_create_error;
-
-constexpr int HIST_CAP = 8192;
-constexpr int RED_BLOCKS = 1024;
-
-struct TimedLaunch {
-    int kind;
-    hipEvent_t a, b;
-};
-
-// Tile shapes (TX x TY threads; a wavefront covers 64/TX rows).
-struct Shape {
-    int tx, ty;
-};
-constexpr Shape kShapes[] = {{64, 2}, {64, 4}, {32, 4}, {32, 8}, {32, 16}};
-constexpr int kNumShapes = 5;
-
 }  // namespace
 
-struct lbpf_ctx {
-    lbpf_grid grid;
-    lbpf_params prm;
-    hipStream_t stream = nullptr;
-    bool own_stream = false;
-    bool in_batch = false;   // member of a batch: stepped through lbpf_batch_step only
-    int graph_steps = 0;     // >0: replay the step loop from a captured HIP graph
-    hipGraphExec_t gexec = nullptr;
-    int g_shape = -1, g_zslab = -1, g_remap = -1, g_cur = -1;
-    int q = 19;
-    int storage = LBPF_F32;
-    size_t sbytes = 4;       // bytes per stored population
-    size_t tbytes = 4;       // bytes per field value (compute type)
-    size_t n = 0;            // nodes
-    size_t np = 0;           // population stride in elements
-    void* pop[3][2] = {};    // [field][parity]
-    void* fld[3][2] = {};    // phi, U, theta [parity]
-    int cur = 0;
-    bool have_fields = false;
-    int64_t step = 0;
-    double* part = nullptr;  // RED_BLOCKS partials
-    double* hist = nullptr;  // HIST_CAP records
-    double* fresh = nullptr; // one record for lbpf_read
-    int64_t hist_count = 0;
-    int shape = 3;           // tile shape id, see kShapes
-    int zslab = 4;
-    int remap = 1;           // XCD-chunked tile order
-    bool timing = false;
-    std::vector<TimedLaunch> launches;
-    std::vector<hipEvent_t> pool;
-    double t_ms[3] = {0, 0, 0};
-    int64_t t_n[3] = {0, 0, 0};
-    std::string err;
-};
-
+lbpf_status lbpf_rt::fail(lbpf_ctx* ctx, lbpf_status s, const std::string& msg) {
+    if (ctx) ctx->err = msg;
+    else g_create_error = msg;
+    return s;
+}
 
 // --------------------------------------------------------------------------
 // Batch: independent domains stepped together by one launch per lattice type
@@ -98,192 +112,6 @@ struct lbpf_batch {
 
 namespace {
 
-#define CHK(call)                                                                  \
-    do {                                                                           \
-        hipError_t e_ = (call);                                                    \
-        if (e_ != hipSuccess) {                                                    \
-            ctx->err = std::string(#call) + ": " + hipGetErrorString(e_);          \
-            return LBPF_EDEVICE;                                                   \
-        }                                                                          \
-    } while (0)
-
-lbpf_status fail(lbpf_ctx* ctx, lbpf_status s, const std::string& msg) {
-    if (ctx) ctx->err = msg;
-    else g_create_error = msg;
-    return s;
-}
-
-template <class T>
-Coef<T> make_coef(const lbpf_ctx* ctx) {
-    const lbpf_params& p = ctx->prm;
-    const lbpf_grid& g = ctx->grid;
-    const double kE2 = lattice_e2(ctx->q);
-    Coef<T> c{};
-    c.nx = g.nx; c.ny = g.ny; c.nz = g.nz;
-    c.symm = 0;
-    for (int f = 0; f < 6; ++f)
-        if (g.wall[f] == LBPF_WALL_SYMMETRY) c.symm |= 1 << f;
-    c.zslab = ctx->zslab;
-    c.remap = ctx->remap;
-    c.nbx = (g.nx + kShapes[ctx->shape].tx - 1) / kShapes[ctx->shape].tx;
-    c.nby = (g.ny + kShapes[ctx->shape].ty - 1) / kShapes[ctx->shape].ty;
-    c.nbz = (g.nz + ctx->zslab - 1) / ctx->zslab;
-    c.np = (long long)ctx->np;
-    c.aniso = p.aniso;
-    c.eps = (T)p.eps;
-    c.delta = (T)p.delta;
-    c.inv2dx = (T)(1.0 / (2.0 * p.dx));
-    c.smin = (T)(1e-12 / (p.dx * p.dx));
-    c.eta_c = (T)(p.W0 * p.W0 * p.dt / (kE2 * p.tau0 * p.dx * p.dx));
-    c.cphi_e2 = (T)(p.dt * p.W0 * p.W0 / (p.dx * p.tau0 * kE2));
-    c.dt_tau0 = (T)(p.dt / p.tau0);
-    c.lambda = (T)p.lambda;
-    c.Mcinf = (T)p.Mcinf;
-    c.k = (T)p.k;
-    c.D = (T)p.D;
-    c.inv_dt = (T)(1.0 / p.dt);
-    c.inv_dx2 = (T)(1.0 / (p.dx * p.dx));
-    c.jat_c = (T)(p.W0 / (2.0 * std::sqrt(2.0)));
-    const double etaU = p.D * p.dt / (kE2 * p.dx * p.dx) + 0.5;
-    const double etaT = p.kappa * p.dt / (kE2 * p.dx * p.dx) + 0.5;
-    c.omU = (T)(1.0 / etaU);
-    c.omT = (T)(1.0 / etaT);
-    c.etaU = (T)etaU;
-    c.dt = (T)p.dt;
-    c.jcoef = (T)(p.dt / (kE2 * p.dx) / etaU);
-    c.jt = (T)(p.dt / (kE2 * p.dx));
-    c.has_adv = 0;
-    for (int a = 0; a < 3; ++a) {
-        c.adv[a] = (T)(p.vel[a] * p.dt / (kE2 * p.dx));
-        if (p.vel[a] != 0.0) c.has_adv = 1;
-    }
-    return c;
-}
-
-bool has_advection(const lbpf_ctx* ctx) {
-    return ctx->prm.vel[0] != 0.0 || ctx->prm.vel[1] != 0.0 || ctx->prm.vel[2] != 0.0;
-}
-
-int default_shape(const lbpf_ctx* ctx) { return ctx->storage == LBPF_F64 ? 2 : 3; }
-
-int total_tiles(const lbpf_ctx* ctx) {
-    const int nbx = (ctx->grid.nx + kShapes[ctx->shape].tx - 1) / kShapes[ctx->shape].tx;
-    const int nby = (ctx->grid.ny + kShapes[ctx->shape].ty - 1) / kShapes[ctx->shape].ty;
-    const int nbz = (ctx->grid.nz + ctx->zslab - 1) / ctx->zslab;
-    return nbx * nby * nbz;
-}
-
-hipEvent_t get_event(lbpf_ctx* ctx) {
-    if (!ctx->pool.empty()) {
-        hipEvent_t e = ctx->pool.back();
-        ctx->pool.pop_back();
-        return e;
-    }
-    hipEvent_t e = nullptr;
-    if (hipEventCreate(&e) != hipSuccess) return nullptr;
-    return e;
-}
-
-// Launch wrapper: optional event pair around the launch.
-template <class F>
-lbpf_status timed(lbpf_ctx* ctx, int kind, F&& launch) {
-    hipEvent_t a = nullptr, b = nullptr;
-    if (ctx->timing) {
-        a = get_event(ctx);
-        b = get_event(ctx);
-        if (!a || !b) return fail(ctx, LBPF_EDEVICE, "hipEventCreate failed");
-        CHK(hipEventRecord(a, ctx->stream));
-    }
-    launch();
-    CHK(hipGetLastError());
-    if (ctx->timing) {
-        CHK(hipEventRecord(b, ctx->stream));
-        ctx->launches.push_back({kind, a, b});
-    }
-    return LBPF_OK;
-}
-
-// ---------------------------------------------------------------- dispatch
-template <class L, class T, class S, int TX, int TY, bool BUF>
-lbpf_status launch_step_b(lbpf_ctx* ctx) {
-    const Coef<T> c = make_coef<T>(ctx);
-    const int nb = total_tiles(ctx);
-    const int a = ctx->cur, b = 1 - ctx->cur;
-    lbpf_status st = timed(ctx, 0, [&] {
-        hipLaunchKernelGGL((k_phi<L, T, S, TX, TY, BUF>), dim3(nb), dim3(TX * TY), 0, ctx->stream, c,
-                           (const S*)ctx->pop[0][a], (S*)ctx->pop[0][b], (const T*)ctx->fld[0][a],
-                           (const T*)ctx->fld[1][a], (const T*)ctx->fld[2][a], (T*)ctx->fld[0][b]);
-    });
-    if (st) return st;
-    // the advection-diffusion variant exists for the default tile of each storage
-    constexpr bool kAdvTile = TX == 32 && (sizeof(T) == 8 ? TY == 4 : TY == 8);
-    if (c.has_adv && !kAdvTile) return fail(ctx, LBPF_EINVAL, "advection runs on the default tile shape only");
-    st = timed(ctx, 1, [&] {
-        auto args = [&](auto kern) {
-            hipLaunchKernelGGL(kern, dim3(nb), dim3(TX * TY), 0, ctx->stream, c, (const S*)ctx->pop[1][a],
-                               (S*)ctx->pop[1][b], (const S*)ctx->pop[2][a], (S*)ctx->pop[2][b],
-                               (const T*)ctx->fld[0][a], (const T*)ctx->fld[0][b], (const T*)ctx->fld[1][a],
-                               (const T*)ctx->fld[2][a], (T*)ctx->fld[1][b], (T*)ctx->fld[2][b]);
-        };
-        if constexpr (kAdvTile) {
-            if (c.has_adv) {
-                args(k_ut<L, T, S, TX, TY, BUF, true>);
-                return;
-            }
-        }
-        args(k_ut<L, T, S, TX, TY, BUF, false>);
-    });
-    if (st) return st;
-    ctx->cur = b;
-    return LBPF_OK;
-}
-
-// One buffer resource per field when its Q population arrays total < 4 GiB.
-template <class L, class T, class S, int TX, int TY>
-lbpf_status launch_step_t(lbpf_ctx* ctx) {
-    const size_t pbytes = (size_t)L::Q * ctx->np * sizeof(S);
-    if (pbytes < ((size_t)1 << 32) - 256) return launch_step_b<L, T, S, TX, TY, true>(ctx);
-    if constexpr (sizeof(T) == 8) return fail(ctx, LBPF_EINVAL, "FP64 verification build limited to < 4 GiB per field");
-    else return launch_step_b<L, T, S, TX, TY, false>(ctx);
-}
-
-// Static LDS of one block of k_ut, the larger of the two step kernels.
-template <class T, int TX, int TY>
-constexpr size_t lds_bytes() {
-    return 3 * (size_t)(TX + 4) * (TY + 4) * 2 * sizeof(T) + 3 * (size_t)(TX + 2) * (TY + 2) * 5 * sizeof(T) +
-           2 * (size_t)TX * TY * 4 * sizeof(T);
-}
-
-template <class T>
-bool shape_ok(int shape) {
-    switch (shape) {
-        case 0: return lds_bytes<T, 64, 2>() <= 65536;
-        case 1: return lds_bytes<T, 64, 4>() <= 65536;
-        case 2: return lds_bytes<T, 32, 4>() <= 65536;
-        case 3: return lds_bytes<T, 32, 8>() <= 65536;
-        case 4: return lds_bytes<T, 32, 16>() <= 65536 + 16384;
-    }
-    return false;
-}
-
-template <class L, class T, class S>
-lbpf_status launch_step_s(lbpf_ctx* ctx) {
-    if constexpr (sizeof(T) == 8) {
-        switch (ctx->shape) {
-            case 0: return launch_step_t<L, T, S, 64, 2>(ctx);
-            case 2: return launch_step_t<L, T, S, 32, 4>(ctx);
-        }
-    } else {
-        switch (ctx->shape) {
-            case 0: return launch_step_t<L, T, S, 64, 2>(ctx);
-            case 1: return launch_step_t<L, T, S, 64, 4>(ctx);
-            case 2: return launch_step_t<L, T, S, 32, 4>(ctx);
-            case 3: return launch_step_t<L, T, S, 32, 8>(ctx);
-            case 4: return launch_step_t<L, T, S, 32, 16>(ctx);
-        }
-    }
-    return fail(ctx, LBPF_EINVAL, "tile shape not available for this storage");
-}
 
 template <class L>
 lbpf_status launch_step_l(lbpf_ctx* ctx) {
@@ -423,6 +251,25 @@ bool healthy(const lbpf_reductions& r) {
     return r.nonfinite == 0.0 && r.phi_max <= 1.0 + 1e-3 && r.phi_min >= -1.0 - 1e-3;
 }
 
+// Waits for the stream and moves the recorded launch events back to the
+// pool, adding their durations to ms[kind] and counts to n[kind] when given.
+lbpf_status drain_launches(lbpf_ctx* ctx, double* ms, int64_t* n) {
+    CHK(hipStreamSynchronize(ctx->stream));
+    lbpf_status st = LBPF_OK;
+    for (auto& l : ctx->launches) {
+        if (ms && !st) {
+            float t = 0.f;
+            if (hipEventElapsedTime(&t, l.a, l.b) != hipSuccess) st = fail(ctx, LBPF_EDEVICE, "event timing");
+            ms[l.kind] += t;
+            n[l.kind] += 1;
+        }
+        ctx->pool.push_back(l.a);
+        ctx->pool.push_back(l.b);
+    }
+    ctx->launches.clear();
+    return st;
+}
+
 void free_all(lbpf_ctx* ctx) {
     if (ctx->gexec) (void)hipGraphExecDestroy(ctx->gexec);
     ctx->gexec = nullptr;
@@ -508,8 +355,11 @@ lbpf_status lbpf_create(const lbpf_grid* grid, const lbpf_params* params, void* 
     ctx->storage = g.storage;
     ctx->sbytes = (size_t)lbpf_storage_bytes(g.storage);
     ctx->tbytes = g.storage == LBPF_F64 ? 8 : 4;
-    ctx->shape = g.storage == LBPF_F64 ? 2 : 3;
-    ctx->zslab = ctx->sbytes == 2 ? 8 : 4;   // measured best at 256^3 and 512^3
+    for (int k = 0; k < 2; ++k) {
+        ctx->shape[k] = kDefaultShape[k][g.storage];
+        ctx->zslab[k] = kDefaultZslab[k][g.storage];
+        ctx->remap[k] = 1;
+    }
     ctx->n = (size_t)g.nx * g.ny * g.nz;
     ctx->np = (ctx->n + 63) / 64 * 64;
     hipError_t e = hipSuccess;
@@ -594,7 +444,12 @@ lbpf_status capture_graph(lbpf_ctx* ctx) {
         ctx->gexec = nullptr;
         return fail(ctx, LBPF_EDEVICE, std::string("graph instantiate: ") + hipGetErrorString(e2));
     }
-    ctx->g_shape = ctx->shape; ctx->g_zslab = ctx->zslab; ctx->g_remap = ctx->remap; ctx->g_cur = cur0;
+    for (int k = 0; k < 2; ++k) {
+        ctx->g_shape[k] = ctx->shape[k];
+        ctx->g_zslab[k] = ctx->zslab[k];
+        ctx->g_remap[k] = ctx->remap[k];
+    }
+    ctx->g_cur = cur0;
     return LBPF_OK;
 }
 
@@ -609,8 +464,11 @@ lbpf_status lbpf_step(lbpf_ctx* ctx, int64_t nsteps) {
     while (left > 0) {
         const int64_t to_red = R > 0 ? R - ctx->step % R : left;
         if (G > 0 && !ctx->timing && std::min(left, to_red) >= G) {
-            if (!ctx->gexec || ctx->g_shape != ctx->shape || ctx->g_zslab != ctx->zslab ||
-                ctx->g_remap != ctx->remap || ctx->g_cur != ctx->cur) {
+            bool same = ctx->gexec && ctx->g_cur == ctx->cur;
+            for (int k = 0; k < 2; ++k)
+                same = same && ctx->g_shape[k] == ctx->shape[k] && ctx->g_zslab[k] == ctx->zslab[k] &&
+                       ctx->g_remap[k] == ctx->remap[k];
+            if (!same) {
                 lbpf_status st = capture_graph(ctx);
                 if (st) return st;
             }
@@ -764,12 +622,8 @@ lbpf_status lbpf_debug_stream_only(lbpf_ctx* ctx, int64_t nsteps) {
 
 lbpf_status lbpf_set_timing(lbpf_ctx* ctx, int32_t enable) {
     if (!ctx) return LBPF_EINVAL;
-    CHK(hipStreamSynchronize(ctx->stream));
-    for (auto& l : ctx->launches) {
-        ctx->pool.push_back(l.a);
-        ctx->pool.push_back(l.b);
-    }
-    ctx->launches.clear();
+    const lbpf_status st = drain_launches(ctx, nullptr, nullptr);
+    if (st) return st;
     for (int i = 0; i < 3; ++i) { ctx->t_ms[i] = 0; ctx->t_n[i] = 0; }
     ctx->timing = enable != 0;
     return LBPF_OK;
@@ -777,47 +631,61 @@ lbpf_status lbpf_set_timing(lbpf_ctx* ctx, int32_t enable) {
 
 lbpf_status lbpf_kernel_times(lbpf_ctx* ctx, double ms[3], int64_t launches[3]) {
     if (!ctx || !ms || !launches) return fail(ctx, LBPF_EINVAL, "bad argument");
-    CHK(hipStreamSynchronize(ctx->stream));
-    for (auto& l : ctx->launches) {
-        float t = 0.f;
-        CHK(hipEventElapsedTime(&t, l.a, l.b));
-        ctx->t_ms[l.kind] += t;
-        ctx->t_n[l.kind] += 1;
-        ctx->pool.push_back(l.a);
-        ctx->pool.push_back(l.b);
-    }
-    ctx->launches.clear();
+    const lbpf_status st = drain_launches(ctx, ctx->t_ms, ctx->t_n);
+    if (st) return st;
     for (int i = 0; i < 3; ++i) { ms[i] = ctx->t_ms[i]; launches[i] = ctx->t_n[i]; }
     return LBPF_OK;
 }
 
-lbpf_status lbpf_set_launch(lbpf_ctx* ctx, int32_t tile_x, int32_t tile_y, int32_t zslab,
-                            int32_t xcd_remap) {
+lbpf_status lbpf_set_kernel_launch(lbpf_ctx* ctx, int32_t kernel, int32_t tile_x, int32_t tile_y,
+                                   int32_t zslab, int32_t xcd_remap) {
     if (!ctx) return LBPF_EINVAL;
+    if (kernel != K_PHI && kernel != K_UT) return fail(ctx, LBPF_EINVAL, "kernel must be 0 (k_phi) or 1 (k_ut)");
     if (zslab < 1) return fail(ctx, LBPF_EINVAL, "zslab < 1");
     if (xcd_remap != 0 && xcd_remap != 1) return fail(ctx, LBPF_EINVAL, "xcd_remap must be 0 or 1");
     for (int i = 0; i < kNumShapes; ++i) {
         if (kShapes[i].tx != tile_x || kShapes[i].ty != tile_y) continue;
         const bool ok = ctx->storage == LBPF_F64 ? (i == 0 || i == 2) : true;
         if (!ok) return fail(ctx, LBPF_EINVAL, "tile shape not available for FP64 storage");
-        if (has_advection(ctx) && i != default_shape(ctx))
-            return fail(ctx, LBPF_EINVAL, "advection runs on the default tile shape only");
-        ctx->shape = i;
-        ctx->zslab = zslab;
-        ctx->remap = xcd_remap;
+        if (kernel == K_UT && has_advection(ctx) && i != default_shape(ctx, K_UT))
+            return fail(ctx, LBPF_EINVAL, "advection runs on the default k_ut tile only");
+        ctx->shape[kernel] = i;
+        ctx->zslab[kernel] = zslab;
+        ctx->remap[kernel] = xcd_remap;
         return LBPF_OK;
     }
     return fail(ctx, LBPF_EINVAL, "unsupported tile shape");
 }
 
+lbpf_status lbpf_get_kernel_launch(lbpf_ctx* ctx, int32_t kernel, int32_t* tile_x, int32_t* tile_y,
+                                   int32_t* zslab, int32_t* xcd_remap) {
+    if (!ctx || !tile_x || !tile_y || !zslab || !xcd_remap) return LBPF_EINVAL;
+    if (kernel != K_PHI && kernel != K_UT) return fail(ctx, LBPF_EINVAL, "kernel must be 0 (k_phi) or 1 (k_ut)");
+    *tile_x = kShapes[ctx->shape[kernel]].tx;
+    *tile_y = kShapes[ctx->shape[kernel]].ty;
+    *zslab = ctx->zslab[kernel];
+    *xcd_remap = ctx->remap[kernel];
+    return LBPF_OK;
+}
+
+lbpf_status lbpf_set_launch(lbpf_ctx* ctx, int32_t tile_x, int32_t tile_y, int32_t zslab,
+                            int32_t xcd_remap) {
+    if (!ctx) return LBPF_EINVAL;
+    const int s0[2] = {ctx->shape[0], ctx->shape[1]}, z0[2] = {ctx->zslab[0], ctx->zslab[1]},
+              r0[2] = {ctx->remap[0], ctx->remap[1]};
+    for (int k = 0; k < 2; ++k) {
+        const lbpf_status st = lbpf_set_kernel_launch(ctx, k, tile_x, tile_y, zslab, xcd_remap);
+        if (st) {   // all or nothing
+            for (int j = 0; j < 2; ++j) { ctx->shape[j] = s0[j]; ctx->zslab[j] = z0[j]; ctx->remap[j] = r0[j]; }
+            return st;
+        }
+    }
+    return LBPF_OK;
+}
+
 lbpf_status lbpf_get_launch(lbpf_ctx* ctx, int32_t* tile_x, int32_t* tile_y, int32_t* zslab,
                             int32_t* xcd_remap) {
-    if (!ctx || !tile_x || !tile_y || !zslab || !xcd_remap) return LBPF_EINVAL;
-    *tile_x = kShapes[ctx->shape].tx;
-    *tile_y = kShapes[ctx->shape].ty;
-    *zslab = ctx->zslab;
-    *xcd_remap = ctx->remap;
-    return LBPF_OK;
+    return lbpf_get_kernel_launch(ctx, K_UT, tile_x, tile_y, zslab, xcd_remap);
 }
 
 lbpf_status lbpf_autotune(lbpf_ctx* ctx, int32_t steps_per_candidate, double* best_ms_per_step) {
@@ -835,56 +703,68 @@ lbpf_status lbpf_autotune(lbpf_ctx* ctx, int32_t steps_per_candidate, double* be
         CHK(hipMemcpyAsync((char*)snap + 3 * pbytes + f * fbytes, ctx->fld[f][cur0], fbytes,
                            hipMemcpyDeviceToDevice, ctx->stream));
     }
+    // launches timed so far count for the caller; the tuner's own stay apart
+    lbpf_status st = drain_launches(ctx, ctx->t_ms, ctx->t_n);
+    if (st) { (void)hipFree(snap); return st; }
     const bool was_timing = ctx->timing;
-    ctx->timing = false;
-    const int shape0 = ctx->shape, zslab0 = ctx->zslab, remap0 = ctx->remap;
-    int best_shape = shape0, best_z = zslab0, best_r = remap0;
-    double best = 1e300;
-    hipEvent_t ea = nullptr, eb = nullptr;
-    lbpf_status st = LBPF_OK;
-    if (hipEventCreate(&ea) != hipSuccess || hipEventCreate(&eb) != hipSuccess) st = fail(ctx, LBPF_EDEVICE, "hipEventCreate");
-    const int zs_list[] = {2, 4, 8, 16, 32};
+    ctx->timing = true;
+    const int s0[2] = {ctx->shape[0], ctx->shape[1]}, z0[2] = {ctx->zslab[0], ctx->zslab[1]},
+              r0[2] = {ctx->remap[0], ctx->remap[1]};
+    int bs[2] = {s0[0], s0[1]}, bz[2] = {z0[0], z0[1]}, br[2] = {r0[0], r0[1]};
+    double best[2] = {1e300, 1e300};
+    // k_phi and k_ut are separate launches: each keeps the launch that is
+    // fastest for it
+    const int zs_list[] = {2, 4, 6, 8, 12, 16};
+    constexpr int NZ = sizeof(zs_list) / sizeof(zs_list[0]);
     for (int sh = 0; sh < kNumShapes && !st; ++sh) {
-        if (ctx->storage == LBPF_F64 ? !(sh == 0 || sh == 2) : false) continue;
-        if (has_advection(ctx) && sh != default_shape(ctx)) continue;
-        for (int zi = 0; zi < 10 && !st; ++zi) {
-            const int zsl = zs_list[zi % 5];
-            if (zsl > 2 * ctx->grid.nz && zi % 5 > 0) continue;
-            ctx->shape = sh;
-            ctx->zslab = zsl;
-            ctx->remap = zi / 5;
-            for (int w = 0; w < 2 && !st; ++w) st = launch_step(ctx);
-            if (st) break;
-            if (hipEventRecord(ea, ctx->stream) != hipSuccess) { st = fail(ctx, LBPF_EDEVICE, "event"); break; }
-            for (int k = 0; k < steps_per_candidate && !st; ++k) st = launch_step(ctx);
-            if (st) break;
-            float ms = 0.f;
-            if (hipEventRecord(eb, ctx->stream) != hipSuccess || hipEventSynchronize(eb) != hipSuccess ||
-                hipEventElapsedTime(&ms, ea, eb) != hipSuccess) {
-                st = fail(ctx, LBPF_EDEVICE, "event timing");
-                break;
+        if (ctx->storage == LBPF_F64 && !(sh == 0 || sh == 2)) continue;
+        for (int zi = 0; zi < 2 * NZ && !st; ++zi) {
+            const int zsl = zs_list[zi % NZ];
+            if (zsl > 2 * ctx->grid.nz && zi % NZ > 0) continue;
+            for (int k = 0; k < 2; ++k) {
+                ctx->shape[k] = sh;
+                ctx->zslab[k] = zsl;
+                ctx->remap[k] = zi / NZ;
             }
-            const double per = ms / steps_per_candidate;
-            if (per < best) { best = per; best_shape = sh; best_z = zsl; best_r = ctx->remap; }
+            if (has_advection(ctx)) ctx->shape[K_UT] = default_shape(ctx, K_UT);
+            for (int w = 0; w < 2 && !st; ++w) st = launch_step(ctx);
+            if (!st) st = drain_launches(ctx, nullptr, nullptr);
+            for (int k = 0; k < steps_per_candidate && !st; ++k) st = launch_step(ctx);
+            double ms[3] = {0, 0, 0};
+            int64_t cnt[3] = {0, 0, 0};
+            if (!st) st = drain_launches(ctx, ms, cnt);
+            if (st) break;
+            for (int k = 0; k < 2; ++k) {
+                const double per = ms[k] / steps_per_candidate;
+                if (per < best[k]) {
+                    best[k] = per;
+                    bs[k] = ctx->shape[k];
+                    bz[k] = zsl;
+                    br[k] = ctx->remap[k];
+                }
+            }
         }
     }
-    if (ea) (void)hipEventDestroy(ea);
-    if (eb) (void)hipEventDestroy(eb);
-    // restore the state and keep the best launch shape
+    // restore the state and keep the best launch of each kernel
     ctx->cur = cur0;
     for (int f = 0; f < 3; ++f) {
         (void)hipMemcpyAsync(ctx->pop[f][cur0], (char*)snap + f * pbytes, pbytes, hipMemcpyDeviceToDevice, ctx->stream);
         (void)hipMemcpyAsync(ctx->fld[f][cur0], (char*)snap + 3 * pbytes + f * fbytes, fbytes,
                              hipMemcpyDeviceToDevice, ctx->stream);
     }
-    (void)hipStreamSynchronize(ctx->stream);
+    (void)drain_launches(ctx, nullptr, nullptr);
     (void)hipFree(snap);
     ctx->timing = was_timing;
-    if (st) { ctx->shape = shape0; ctx->zslab = zslab0; ctx->remap = remap0; return st; }
-    ctx->shape = best_shape;
-    ctx->zslab = best_z;
-    ctx->remap = best_r;
-    if (best_ms_per_step) *best_ms_per_step = best;
+    const int* keep_s = st ? s0 : bs;
+    const int* keep_z = st ? z0 : bz;
+    const int* keep_r = st ? r0 : br;
+    for (int k = 0; k < 2; ++k) {
+        ctx->shape[k] = keep_s[k];
+        ctx->zslab[k] = keep_z[k];
+        ctx->remap[k] = keep_r[k];
+    }
+    if (st) return st;
+    if (best_ms_per_step) *best_ms_per_step = best[0] + best[1];
     return LBPF_OK;
 }
 
@@ -978,9 +858,11 @@ lbpf_status batch_build_t(lbpf_batch* b) {
     std::vector<std::vector<int2>> items(2);
     for (int d = 0; d < nd; ++d) {
         lbpf_ctx* c = b->dom[d];
-        c->shape = b->shape;
-        c->zslab = b->zslab;
-        c->remap = 0;   // the work table carries the XCD order
+        for (int k = 0; k < 2; ++k) {   // one tiling for both batch kernels
+            c->shape[k] = b->shape;
+            c->zslab[k] = b->zslab;
+            c->remap[k] = 0;   // the work table carries the XCD order
+        }
         desc[d].c = make_coef<T>(c);
         for (int f = 0; f < 3; ++f)
             for (int par = 0; par < 2; ++par) {
@@ -988,7 +870,7 @@ lbpf_status batch_build_t(lbpf_batch* b) {
                 desc[d].fld[f][par] = (T*)c->fld[f][par];
             }
         const int li = c->q == 15 ? 0 : 1;
-        const int nt = total_tiles(c);
+        const int nt = total_tiles(c, K_PHI);
         for (int t = 0; t < nt; ++t) items[li].push_back(int2{d, t});
     }
     if (!b->d_desc) BCHK(hipMalloc(&b->d_desc, sizeof(DomainDesc<T>) * nd));
@@ -1075,7 +957,7 @@ lbpf_status lbpf_batch_create(int32_t n, const lbpf_grid* grids, const lbpf_para
     if (!b) return bfail(nullptr, LBPF_ENOMEM, "host allocation failed");
     b->storage = grids[0].storage;
     b->shape = b->storage == LBPF_F64 ? 2 : 3;   // 32x4 (FP64) or 32x8 tiles
-    b->zslab = lbpf_storage_bytes(b->storage) == 2 ? 8 : 4;   // as a single domain
+    b->zslab = lbpf_storage_bytes(b->storage) == 2 ? 8 : 4;   // measured for the batch kernels
     b->stream = (hipStream_t)hip_stream;
     if (!b->stream) {
         if (hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking) != hipSuccess) {

@@ -60,7 +60,8 @@ SYMBOLS = ["lbpf_create", "lbpf_destroy", "lbpf_set_fields", "lbpf_step", "lbpf_
            "lbpf_read", "lbpf_history", "lbpf_read_populations", "lbpf_write_populations",
            "lbpf_read_populations_f64",
            "lbpf_debug_stream_only", "lbpf_set_timing", "lbpf_kernel_times",
-           "lbpf_set_launch", "lbpf_get_launch", "lbpf_autotune",
+           "lbpf_set_launch", "lbpf_get_launch", "lbpf_set_kernel_launch",
+           "lbpf_get_kernel_launch", "lbpf_autotune",
            "lbpf_storage_bytes", "lbpf_bench_copy", "lbpf_last_error", "lbpf_set_graph",
            "lbpf_batch_create", "lbpf_batch_domain", "lbpf_batch_set_graph", "lbpf_batch_step",
            "lbpf_batch_sync", "lbpf_batch_destroy", "lbpf_batch_last_error",
@@ -99,6 +100,10 @@ def load():
                             ctypes.c_int),
         "lbpf_get_launch": ([vp, P(ctypes.c_int32), P(ctypes.c_int32), P(ctypes.c_int32),
                              P(ctypes.c_int32)], ctypes.c_int),
+        "lbpf_set_kernel_launch": ([vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                    ctypes.c_int32], ctypes.c_int),
+        "lbpf_get_kernel_launch": ([vp, ctypes.c_int32, P(ctypes.c_int32), P(ctypes.c_int32),
+                                    P(ctypes.c_int32), P(ctypes.c_int32)], ctypes.c_int),
         "lbpf_autotune": ([vp, ctypes.c_int32, dp], ctypes.c_int),
         "lbpf_storage_bytes": ([ctypes.c_int32], ctypes.c_int32),
         "lbpf_bench_copy": ([vp, vp, ctypes.c_int64, vp], ctypes.c_int),
@@ -292,15 +297,32 @@ class Solver:
                                               int(xcd_remap)))
 
     def get_launch(self):
+        """(tile_x, tile_y, zslab, xcd_remap) of k_ut."""
         a, b, c, d = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
         self._check(self._lib.lbpf_get_launch(self._h, ctypes.byref(a), ctypes.byref(b),
                                               ctypes.byref(c), ctypes.byref(d)))
         return a.value, b.value, c.value, d.value
 
+    def set_kernel_launch(self, kernel, tile_x, tile_y, zslab, xcd_remap=1):
+        """kernel 0: k_phi, 1: k_ut."""
+        self._check(self._lib.lbpf_set_kernel_launch(self._h, int(kernel), int(tile_x), int(tile_y),
+                                                     int(zslab), int(xcd_remap)))
+
+    def get_kernel_launch(self, kernel):
+        a, b, c, d = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        self._check(self._lib.lbpf_get_kernel_launch(self._h, int(kernel), ctypes.byref(a),
+                                                     ctypes.byref(b), ctypes.byref(c), ctypes.byref(d)))
+        return a.value, b.value, c.value, d.value
+
+    def launches(self):
+        """{"k_phi": (tx, ty, zslab, remap), "k_ut": (...)}."""
+        return {"k_phi": self.get_kernel_launch(0), "k_ut": self.get_kernel_launch(1)}
+
     def autotune(self, steps_per_candidate=10):
+        """Returns ({"k_phi": launch, "k_ut": launch}, best ms per step)."""
         best = ctypes.c_double()
         self._check(self._lib.lbpf_autotune(self._h, int(steps_per_candidate), ctypes.byref(best)))
-        return self.get_launch(), best.value
+        return self.launches(), best.value
 
     def kernel_times(self):
         ms = (ctypes.c_double * 3)()

@@ -183,12 +183,22 @@ def test_advection_matches_oracle(lattice, storage, tol):
 
 
 def test_advection_keeps_default_tile():
+    """With an advective velocity k_ut stays on its default tile (the only
+    one with the advective variant); k_phi may take any."""
     pb = dataclasses.replace(ragged_problem(19, 0), vel=ADV_VEL)
     s = make_gpu(pb, storage="f32")
-    tx, ty, zs, rm = s.get_launch()
-    assert (tx, ty) == (32, 8)
-    with pytest.raises(lbpf.LbpfError, match="default tile"):
-        s.set_launch(64, 4, zs, rm)
-    s.set_launch(tx, ty, zs, rm)                      # the default shape stays allowed
-    (shape, _), = [s.autotune(2)]
-    assert shape[:2] == (32, 8)
+    ut = s.get_kernel_launch(1)
+    phi = s.get_kernel_launch(0)
+    other = (32, 16) if ut[:2] != (32, 16) else (32, 4)
+    with pytest.raises(lbpf.LbpfError, match="default k_ut tile"):
+        s.set_launch(other[0], other[1], 4, 1)
+    assert s.get_kernel_launch(1) == ut and s.get_kernel_launch(0) == phi   # all or nothing
+    s.set_kernel_launch(0, other[0], other[1], 4, 1)                         # k_phi is free
+    s.set_launch(ut[0], ut[1], ut[2], ut[3])
+    launches, _ = s.autotune(2)
+    assert launches["k_ut"][:2] == ut[:2]
+    o = make_oracle(pb)
+    s.step(20)
+    o.step(20)
+    for a, b in zip(s.read()[:3], o.fields()):
+        assert maxabs(a, b) <= 1e-5

@@ -40,6 +40,17 @@ def test_launch_shape_does_not_change_results():
         else:
             for a, b in zip(ref, out):
                 assert np.array_equal(a, b), launch
+    # the two kernels on different launches
+    for phi_l, ut_l in [((64, 4, 6, 1), (32, 8, 2, 0)), ((32, 16, 3, 0), (64, 2, 5, 1))]:
+        s = make_gpu(pb, "f32")
+        s.set_kernel_launch(0, *phi_l)
+        s.set_kernel_launch(1, *ut_l)
+        assert s.launches() == {"k_phi": phi_l, "k_ut": ut_l}
+        s.step(40)
+        out = fields(s)
+        s.close()
+        for a, b in zip(ref, out):
+            assert np.array_equal(a, b), (phi_l, ut_l)
 
 
 def test_graph_replay_equals_plain_launches():

@@ -64,6 +64,8 @@ def _load():
     lib.orc_destroy.argtypes = [ctypes.c_void_p]
     lib.orc_init.argtypes = [ctypes.c_void_p, dp, dp, dp]
     lib.orc_step.argtypes = [ctypes.c_void_p, ctypes.c_int64]
+    lib.orc_set_velocity_field.restype = ctypes.c_int
+    lib.orc_set_velocity_field.argtypes = [ctypes.c_void_p, dp, dp, dp]
     lib.orc_stream_only.argtypes = [ctypes.c_void_p, ctypes.c_int64]
     lib.orc_fields.argtypes = [ctypes.c_void_p, dp, dp, dp]
     lib.orc_get_pops.argtypes = [ctypes.c_void_p, ctypes.c_int, dp]
@@ -181,6 +183,17 @@ class Oracle:
 
     def step(self, n=1):
         self._lib.orc_step(self._h, int(n))
+
+    def set_velocity_field(self, vx, vy, vz):
+        """Per-node advective velocity of the heat equation, arrays of shape
+        (nz, ny, nx); None for all three clears it (the uniform vel applies)."""
+        if vx is None and vy is None and vz is None:
+            rc = self._lib.orc_set_velocity_field(self._h, None, None, None)
+        else:
+            self._vf = [_f64(v).reshape(self.shape) for v in (vx, vy, vz)]
+            rc = self._lib.orc_set_velocity_field(self._h, *[_dptr(a) for a in self._vf])
+        if rc != 0:
+            raise ValueError("orc_set_velocity_field failed")
 
     def stream_only(self, n=1):
         self._lib.orc_stream_only(self._h, int(n))

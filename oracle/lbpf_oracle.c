@@ -67,6 +67,7 @@ struct orc_ctx {
     int *bnode;
     /* supersaturation / heat node terms */
     double *r, *wz, *qf, *J, *srcU, *Qth;
+    double *vfield;      /* NULL, or per-node advective velocity [3][n] */
     int64_t steps;
 };
 
@@ -251,6 +252,7 @@ void orc_destroy(orc_ctx* c)
     free(c->phi); free(c->U); free(c->th); free(c->phi_old);
     free(c->as2); free(c->eta); free(c->Nvec); free(c->Qphi); free(c->bnode);
     free(c->r); free(c->wz); free(c->qf); free(c->J); free(c->srcU); free(c->Qth);
+    free(c->vfield);
     free(c);
 }
 
@@ -509,13 +511,35 @@ static void ut_terms(orc_ctx* c, const double* phin, const double* phio,
     }
 }
 
-/* Heat equilibrium, eq. (EqFunction_Tempr); with an advective velocity v the
- * advection-diffusion form of Sec. 3.1: w_i theta [1 + e^-2 (e_i . v) dt/dx]. */
-static double theta_eq(const orc_ctx* c, int i, double t)
+/* Heat equilibrium at node s, eq. (EqFunction_Tempr); with an advective
+ * velocity v the advection-diffusion form of Sec. 3.1:
+ * w_i theta [1 + e^-2 (e_i . v) dt/dx].  v is the node's entry of the
+ * velocity field when one is set, else the uniform p->vel. */
+static double theta_eq(const orc_ctx* c, int i, size_t s, double t)
 {
     const orc_params* p = &c->p;
-    const double ev = c->e[i][0]*p->vel[0] + c->e[i][1]*p->vel[1] + c->e[i][2]*p->vel[2];
+    double v[3] = {p->vel[0], p->vel[1], p->vel[2]};
+    if (c->vfield)
+        for (int a = 0; a < 3; ++a) v[a] = c->vfield[(size_t)a * c->n + s];
+    const double ev = c->e[i][0]*v[0] + c->e[i][1]*v[1] + c->e[i][2]*v[2];
     return c->w[i] * t * (1.0 + ev * p->dt / (c->e2 * p->dx));
+}
+
+int orc_set_velocity_field(orc_ctx* c, const double* vx, const double* vy, const double* vz)
+{
+    const size_t n = c->n;
+    if (!vx && !vy && !vz) {
+        free(c->vfield);
+        c->vfield = NULL;
+        return 0;
+    }
+    if (!vx || !vy || !vz) return -1;
+    if (!c->vfield) c->vfield = (double*)malloc(3 * n * sizeof(double));
+    if (!c->vfield) return -1;
+    memcpy(c->vfield, vx, n * sizeof(double));
+    memcpy(c->vfield + n, vy, n * sizeof(double));
+    memcpy(c->vfield + 2 * n, vz, n * sizeof(double));
+    return 0;
 }
 
 /* Supersaturation and heat collisions, eqs. (LBE_Eq_Transport), (LBE_Eq_Temp). */
@@ -534,7 +558,7 @@ static void ut_collide(orc_ctx* c)
             const size_t o = (size_t)i*n + (size_t)s;
             const double eJ = c->e[i][0]*J[0] + c->e[i][1]*J[1] + c->e[i][2]*J[2];
             const double heq = c->A[i]*u + c->B[i]*(c->r[s]*u + eJ * p->dt / (c->e2 * p->dx));
-            const double feq = theta_eq(c, i, t);
+            const double feq = theta_eq(c, i, (size_t)s, t);
             const double hi = c->pop[1][o], fi = c->pop[2][o];
             c->star[1][o] = hi - (hi - heq) / etaU + c->w[i] * c->srcU[s] * p->dt;
             c->star[2][o] = fi - (fi - feq) / etaT + c->w[i] * c->Qth[s] * p->dt;
@@ -563,7 +587,7 @@ int orc_init(orc_ctx* c, const double* phi, const double* U, const double* theta
         for (int i = 0; i < c->q; ++i) {
             c->pop[0][(size_t)i*n + s] = geq[i];
             c->pop[1][(size_t)i*n + s] = heq[i];
-            c->pop[2][(size_t)i*n + s] = theta_eq(c, i, c->th[s]);
+            c->pop[2][(size_t)i*n + s] = theta_eq(c, i, s, c->th[s]);
         }
     }
     c->steps = 0;

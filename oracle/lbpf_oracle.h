@@ -61,6 +61,10 @@ orc_ctx* orc_create(const orc_params* p);
 void     orc_destroy(orc_ctx* c);
 /* Initial populations = equilibria of the given fields. */
 int      orc_init(orc_ctx* c, const double* phi, const double* U, const double* theta);
+/* Per-node advective velocity of the heat equation (three arrays of n
+ * values, physical units, copied), used instead of p->vel; all three NULL
+ * clears it.  Returns 0, or -1 (some but not all NULL, out of memory). */
+int      orc_set_velocity_field(orc_ctx* c, const double* vx, const double* vy, const double* vz);
 /* nsteps full time steps (phi first, then U and theta). */
 int      orc_step(orc_ctx* c, int64_t nsteps);
 /* Streaming only (collision = identity), used to check the permutation. */

@@ -422,3 +422,52 @@ def test_advected_gaussian_heat_equation(lattice):
     a.step(10)
     b.step(10)
     assert np.array_equal(a.fields()[2], b.fields()[2])
+
+
+@pytest.mark.parametrize("lattice", [19, 7])
+def test_sheared_gaussian_moments(lattice):
+    """Advection-diffusion equilibrium of Sec. 3.1 with a per-node velocity:
+    a Gaussian theta pulse in the plane shear flow v = (a (z - z0), 0, 0).
+    The heat equation's moments have closed forms there: the x-centroid moves
+    at a (<z> - z0), <z> stays put, sigma_xz grows as a (sigma_zz0 t +
+    kappa t^2), sigma_zz as 2 kappa t and sigma_xx as 2 kappa t +
+    a^2 (sigma_zz0 t^2 + 2 kappa t^3 / 3).  The centroid motion is exact in
+    the scheme (the equilibrium's first moment is v theta, and sum v theta
+    stays constant); the second moments agree to O(dt).  A uniform field
+    reproduces the uniform-velocity run bit for bit."""
+    n, steps, kappa, a, z0 = 64, 60, 0.1, 0.004, 31.5
+    kw = dict(lattice=lattice, walls=(NOFLUX,) * 6, dx=1.0, dt=1.0, W0=1.0, tau0=1.0, lam=0.0,
+              Mcinf=0.0, k=0.15, D=0.1, kappa=kappa, eps=0.0)
+    z, y, x = np.meshgrid(*(np.arange(n, dtype=float),) * 3, indexing="ij")
+    th0 = np.exp(-((x - 31.5) ** 2 + (y - 32.0) ** 2 + (z - 36.5) ** 2) / (2 * 3.0 ** 2))
+    phi0, U0 = -np.ones_like(th0), np.zeros_like(th0)
+
+    def moments(th):
+        m = th.sum()
+        cx, cz = (x * th).sum() / m, (z * th).sum() / m
+        return (m, cx, cz, ((x - cx) * (z - cz) * th).sum() / m, ((z - cz) ** 2 * th).sum() / m,
+                ((x - cx) ** 2 * th).sum() / m)
+
+    o = Oracle(n, n, n, **kw)
+    o.set_velocity_field(a * (z - z0), np.zeros_like(x), np.zeros_like(x))
+    o.init(phi0, U0, th0)
+    m0, cx0, cz0, sxz0, szz0, sxx0 = moments(th0)
+    o.step(steps)
+    m1, cx1, cz1, sxz1, szz1, sxx1 = moments(o.fields()[2])
+    t = steps
+    assert abs(m1 - m0) < 1e-10 * m0
+    assert abs((cx1 - cx0) - a * (cz0 - z0) * t) < 1e-6
+    assert abs(cz1 - cz0) < 1e-6
+    assert abs((sxz1 - sxz0) - a * (szz0 * t + kappa * t * t)) < 0.02 * a * (szz0 * t + kappa * t * t)
+    assert abs((szz1 - szz0) - 2 * kappa * t) < 0.02 * 2 * kappa * t
+    sxx_exact = 2 * kappa * t + a * a * (szz0 * t * t + 2 * kappa * t ** 3 / 3)
+    assert abs((sxx1 - sxx0) - sxx_exact) < 0.02 * sxx_exact
+    # a uniform field is the uniform velocity
+    v = (0.03, -0.02, 0.01)
+    f = Oracle(n, n, n, **kw)
+    f.set_velocity_field(*(np.full_like(x, c) for c in v))
+    u = Oracle(n, n, n, vel=v, **kw)
+    for s in (f, u):
+        s.init(phi0, U0, th0)
+        s.step(5)
+    assert all(np.array_equal(p, q) for p, q in zip(f.fields(), u.fields()))

@@ -221,6 +221,20 @@ lbpf_status lbpf_read_populations_f64(lbpf_ctx* ctx, int32_t field, double* dst)
  * bits, with the wall rules: checks the index mapping.  Asynchronous. */
 lbpf_status lbpf_debug_stream_only(lbpf_ctx* ctx, int64_t nsteps);
 
+/* Per-node advective velocity of the heat equation (Sec. 3.1: the theta
+ * equilibrium w_i theta (1 + e_i.v dt / (e^2 dx)) with v = v(x)), the step
+ * toward a coupled flow solver that Sec. 5 outlines.  vx, vy, vz: host
+ * arrays of n doubles each, same layout as the fields, physical units;
+ * copied to the device in the compute type (FP32, FP64 for FP64 storage).
+ * The field replaces lbpf_params.vel; all three NULL removes it.  It acts
+ * from the next step and in the next lbpf_set_fields (whose theta
+ * populations start from the advective equilibrium: set the field first to
+ * start there).  Puts k_ut back on its default tile, the only one with the
+ * advective variant, and drops a captured step graph.  Synchronises.
+ * Errors: EINVAL (one or two NULL, non-finite value), ESTATE (a batch
+ * member), ENOMEM. */
+lbpf_status lbpf_set_velocity_field(lbpf_ctx* ctx, const double* vx, const double* vy, const double* vz);
+
 /* Per-kernel timing with HIP events recorded on the context stream around
  * each launch.  Enabling resets the accumulators.  lbpf_kernel_times
  * synchronises and returns the summed milliseconds and launch counts of the

@@ -175,7 +175,8 @@ struct Coef {
     T jcoef;           // omU dt / (e^2 dx)
     T jt;              // dt / (e^2 dx)
     T adv[3];          // v dt / (e^2 dx): advection-diffusion heat equilibrium (Sec. 3.1)
-    int has_adv;       // v != 0
+    const T* advf;     // NULL, or v dt / (e^2 dx) per node, [3][nodes], replacing adv
+    int has_adv;       // v != 0 or a velocity field
 };
 
 __device__ __forceinline__ int clampi(int v, int n) { return v < 0 ? 0 : (v >= n ? n - 1 : v); }
@@ -661,6 +662,8 @@ __device__ __forceinline__ void ut_body(const Coef<T>& c, int block, const S* __
 
     T pa[M::NA];                          // phi^{n+1} of the staged plane
     T po_[M::NB], pu[M::NB], pt[M::NB];   // phi^n, U^n, theta^n at the term nodes
+    T pv[ADV ? 3 : 1][ADV ? M::NB : 1];   // advective velocity at the term nodes (field)
+    [[maybe_unused]] const size_t nodes = (size_t)plane * (size_t)nz;
     typename Raw<S>::type ph_[L::Q], pf_[L::Q];   // dh_j, df_j of the pulled plane's sources, raw
     T pUx = T(0), pthx = T(0);            // U^n, theta^n of the pulled node
     auto prefetch = [&](int zz) {
@@ -686,6 +689,13 @@ __device__ __forceinline__ void ut_body(const Coef<T>& c, int block, const S* __
                     po_[kk] = phio[gi];
                     pu[kk] = Un[gi];
                     pt[kk] = thn[gi];
+                    if constexpr (ADV) {
+                        if (c.advf) {
+                            pv[0][kk] = c.advf[gi];
+                            pv[1][kk] = c.advf[nodes + gi];
+                            pv[2][kk] = c.advf[2 * nodes + gi];
+                        }
+                    }
                 }
             }
         }
@@ -796,7 +806,9 @@ __device__ __forceinline__ void ut_body(const Coef<T>& c, int block, const S* __
                 sa[t] = V4<T>{P + C + Ssrc, th + T(0.5) * dphi, c.jcoef * Jx, c.jcoef * Jy};
                 if constexpr (ADV) {
                     const T ot = c.omT * th;
-                    sk[t] = V4<T>{c.jcoef * Jz, ot * c.adv[0], ot * c.adv[1], ot * c.adv[2]};
+                    const T ax = c.advf ? pv[0][kk] : c.adv[0], ay = c.advf ? pv[1][kk] : c.adv[1],
+                            az = c.advf ? pv[2][kk] : c.adv[2];
+                    sk[t] = V4<T>{c.jcoef * Jz, ot * ax, ot * ay, ot * az};
                 } else {
                     sk[t] = c.jcoef * Jz;
                 }
@@ -990,6 +1002,9 @@ __global__ __launch_bounds__(256) void k_init(const Coef<T> c, S* __restrict__ g
     const T Jx = c.D * ((rn[0] - rn[1]) * c.inv2dx + q0 * (wn[0] - wn[1]) * c.inv2dx) * u;
     const T Jy = c.D * ((rn[2] - rn[3]) * c.inv2dx + q0 * (wn[2] - wn[3]) * c.inv2dx) * u;
     const T Jz = c.D * ((rn[4] - rn[5]) * c.inv2dx + q0 * (wn[4] - wn[5]) * c.inv2dx) * u;
+    const size_t nodes = (size_t)c.nx * (size_t)c.ny * (size_t)c.nz;
+    const T ax = c.advf ? c.advf[s] : c.adv[0], ay = c.advf ? c.advf[nodes + s] : c.adv[1],
+            az = c.advf ? c.advf[2 * nodes + s] : c.adv[2];
     Unroll<0, L::Q>::run([&](auto ic) {
         constexpr int I = decltype(ic)::value;
         constexpr T wi = T(L::w(I));
@@ -999,7 +1014,7 @@ __global__ __launch_bounds__(256) void k_init(const Coef<T> c, S* __restrict__ g
         g[o] = Codec<S>::enc(-wi * eN * c.cphi_e2);
         h[o] = Codec<S>::enc((I == 0) ? T(0) : wi * eJ * c.jt);
         // f = w_i theta [1 + e_i . v dt / (e^2 dx)]: deviation w_i theta e_i . v'
-        const T ev = T(L::ex(I)) * c.adv[0] + T(L::ey(I)) * c.adv[1] + T(L::ez(I)) * c.adv[2];
+        const T ev = T(L::ex(I)) * ax + T(L::ey(I)) * ay + T(L::ez(I)) * az;
         f[o] = Codec<S>::enc(c.has_adv ? wi * th[s] * ev : T(0));
     });
 }

@@ -282,7 +282,9 @@ void free_all(lbpf_ctx* ctx) {
     if (ctx->part) (void)hipFree(ctx->part);
     if (ctx->hist) (void)hipFree(ctx->hist);
     if (ctx->fresh) (void)hipFree(ctx->fresh);
+    if (ctx->vfield) (void)hipFree(ctx->vfield);
     ctx->part = ctx->hist = ctx->fresh = nullptr;
+    ctx->vfield = nullptr;
     for (auto& l : ctx->launches) {
         (void)hipEventDestroy(l.a);
         (void)hipEventDestroy(l.b);
@@ -784,6 +786,41 @@ lbpf_status convert_field(lbpf_ctx* ctx, const void* in, int32_t in_f64, void* o
         hipLaunchKernelGGL((k_convert<float, double>), dim3(nb), dim3(256), 0, ctx->stream, (const float*)in,
                            (double*)out, n);
     CHK(hipGetLastError());
+    return LBPF_OK;
+}
+
+lbpf_status lbpf_set_velocity_field(lbpf_ctx* ctx, const double* vx, const double* vy, const double* vz) {
+    if (!ctx) return LBPF_EINVAL;
+    if (ctx->in_batch) return fail(ctx, LBPF_ESTATE, "batched domains have no advective velocity");
+    const size_t n = ctx->n;
+    if (!vx && !vy && !vz) {
+        CHK(hipStreamSynchronize(ctx->stream));
+        if (ctx->vfield) CHK(hipFree(ctx->vfield));
+        ctx->vfield = nullptr;
+    } else {
+        if (!vx || !vy || !vz) return fail(ctx, LBPF_EINVAL, "give all three velocity components or none");
+        const double scale = ctx->prm.dt / (lattice_e2(ctx->q) * ctx->prm.dx);
+        std::vector<char> host(3 * n * ctx->tbytes);
+        const double* comp[3] = {vx, vy, vz};
+        for (int a = 0; a < 3; ++a)
+            for (size_t i = 0; i < n; ++i) {
+                const double v = comp[a][i];
+                if (!std::isfinite(v)) return fail(ctx, LBPF_EINVAL, "advective velocity must be finite");
+                if (ctx->tbytes == 8) ((double*)host.data())[a * n + i] = v * scale;
+                else ((float*)host.data())[a * n + i] = (float)(v * scale);
+            }
+        CHK(hipStreamSynchronize(ctx->stream));
+        if (!ctx->vfield && hipMalloc(&ctx->vfield, host.size()) != hipSuccess) {
+            ctx->vfield = nullptr;
+            return fail(ctx, LBPF_ENOMEM, "hipMalloc of the velocity field failed");
+        }
+        CHK(hipMemcpy(ctx->vfield, host.data(), host.size(), hipMemcpyHostToDevice));
+        // the advective variant of k_ut exists for its default tile only
+        ctx->shape[K_UT] = default_shape(ctx, K_UT);
+    }
+    // a captured step loop holds the old constants
+    if (ctx->gexec) (void)hipGraphExecDestroy(ctx->gexec);
+    ctx->gexec = nullptr;
     return LBPF_OK;
 }
 

@@ -71,6 +71,7 @@ struct lbpf_ctx {
     double* part = nullptr;  // RED_BLOCKS partials
     double* hist = nullptr;  // HIST_CAP records
     double* fresh = nullptr; // one record for lbpf_read
+    void* vfield = nullptr;  // NULL, or the advective velocity field, [3][n] values of v dt/(e^2 dx)
     int64_t hist_count = 0;
     // launch of k_phi [0] and k_ut [1]: tile shape id (see kShapes), z slab,
     // XCD-chunked tile order
@@ -141,7 +142,8 @@ Coef<T> make_coef(const lbpf_ctx* ctx, int k = K_PHI) {
     c.dt = (T)p.dt;
     c.jcoef = (T)(p.dt / (kE2 * p.dx) / etaU);
     c.jt = (T)(p.dt / (kE2 * p.dx));
-    c.has_adv = 0;
+    c.has_adv = ctx->vfield != nullptr;
+    c.advf = (const T*)ctx->vfield;
     for (int a = 0; a < 3; ++a) {
         c.adv[a] = (T)(p.vel[a] * p.dt / (kE2 * p.dx));
         if (p.vel[a] != 0.0) c.has_adv = 1;
@@ -150,7 +152,8 @@ Coef<T> make_coef(const lbpf_ctx* ctx, int k = K_PHI) {
 }
 
 inline bool has_advection(const lbpf_ctx* ctx) {
-    return ctx->prm.vel[0] != 0.0 || ctx->prm.vel[1] != 0.0 || ctx->prm.vel[2] != 0.0;
+    return ctx->vfield != nullptr || ctx->prm.vel[0] != 0.0 || ctx->prm.vel[1] != 0.0 ||
+           ctx->prm.vel[2] != 0.0;
 }
 
 inline int default_shape(const lbpf_ctx* ctx, int k) { return kDefaultShape[k][ctx->storage]; }

@@ -59,7 +59,8 @@ FIELD_TYPE = {"f32": 0, "f64": 1}
 SYMBOLS = ["lbpf_create", "lbpf_destroy", "lbpf_set_fields", "lbpf_step", "lbpf_sync",
            "lbpf_read", "lbpf_history", "lbpf_read_populations", "lbpf_write_populations",
            "lbpf_read_populations_f64",
-           "lbpf_debug_stream_only", "lbpf_set_timing", "lbpf_kernel_times",
+           "lbpf_debug_stream_only", "lbpf_set_velocity_field", "lbpf_set_timing",
+           "lbpf_kernel_times",
            "lbpf_set_launch", "lbpf_get_launch", "lbpf_set_kernel_launch",
            "lbpf_get_kernel_launch", "lbpf_autotune",
            "lbpf_storage_bytes", "lbpf_bench_copy", "lbpf_last_error", "lbpf_set_graph",
@@ -94,6 +95,7 @@ def load():
         "lbpf_write_populations": ([vp, ctypes.c_int32, vp], ctypes.c_int),
         "lbpf_read_populations_f64": ([vp, ctypes.c_int32, dp], ctypes.c_int),
         "lbpf_debug_stream_only": ([vp, ctypes.c_int64], ctypes.c_int),
+        "lbpf_set_velocity_field": ([vp, dp, dp, dp], ctypes.c_int),
         "lbpf_set_timing": ([vp, ctypes.c_int32], ctypes.c_int),
         "lbpf_kernel_times": ([vp, dp, P(ctypes.c_int64)], ctypes.c_int),
         "lbpf_set_launch": ([vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32],
@@ -285,6 +287,17 @@ class Solver:
 
     def debug_stream_only(self, n=1):
         self._check(self._lib.lbpf_debug_stream_only(self._h, int(n)))
+
+    def set_velocity_field(self, vx, vy, vz):
+        """Per-node advective velocity of theta, arrays of shape (nz, ny, nx);
+        None for all three removes it."""
+        if vx is None and vy is None and vz is None:
+            self._check(self._lib.lbpf_set_velocity_field(self._h, None, None, None))
+            return
+        arr = [np.ascontiguousarray(np.asarray(v, dtype=np.float64).reshape(self.shape))
+               for v in (vx, vy, vz)]
+        dp = ctypes.POINTER(ctypes.c_double)
+        self._check(self._lib.lbpf_set_velocity_field(self._h, *[a.ctypes.data_as(dp) for a in arr]))
 
     def set_timing(self, enable=True):
         self._check(self._lib.lbpf_set_timing(self._h, 1 if enable else 0))

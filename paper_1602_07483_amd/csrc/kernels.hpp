@@ -153,6 +153,7 @@ template <class T> struct alignas(2 * sizeof(T)) V2 { T x, y; };
 template <class T>
 struct Coef {
     int nx, ny, nz;
+    int px;            // row pitch of every device array: nx rounded up to 32 elements
     int symm;          // bit f set: face f (-x,+x,-y,+y,-z,+z) is a symmetry wall
     int zslab;         // z planes per block
     int nbx, nby, nbz; // tiles per axis
@@ -366,36 +367,6 @@ struct Tile {
     }
 };
 
-// Load one (TX+4) x (TY+4) plane of phi into LDS, mirror ghosts by clamping.
-template <class T, int TX, int TY>
-__device__ __forceinline__ void load_plane(T* dst, const T* __restrict__ f, int zz, int x0, int y0,
-                                           int nx, int ny, int nz) {
-    using G = Tile<TX, TY>;
-    const int gz = clampi(zz, nz);
-    const size_t base = (size_t)gz * (size_t)nx * (size_t)ny;
-    for (int t = threadIdx.x; t < G::PN; t += G::NT) {
-        const int lx = t % G::PX, ly = t / G::PX;
-        const int gx = clampi(x0 - 2 + lx, nx), gy = clampi(y0 - 2 + ly, ny);
-        dst[t] = f[base + (size_t)gy * nx + gx];
-    }
-}
-
-// Same, storing (phi, 1/zeta(phi)).
-template <class T, int TX, int TY>
-__device__ __forceinline__ void load_plane_w(V2<T>* dst, const T* __restrict__ f, int zz, int x0,
-                                             int y0, int nx, int ny, int nz, T zA, T zB) {
-    using G = Tile<TX, TY>;
-    const int gz = clampi(zz, nz);
-    const size_t base = (size_t)gz * (size_t)nx * (size_t)ny;
-    for (int t = threadIdx.x; t < G::PN; t += G::NT) {
-        const int lx = t % G::PX, ly = t / G::PX;
-        const int gx = clampi(x0 - 2 + lx, nx), gy = clampi(y0 - 2 + ly, ny);
-        const T p = f[base + (size_t)gy * nx + gx];
-        dst[t] = V2<T>{p, frcp(zA - zB * p)};
-    }
-}
-
-// ==========================================================================
 // The march.  Iteration zz of a block stages the stencil-field plane zz (A),
 // computes the node terms of plane zz-1 (B) and pulls plane zz-2 (C).  All
 // global loads an iteration needs (the field plane, the fields at the term
@@ -436,8 +407,8 @@ __device__ __forceinline__ void phi_body(const Coef<T>& c, int block, const S* _
     __shared__ V4<T> stb[3][G::HN];       // node terms, second 4-vector
 
     G tile(c, block);
-    const int nx = c.nx, ny = c.ny, nz = c.nz;
-    const unsigned plane = (unsigned)nx * (unsigned)ny;
+    const int nx = c.nx, ny = c.ny, nz = c.nz, px = c.px;
+    const unsigned plane = (unsigned)px * (unsigned)ny;
     const unsigned pbytes = (unsigned)((size_t)L::Q * (size_t)c.np * sizeof(S));
     const __amdgpu_buffer_rsrc_t rin = make_rsrc(gin, BUF ? pbytes : 0u);
     const __amdgpu_buffer_rsrc_t rout = make_rsrc(gout, BUF ? pbytes : 0u);
@@ -456,7 +427,7 @@ __device__ __forceinline__ void phi_body(const Coef<T>& c, int block, const S* _
                 const int t = (int)threadIdx.x + k * G::NT;
                 if (t < G::PN) {
                     const int gx = clampi(tile.x0 - 2 + t % G::PX, nx), gy = clampi(tile.y0 - 2 + t / G::PX, ny);
-                    pa[k] = phin[base + (size_t)gy * nx + gx];
+                    pa[k] = phin[base + (size_t)gy * px + gx];
                 }
             }
         }
@@ -467,7 +438,7 @@ __device__ __forceinline__ void phi_body(const Coef<T>& c, int block, const S* _
                 const int t = (int)threadIdx.x + k * G::NT;
                 if (t < G::HN) {
                     const int gx = clampi(tile.x0 - 1 + t % G::HX, nx), gy = clampi(tile.y0 - 1 + t / G::HX, ny);
-                    const size_t gi = base + (size_t)gy * nx + gx;
+                    const size_t gi = base + (size_t)gy * px + gx;
                     pu[k] = Un[gi];
                     pt[k] = thn[gi];
                 }
@@ -475,7 +446,7 @@ __device__ __forceinline__ void phi_body(const Coef<T>& c, int block, const S* _
         }
         if (zz >= tile.zs + 2 && tile.active) {   // C of iteration zz: plane zz-2
             const int z = zz - 2;
-            const unsigned xi = (unsigned)z * plane + (unsigned)tile.y * nx + tile.x;
+            const unsigned xi = (unsigned)z * plane + (unsigned)tile.y * px + tile.x;
             Faces f = tile.f;
             f.zl = z == 0;
             f.zh = z == nz - 1;
@@ -483,7 +454,7 @@ __device__ __forceinline__ void phi_body(const Coef<T>& c, int block, const S* _
             Unroll<0, L::Q>::run([&](auto ic) {
                 constexpr int I = decltype(ic)::value;
                 constexpr int ex = L::ex(I), ey = L::ey(I), ez = L::ez(I);
-                const int off = ex + ey * nx + ez * (int)plane;
+                const int off = ex + ey * px + ez * (int)plane;
                 const bool cr = crosses<L, I>(f);    // wall links: read any in-bounds value
                 if constexpr (BUF) {
                     const unsigned vx = xi * (unsigned)sizeof(S);
@@ -549,7 +520,7 @@ __device__ __forceinline__ void phi_body(const Coef<T>& c, int block, const S* _
         // C: pull plane zz-2 (terms of planes zz-3 .. zz-1 are ready)
         if (zz >= tile.zs + 2 && tile.active) {
             const int z = zz - 2;
-            const unsigned xi = (unsigned)z * plane + (unsigned)tile.y * nx + tile.x;
+            const unsigned xi = (unsigned)z * plane + (unsigned)tile.y * px + tile.x;
             const int sl[3] = {(z + 2) % 3, (z + 3) % 3, (z + 4) % 3};   // planes z-1, z, z+1
             const T phx = sta[sl[1]][tile.lt].w;
             Faces f = tile.f;
@@ -565,7 +536,7 @@ __device__ __forceinline__ void phi_body(const Coef<T>& c, int block, const S* _
             auto wall_link = [&](auto ic) -> T {
                 constexpr int I = decltype(ic)::value;
                 const Src s = source<L, I>(opaque_v(tile.x), opaque_v(tile.y), z, nx, ny, nz, c.symm);
-                const size_t si = ((size_t)s.sz * ny + s.sy) * nx + s.sx;
+                const size_t si = ((size_t)s.sz * ny + s.sy) * px + s.sx;
                 const T dj = (T)Codec<S>::dec(gin[(size_t)s.j * np + si]);
                 const T dnl = (T)Raw<S>::dec(pnl[I]);
                 const int tsl = (s.sz + 3) % 3, tl = (s.sy - tile.y0 + 1) * G::HX + (s.sx - tile.x0 + 1);
@@ -649,8 +620,8 @@ __device__ __forceinline__ void ut_body(const Coef<T>& c, int block, const S* __
     __shared__ V4<T> sown[2][G::NT];      // (P, C, S, r) of the tile's own nodes
 
     G tile(c, block);
-    const int nx = c.nx, ny = c.ny, nz = c.nz;
-    const unsigned plane = (unsigned)nx * (unsigned)ny;
+    const int nx = c.nx, ny = c.ny, nz = c.nz, px = c.px;
+    const unsigned plane = (unsigned)px * (unsigned)ny;
     const T k = c.k;
     const T zA = T(0.5) * (T(1) + k), zB = T(0.5) * (T(1) - k);
     const T omU1 = T(1) - c.omU, omT1 = T(1) - c.omT;
@@ -674,7 +645,7 @@ __device__ __forceinline__ void ut_body(const Coef<T>& c, int block, const S* __
                 const int t = (int)threadIdx.x + kk * G::NT;
                 if (t < G::PN) {
                     const int gx = clampi(tile.x0 - 2 + t % G::PX, nx), gy = clampi(tile.y0 - 2 + t / G::PX, ny);
-                    pa[kk] = phnew[base + (size_t)gy * nx + gx];
+                    pa[kk] = phnew[base + (size_t)gy * px + gx];
                 }
             }
         }
@@ -685,7 +656,7 @@ __device__ __forceinline__ void ut_body(const Coef<T>& c, int block, const S* __
                 const int t = (int)threadIdx.x + kk * G::NT;
                 if (t < G::HN) {
                     const int gx = clampi(tile.x0 - 1 + t % G::HX, nx), gy = clampi(tile.y0 - 1 + t / G::HX, ny);
-                    const size_t gi = base + (size_t)gy * nx + gx;
+                    const size_t gi = base + (size_t)gy * px + gx;
                     po_[kk] = phio[gi];
                     pu[kk] = Un[gi];
                     pt[kk] = thn[gi];
@@ -701,7 +672,7 @@ __device__ __forceinline__ void ut_body(const Coef<T>& c, int block, const S* __
         }
         if (zz >= tile.zs + 2 && tile.active) {
             const int z = zz - 2;
-            const unsigned xi = (unsigned)z * plane + (unsigned)tile.y * nx + tile.x;
+            const unsigned xi = (unsigned)z * plane + (unsigned)tile.y * px + tile.x;
             Faces f = tile.f;
             f.zl = z == 0;
             f.zh = z == nz - 1;
@@ -711,7 +682,7 @@ __device__ __forceinline__ void ut_body(const Coef<T>& c, int block, const S* __
             Unroll<0, L::Q>::run([&](auto ic) {
                 constexpr int I = decltype(ic)::value;
                 constexpr int ex = L::ex(I), ey = L::ey(I), ez = L::ez(I);
-                const int off = ex + ey * nx + ez * (int)plane;
+                const int off = ex + ey * px + ez * (int)plane;
                 const bool cr = crosses<L, I>(f);    // wall links: read any in-bounds value
                 if constexpr (BUF) {
                     const unsigned vx = xi * (unsigned)sizeof(S);
@@ -819,7 +790,7 @@ __device__ __forceinline__ void ut_body(const Coef<T>& c, int block, const S* __
         __syncthreads();
         if (zz >= tile.zs + 2 && tile.active) {
             const int z = zz - 2;
-            const unsigned xi = (unsigned)z * plane + (unsigned)tile.y * nx + tile.x;
+            const unsigned xi = (unsigned)z * plane + (unsigned)tile.y * px + tile.x;
             const int sl[3] = {(z + 2) % 3, (z + 3) % 3, (z + 4) % 3};
             const V4<T> own = sown[z & 1][threadIdx.x];
             const T Px = own.x, Cx = own.y, Sx = own.z, rx = own.w;
@@ -835,7 +806,7 @@ __device__ __forceinline__ void ut_body(const Coef<T>& c, int block, const S* __
             auto wall_link = [&](auto ic, T& vu, T& vt) {
                 constexpr int I = decltype(ic)::value;
                 const Src s = source<L, I>(opaque_v(tile.x), opaque_v(tile.y), z, nx, ny, nz, c.symm);
-                const size_t si = ((size_t)s.sz * ny + s.sy) * nx + s.sx;
+                const size_t si = ((size_t)s.sz * ny + s.sy) * px + s.sx;
                 const T dh = (T)Codec<S>::dec(hin[(size_t)s.j * np + si]);
                 const T df = (T)Codec<S>::dec(fin[(size_t)s.j * np + si]);
                 const int tsl = (s.sz + 3) % 3, tl = (s.sy - tile.y0 + 1) * G::HX + (s.sx - tile.x0 + 1);
@@ -976,13 +947,14 @@ template <class L, class T, class S>
 __global__ __launch_bounds__(256) void k_init(const Coef<T> c, S* __restrict__ g, S* __restrict__ h,
                                               S* __restrict__ f, const T* __restrict__ phi,
                                               const T* __restrict__ U, const T* __restrict__ th) {
-    const int nx = c.nx, ny = c.ny, nz = c.nz;
+    const int nx = c.nx, ny = c.ny, nz = c.nz, px = c.px;
     const size_t n = (size_t)nx * ny * nz;
-    const size_t s = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (s >= n) return;
-    const int x = (int)(s % nx), y = (int)((s / nx) % ny), z = (int)(s / ((size_t)nx * ny));
+    const size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x;   // node number
+    if (q >= n) return;
+    const int x = (int)(q % nx), y = (int)((q / nx) % ny), z = (int)(q / ((size_t)nx * ny));
+    const size_t s = ((size_t)z * ny + y) * px + x;                    // its address
     auto at = [&](int xx, int yy, int zz) {
-        return phi[((size_t)clampi(zz, nz) * ny + clampi(yy, ny)) * nx + clampi(xx, nx)];
+        return phi[((size_t)clampi(zz, nz) * ny + clampi(yy, ny)) * px + clampi(xx, nx)];
     };
     const T p0 = phi[s];
     const T pn[6] = {at(x + 1, y, z), at(x - 1, y, z), at(x, y + 1, z),
@@ -1002,7 +974,7 @@ __global__ __launch_bounds__(256) void k_init(const Coef<T> c, S* __restrict__ g
     const T Jx = c.D * ((rn[0] - rn[1]) * c.inv2dx + q0 * (wn[0] - wn[1]) * c.inv2dx) * u;
     const T Jy = c.D * ((rn[2] - rn[3]) * c.inv2dx + q0 * (wn[2] - wn[3]) * c.inv2dx) * u;
     const T Jz = c.D * ((rn[4] - rn[5]) * c.inv2dx + q0 * (wn[4] - wn[5]) * c.inv2dx) * u;
-    const size_t nodes = (size_t)c.nx * (size_t)c.ny * (size_t)c.nz;
+    const size_t nodes = (size_t)px * (size_t)ny * (size_t)nz;
     const T ax = c.advf ? c.advf[s] : c.adv[0], ay = c.advf ? c.advf[nodes + s] : c.adv[1],
             az = c.advf ? c.advf[2 * nodes + s] : c.adv[2];
     Unroll<0, L::Q>::run([&](auto ic) {
@@ -1025,8 +997,9 @@ __global__ __launch_bounds__(256) void k_decode(const Coef<T> c, const S* __rest
                                                 const T* __restrict__ phi, const T* __restrict__ U,
                                                 const T* __restrict__ th, double* __restrict__ out) {
     const size_t n = (size_t)c.nx * c.ny * c.nz;
-    const size_t s = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (s >= n) return;
+    const size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x;   // node number (output index)
+    if (q >= n) return;
+    const size_t s = (q / c.nx) * c.px + q % c.nx;                      // its address
     const T zA = T(0.5) * (T(1) + c.k), zB = T(0.5) * (T(1) - c.k);
     Unroll<0, L::Q>::run([&](auto ic) {
         constexpr int I = decltype(ic)::value;
@@ -1041,7 +1014,7 @@ __global__ __launch_bounds__(256) void k_decode(const Coef<T> c, const S* __rest
         } else {
             ref = wi * (double)th[s];
         }
-        out[(size_t)I * n + s] = d + ref;
+        out[(size_t)I * n + q] = d + ref;
     });
 }
 
@@ -1050,16 +1023,17 @@ __global__ __launch_bounds__(256) void k_decode(const Coef<T> c, const S* __rest
 // mapping and the wall rules.
 // ==========================================================================
 template <class L, class B>
-__global__ __launch_bounds__(256) void k_stream_only(int nx, int ny, int nz, int symm, long long np,
+__global__ __launch_bounds__(256) void k_stream_only(int nx, int ny, int nz, int px, int symm, long long np,
                                                      const B* __restrict__ in, B* __restrict__ out) {
     const size_t n = (size_t)nx * ny * nz;
-    const size_t s = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (s >= n) return;
-    const int x = (int)(s % nx), y = (int)((s / nx) % ny), z = (int)(s / ((size_t)nx * ny));
+    const size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= n) return;
+    const int x = (int)(q % nx), y = (int)((q / nx) % ny), z = (int)(q / ((size_t)nx * ny));
+    const size_t s = ((size_t)z * ny + y) * px + x;
     Unroll<0, L::Q>::run([&](auto ic) {
         constexpr int I = decltype(ic)::value;
         const Src src = source<L, I>(x, y, z, nx, ny, nz, symm);
-        const size_t si = ((size_t)src.sz * ny + src.sy) * nx + src.sx;
+        const size_t si = ((size_t)src.sz * ny + src.sy) * px + src.sx;
         out[(size_t)I * np + s] = in[(size_t)src.j * np + si];
     });
 }
@@ -1084,7 +1058,7 @@ __device__ __forceinline__ double wave_max(double v) {
 }
 
 template <class T>
-__global__ __launch_bounds__(256) void k_reduce_part(int nx, int ny, int nz, double k, double dv,
+__global__ __launch_bounds__(256) void k_reduce_part(int nx, int ny, int nz, int px, double k, double dv,
                                                      const T* __restrict__ phi, const T* __restrict__ U,
                                                      const T* __restrict__ th, double* __restrict__ part) {
     __shared__ double sh[4][RV_COUNT];
@@ -1094,8 +1068,10 @@ __global__ __launch_bounds__(256) void k_reduce_part(int nx, int ny, int nz, dou
     for (int i = 0; i < RV_NSUM; ++i) v[i] = 0.0;
 #pragma unroll
     for (int i = RV_NSUM; i < RV_COUNT; ++i) v[i] = -INFINITY;
-    for (size_t s = (size_t)blockIdx.x * blockDim.x + threadIdx.x; s < n;
-         s += (size_t)gridDim.x * blockDim.x) {
+    for (size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x; q < n;
+         q += (size_t)gridDim.x * blockDim.x) {
+        const int x = (int)(q % nx), y = (int)((q / nx) % ny), z = (int)(q / ((size_t)nx * ny));
+        const size_t s = ((size_t)z * ny + y) * px + x;
         const double f = (double)phi[s], u = (double)U[s], t = (double)th[s];
         if (!isfinite(f) || !isfinite(u) || !isfinite(t)) {
             v[RV_BAD] += 1.0;
@@ -1109,17 +1085,16 @@ __global__ __launch_bounds__(256) void k_reduce_part(int nx, int ny, int nz, dou
         v[RV_PMAX] = fmax(v[RV_PMAX], f);
         v[RV_NEG_PMIN] = fmax(v[RV_NEG_PMIN], -f);
         if (f > 0.0) {
-            const int x = (int)(s % nx), y = (int)((s / nx) % ny), z = (int)(s / ((size_t)nx * ny));
             if (x + 1 < nx) {
                 const double fn = (double)phi[s + 1];
                 if (fn <= 0.0) v[RV_TIPX] = fmax(v[RV_TIPX], x + f / (f - fn));
             }
             if (y + 1 < ny) {
-                const double fn = (double)phi[s + nx];
+                const double fn = (double)phi[s + px];
                 if (fn <= 0.0) v[RV_TIPY] = fmax(v[RV_TIPY], y + f / (f - fn));
             }
             if (z + 1 < nz) {
-                const double fn = (double)phi[s + (size_t)nx * ny];
+                const double fn = (double)phi[s + (size_t)px * ny];
                 if (fn <= 0.0) v[RV_TIPZ] = fmax(v[RV_TIPZ], z + f / (f - fn));
             }
         }
@@ -1139,11 +1114,17 @@ __global__ __launch_bounds__(256) void k_reduce_part(int nx, int ny, int nz, dou
     }
 }
 
-// Element-wise type conversion of a field (device-resident field I/O).
+// Element-wise type conversion of a field between row pitches (device-resident
+// field I/O): rows of nx values, pin and pout elements apart.
 template <class From, class To>
-__global__ __launch_bounds__(256) void k_convert(const From* __restrict__ in, To* __restrict__ out, size_t n) {
+__global__ __launch_bounds__(256) void k_convert(const From* __restrict__ in, To* __restrict__ out, int nx,
+                                                 int pin, int pout, size_t rows) {
+    const size_t n = rows * (size_t)nx;
     const size_t stride = (size_t)gridDim.x * blockDim.x;
-    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) out[i] = (To)in[i];
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        const size_t r = i / nx, x = i % nx;
+        out[r * pout + x] = (To)in[r * pin + x];
+    }
 }
 
 }  // namespace lbpf

@@ -189,12 +189,12 @@ lbpf_status stream_only_t(lbpf_ctx* ctx) {
     const int a = ctx->cur, b = 1 - ctx->cur;
     for (int f = 0; f < 3; ++f)
         hipLaunchKernelGGL((k_stream_only<L, B>), dim3(nb), dim3(256), 0, ctx->stream, ctx->grid.nx,
-                           ctx->grid.ny, ctx->grid.nz, symm, (long long)ctx->np,
+                           ctx->grid.ny, ctx->grid.nz, ctx->px, symm, (long long)ctx->np,
                            (const B*)ctx->pop[f][a], (B*)ctx->pop[f][b]);
     CHK(hipGetLastError());
     // the fields follow the populations' parity unchanged
     for (int f = 0; f < 3; ++f)
-        CHK(hipMemcpyAsync(ctx->fld[f][b], ctx->fld[f][a], ctx->n * ctx->tbytes,
+        CHK(hipMemcpyAsync(ctx->fld[f][b], ctx->fld[f][a], ctx->na * ctx->tbytes,
                            hipMemcpyDeviceToDevice, ctx->stream));
     ctx->cur = b;
     return LBPF_OK;
@@ -217,7 +217,7 @@ lbpf_status launch_reduce_t(lbpf_ctx* ctx, double* rec) {
     const int nb = (int)std::min<size_t>(RED_BLOCKS, (ctx->n + 255) / 256);
     lbpf_status st = timed(ctx, 2, [&] {
         hipLaunchKernelGGL((k_reduce_part<T>), dim3(nb), dim3(256), 0, ctx->stream, ctx->grid.nx,
-                           ctx->grid.ny, ctx->grid.nz, p.k, p.dx * p.dx * p.dx,
+                           ctx->grid.ny, ctx->grid.nz, ctx->px, p.k, p.dx * p.dx * p.dx,
                            (const T*)ctx->fld[0][a], (const T*)ctx->fld[1][a],
                            (const T*)ctx->fld[2][a], ctx->part);
     });
@@ -363,12 +363,15 @@ lbpf_status lbpf_create(const lbpf_grid* grid, const lbpf_params* params, void* 
         ctx->remap[k] = 1;
     }
     ctx->n = (size_t)g.nx * g.ny * g.nz;
-    ctx->np = (ctx->n + 63) / 64 * 64;
+    // rows start on 128-byte lines (FP32): a tile row then reads whole lines
+    ctx->px = (g.nx + 31) / 32 * 32;
+    ctx->na = (size_t)ctx->px * g.ny * g.nz;
+    ctx->np = (ctx->na + 63) / 64 * 64;
     hipError_t e = hipSuccess;
     for (int f = 0; f < 3 && e == hipSuccess; ++f)
         for (int par = 0; par < 2 && e == hipSuccess; ++par) {
             e = hipMalloc(&ctx->pop[f][par], ctx->np * ctx->q * ctx->sbytes);
-            if (e == hipSuccess) e = hipMalloc(&ctx->fld[f][par], ctx->n * ctx->tbytes);
+            if (e == hipSuccess) e = hipMalloc(&ctx->fld[f][par], ctx->na * ctx->tbytes);
         }
     if (e == hipSuccess) e = hipMalloc((void**)&ctx->part, RED_BLOCKS * RED_STRIDE * sizeof(double));
     if (e == hipSuccess) e = hipMalloc((void**)&ctx->hist, (size_t)HIST_CAP * RED_STRIDE * sizeof(double));
@@ -401,14 +404,16 @@ lbpf_status lbpf_set_fields(lbpf_ctx* ctx, const double* phi, const double* U, c
     ctx->cur = 0;
     const double* src[3] = {phi, U, theta};
     for (int f = 0; f < 3; ++f) {
+        const size_t nx = ctx->grid.nx, rows = (size_t)ctx->grid.ny * ctx->grid.nz;
         if (ctx->tbytes == 8) {
-            CHK(hipMemcpyAsync(ctx->fld[f][0], src[f], ctx->n * 8, hipMemcpyHostToDevice, ctx->stream));
+            CHK(hipMemcpy2DAsync(ctx->fld[f][0], ctx->px * 8, src[f], nx * 8, nx * 8, rows,
+                                 hipMemcpyHostToDevice, ctx->stream));
             CHK(hipStreamSynchronize(ctx->stream));
         } else {
             std::vector<float> tmp(ctx->n);
             for (size_t i = 0; i < ctx->n; ++i) tmp[i] = (float)src[f][i];
-            CHK(hipMemcpyAsync(ctx->fld[f][0], tmp.data(), ctx->n * 4, hipMemcpyHostToDevice,
-                               ctx->stream));
+            CHK(hipMemcpy2DAsync(ctx->fld[f][0], ctx->px * 4, tmp.data(), nx * 4, nx * 4, rows,
+                                 hipMemcpyHostToDevice, ctx->stream));
             CHK(hipStreamSynchronize(ctx->stream));
         }
     }
@@ -528,11 +533,14 @@ lbpf_status lbpf_read(lbpf_ctx* ctx, double* phi, double* U, double* theta, lbpf
     CHK(hipStreamSynchronize(ctx->stream));
     for (int f = 0; f < 3; ++f) {
         if (!dst[f]) continue;
+        const size_t nx = ctx->grid.nx, rows = (size_t)ctx->grid.ny * ctx->grid.nz;
         if (ctx->tbytes == 8) {
-            CHK(hipMemcpy(dst[f], ctx->fld[f][ctx->cur], ctx->n * 8, hipMemcpyDeviceToHost));
+            CHK(hipMemcpy2D(dst[f], nx * 8, ctx->fld[f][ctx->cur], ctx->px * 8, nx * 8, rows,
+                            hipMemcpyDeviceToHost));
         } else {
             std::vector<float> tmp(ctx->n);
-            CHK(hipMemcpy(tmp.data(), ctx->fld[f][ctx->cur], ctx->n * 4, hipMemcpyDeviceToHost));
+            CHK(hipMemcpy2D(tmp.data(), nx * 4, ctx->fld[f][ctx->cur], ctx->px * 4, nx * 4, rows,
+                            hipMemcpyDeviceToHost));
             for (size_t i = 0; i < ctx->n; ++i) dst[f][i] = (double)tmp[i];
         }
     }
@@ -572,10 +580,11 @@ lbpf_status lbpf_read_populations(lbpf_ctx* ctx, int32_t field, void* dst) {
     if (!ctx) return LBPF_EINVAL;
     if (field < 0 || field > 2 || !dst) return fail(ctx, LBPF_EINVAL, "bad field or NULL dst");
     CHK(hipStreamSynchronize(ctx->stream));
-    const size_t row = ctx->n * ctx->sbytes;
+    const size_t arr = ctx->n * ctx->sbytes, w = ctx->grid.nx * ctx->sbytes;
+    const size_t rows = (size_t)ctx->grid.ny * ctx->grid.nz;
     for (int i = 0; i < ctx->q; ++i)
-        CHK(hipMemcpy((char*)dst + i * row, (const char*)ctx->pop[field][ctx->cur] + i * ctx->np * ctx->sbytes,
-                      row, hipMemcpyDeviceToHost));
+        CHK(hipMemcpy2D((char*)dst + i * arr, w, (const char*)ctx->pop[field][ctx->cur] + i * ctx->np * ctx->sbytes,
+                        ctx->px * ctx->sbytes, w, rows, hipMemcpyDeviceToHost));
     return LBPF_OK;
 }
 
@@ -584,10 +593,11 @@ lbpf_status lbpf_write_populations(lbpf_ctx* ctx, int32_t field, const void* src
     if (field < 0 || field > 2 || !src) return fail(ctx, LBPF_EINVAL, "bad field or NULL src");
     if (!ctx->have_fields) return fail(ctx, LBPF_ESTATE, "lbpf_set_fields has not been called");
     CHK(hipStreamSynchronize(ctx->stream));
-    const size_t row = ctx->n * ctx->sbytes;
+    const size_t arr = ctx->n * ctx->sbytes, w = ctx->grid.nx * ctx->sbytes;
+    const size_t rows = (size_t)ctx->grid.ny * ctx->grid.nz;
     for (int i = 0; i < ctx->q; ++i)
-        CHK(hipMemcpy((char*)ctx->pop[field][ctx->cur] + i * ctx->np * ctx->sbytes, (const char*)src + i * row,
-                      row, hipMemcpyHostToDevice));
+        CHK(hipMemcpy2D((char*)ctx->pop[field][ctx->cur] + i * ctx->np * ctx->sbytes, ctx->px * ctx->sbytes,
+                        (const char*)src + i * arr, w, w, rows, hipMemcpyHostToDevice));
     return LBPF_OK;
 }
 
@@ -696,7 +706,7 @@ lbpf_status lbpf_autotune(lbpf_ctx* ctx, int32_t steps_per_candidate, double* be
     if (!ctx->have_fields) return fail(ctx, LBPF_ESTATE, "lbpf_set_fields has not been called");
     CHK(hipStreamSynchronize(ctx->stream));
     // snapshot of the current state (populations and fields of parity cur)
-    const size_t pbytes = ctx->np * ctx->q * ctx->sbytes, fbytes = ctx->n * ctx->tbytes;
+    const size_t pbytes = ctx->np * ctx->q * ctx->sbytes, fbytes = ctx->na * ctx->tbytes;
     void* snap = nullptr;
     CHK(hipMalloc(&snap, 3 * (pbytes + fbytes)));
     const int cur0 = ctx->cur;
@@ -772,19 +782,26 @@ lbpf_status lbpf_autotune(lbpf_ctx* ctx, int32_t steps_per_candidate, double* be
 
 // Device-resident field I/O: convert between the caller's FP32/FP64 arrays
 // and the context's field type on the context's stream.
-lbpf_status convert_field(lbpf_ctx* ctx, const void* in, int32_t in_f64, void* out, int32_t out_f64) {
-    const size_t n = ctx->n;
-    if (in_f64 == out_f64) {
-        CHK(hipMemcpyAsync(out, in, n * (in_f64 ? 8 : 4), hipMemcpyDeviceToDevice, ctx->stream));
-        return LBPF_OK;
-    }
-    const int nb = (int)std::min<size_t>(8192, (n + 255) / 256);
-    if (in_f64)
+// in_pitched / out_pitched: the array has the context's row pitch (its own
+// fields), else rows of nx (the caller's arrays).
+lbpf_status convert_field(lbpf_ctx* ctx, const void* in, int32_t in_f64, bool in_pitched, void* out,
+                          int32_t out_f64, bool out_pitched) {
+    const int nx = ctx->grid.nx;
+    const size_t rows = (size_t)ctx->grid.ny * ctx->grid.nz;
+    const int pin = in_pitched ? ctx->px : nx, pout = out_pitched ? ctx->px : nx;
+    const int nb = (int)std::min<size_t>(8192, (ctx->n + 255) / 256);
+    if (in_f64 && out_f64)
+        hipLaunchKernelGGL((k_convert<double, double>), dim3(nb), dim3(256), 0, ctx->stream, (const double*)in,
+                           (double*)out, nx, pin, pout, rows);
+    else if (in_f64)
         hipLaunchKernelGGL((k_convert<double, float>), dim3(nb), dim3(256), 0, ctx->stream, (const double*)in,
-                           (float*)out, n);
-    else
+                           (float*)out, nx, pin, pout, rows);
+    else if (out_f64)
         hipLaunchKernelGGL((k_convert<float, double>), dim3(nb), dim3(256), 0, ctx->stream, (const float*)in,
-                           (double*)out, n);
+                           (double*)out, nx, pin, pout, rows);
+    else
+        hipLaunchKernelGGL((k_convert<float, float>), dim3(nb), dim3(256), 0, ctx->stream, (const float*)in,
+                           (float*)out, nx, pin, pout, rows);
     CHK(hipGetLastError());
     return LBPF_OK;
 }
@@ -800,14 +817,17 @@ lbpf_status lbpf_set_velocity_field(lbpf_ctx* ctx, const double* vx, const doubl
     } else {
         if (!vx || !vy || !vz) return fail(ctx, LBPF_EINVAL, "give all three velocity components or none");
         const double scale = ctx->prm.dt / (lattice_e2(ctx->q) * ctx->prm.dx);
-        std::vector<char> host(3 * n * ctx->tbytes);
+        // device layout: three arrays of na values with the fields' row pitch
+        const size_t na = ctx->na, nx = ctx->grid.nx;
+        std::vector<char> host(3 * na * ctx->tbytes, 0);
         const double* comp[3] = {vx, vy, vz};
         for (int a = 0; a < 3; ++a)
             for (size_t i = 0; i < n; ++i) {
                 const double v = comp[a][i];
                 if (!std::isfinite(v)) return fail(ctx, LBPF_EINVAL, "advective velocity must be finite");
-                if (ctx->tbytes == 8) ((double*)host.data())[a * n + i] = v * scale;
-                else ((float*)host.data())[a * n + i] = (float)(v * scale);
+                const size_t d = a * na + (i / nx) * ctx->px + i % nx;
+                if (ctx->tbytes == 8) ((double*)host.data())[d] = v * scale;
+                else ((float*)host.data())[d] = (float)(v * scale);
             }
         CHK(hipStreamSynchronize(ctx->stream));
         if (!ctx->vfield && hipMalloc(&ctx->vfield, host.size()) != hipSuccess) {
@@ -832,7 +852,8 @@ lbpf_status lbpf_set_fields_device(lbpf_ctx* ctx, const void* phi, const void* U
     ctx->cur = 0;
     const void* src[3] = {phi, U, theta};
     for (int f = 0; f < 3; ++f) {
-        lbpf_status st = convert_field(ctx, src[f], dtype == LBPF_FIELD_F64, ctx->fld[f][0], ctx->tbytes == 8);
+        lbpf_status st = convert_field(ctx, src[f], dtype == LBPF_FIELD_F64, false, ctx->fld[f][0],
+                                       ctx->tbytes == 8, true);
         if (st) return st;
     }
     lbpf_status st = init_or_decode(ctx, 0, 0, nullptr);
@@ -851,7 +872,8 @@ lbpf_status lbpf_read_fields_device(lbpf_ctx* ctx, void* phi, void* U, void* the
     void* dst[3] = {phi, U, theta};
     for (int f = 0; f < 3; ++f) {
         if (!dst[f]) continue;
-        lbpf_status st = convert_field(ctx, ctx->fld[f][ctx->cur], ctx->tbytes == 8, dst[f], dtype == LBPF_FIELD_F64);
+        lbpf_status st = convert_field(ctx, ctx->fld[f][ctx->cur], ctx->tbytes == 8, true, dst[f],
+                                       dtype == LBPF_FIELD_F64, false);
         if (st) return st;
     }
     return LBPF_OK;

@@ -62,7 +62,9 @@ struct lbpf_ctx {
     size_t sbytes = 4;       // bytes per stored population
     size_t tbytes = 4;       // bytes per field value (compute type)
     size_t n = 0;            // nodes
-    size_t np = 0;           // population stride in elements
+    int px = 0;              // row pitch of the device arrays: nx rounded up to 32
+    size_t na = 0;           // elements of one device field array, px * ny * nz
+    size_t np = 0;           // population stride in elements (na rounded up to 64)
     void* pop[3][2] = {};    // [field][parity]
     void* fld[3][2] = {};    // phi, U, theta [parity]
     int cur = 0;
@@ -110,6 +112,7 @@ Coef<T> make_coef(const lbpf_ctx* ctx, int k = K_PHI) {
     const Shape sh = kShapes[ctx->shape[k]];
     Coef<T> c{};
     c.nx = g.nx; c.ny = g.ny; c.nz = g.nz;
+    c.px = ctx->px;
     c.symm = 0;
     for (int f = 0; f < 6; ++f)
         if (g.wall[f] == LBPF_WALL_SYMMETRY) c.symm |= 1 << f;

@@ -38,6 +38,10 @@
  *  R8  The derivative of a_s printed in Sec. 3.4 (eq. Derivees_As) has a typo
  *      in its index list for the second component; the indices used here are
  *      (alpha,beta,gamma) = (x,y,z), (y,x,z), (z,x,y).
+ *  R20 Advection (end of Sec. 3.1): only theta is advected, by the uniform
+ *      velocity of the parameters or by a per-node field that replaces it;
+ *      the equilibrium at node x takes v(x).  Walls bounce back the whole
+ *      population, the advective part included.
  */
 #include "lbpf_oracle.h"
 

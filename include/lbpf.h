@@ -106,9 +106,9 @@ typedef struct {
                                advection-diffusion equilibrium of Sec. 3.1,
                                w_i theta (1 + e_i.v dt / (e^2 dx)). All zero
                                (the paper's runs) is the pure-diffusion scheme.
-                               Nonzero keeps k_ut on its default tile
-                               (lbpf_set_launch refuses other k_ut tiles,
-                               lbpf_autotune does not try them) and is refused by
+                               Nonzero runs k_ut on its advection tile, 32x8
+                               (FP64 32x4): lbpf_set_launch refuses other k_ut
+                               tiles, lbpf_autotune does not try them. Refused by
                                lbpf_batch_create; non-finite -> LBPF_EINVAL. */
 } lbpf_params;
 
@@ -229,8 +229,9 @@ lbpf_status lbpf_debug_stream_only(lbpf_ctx* ctx, int64_t nsteps);
  * The field replaces lbpf_params.vel; all three NULL removes it.  It acts
  * from the next step and in the next lbpf_set_fields (whose theta
  * populations start from the advective equilibrium: set the field first to
- * start there).  Puts k_ut back on its default tile, the only one with the
- * advective variant, and drops a captured step graph.  Synchronises.
+ * start there).  Puts k_ut on its advection tile (32x8; FP64 32x4), the
+ * only one with the advective variant, and drops a captured step graph.
+ * Removing the field leaves k_ut's launch as it is.  Synchronises.
  * Errors: EINVAL (one or two NULL, non-finite value), ESTATE (a batch
  * member), ENOMEM. */
 lbpf_status lbpf_set_velocity_field(lbpf_ctx* ctx, const double* vx, const double* vy, const double* vz);
@@ -257,9 +258,11 @@ lbpf_status lbpf_kernel_times(lbpf_ctx* ctx, double ms[3], int64_t launches[3]);
  * that moves the most bytes; lbpf_get_kernel_launch either.
  * Defaults: k_phi 32x8, zslab 6 (FP32) or 8 (16-bit); k_ut 64x4 zslab 6
  * (FP32) or 32x8 zslab 8 (16-bit); FP64 32x4 zslab 4 for both; remap 1.
- * With an advective velocity (lbpf_params.vel) k_ut keeps its default tile.
- * Errors: EINVAL (unsupported shape, flag or kernel index; a k_ut tile
- * other than the default while advecting). */
+ * With an advective velocity (lbpf_params.vel or a velocity field) k_ut
+ * runs on its advection tile, 32x8 (FP64 32x4), the only one with the
+ * advective variant.
+ * Errors: EINVAL (unsupported shape, flag or kernel index; another k_ut
+ * tile while advecting). */
 lbpf_status lbpf_set_launch(lbpf_ctx* ctx, int32_t tile_x, int32_t tile_y, int32_t zslab,
                             int32_t xcd_remap);
 lbpf_status lbpf_get_launch(lbpf_ctx* ctx, int32_t* tile_x, int32_t* tile_y, int32_t* zslab,

@@ -362,6 +362,7 @@ lbpf_status lbpf_create(const lbpf_grid* grid, const lbpf_params* params, void* 
         ctx->zslab[k] = kDefaultZslab[k][g.storage];
         ctx->remap[k] = 1;
     }
+    if (has_advection(ctx)) ctx->shape[K_UT] = adv_shape(ctx);
     ctx->n = (size_t)g.nx * g.ny * g.nz;
     // rows start on 128-byte lines (FP32): a tile row then reads whole lines
     ctx->px = (g.nx + 31) / 32 * 32;
@@ -659,8 +660,8 @@ lbpf_status lbpf_set_kernel_launch(lbpf_ctx* ctx, int32_t kernel, int32_t tile_x
         if (kShapes[i].tx != tile_x || kShapes[i].ty != tile_y) continue;
         const bool ok = ctx->storage == LBPF_F64 ? (i == 0 || i == 2) : true;
         if (!ok) return fail(ctx, LBPF_EINVAL, "tile shape not available for FP64 storage");
-        if (kernel == K_UT && has_advection(ctx) && i != default_shape(ctx, K_UT))
-            return fail(ctx, LBPF_EINVAL, "advection runs on the default k_ut tile only");
+        if (kernel == K_UT && has_advection(ctx) && i != adv_shape(ctx))
+            return fail(ctx, LBPF_EINVAL, kAdvTileMsg);
         ctx->shape[kernel] = i;
         ctx->zslab[kernel] = zslab;
         ctx->remap[kernel] = xcd_remap;
@@ -738,7 +739,7 @@ lbpf_status lbpf_autotune(lbpf_ctx* ctx, int32_t steps_per_candidate, double* be
                 ctx->zslab[k] = zsl;
                 ctx->remap[k] = zi / NZ;
             }
-            if (has_advection(ctx)) ctx->shape[K_UT] = default_shape(ctx, K_UT);
+            if (has_advection(ctx)) ctx->shape[K_UT] = adv_shape(ctx);
             for (int w = 0; w < 2 && !st; ++w) st = launch_step(ctx);
             if (!st) st = drain_launches(ctx, nullptr, nullptr);
             for (int k = 0; k < steps_per_candidate && !st; ++k) st = launch_step(ctx);
@@ -835,8 +836,8 @@ lbpf_status lbpf_set_velocity_field(lbpf_ctx* ctx, const double* vx, const doubl
             return fail(ctx, LBPF_ENOMEM, "hipMalloc of the velocity field failed");
         }
         CHK(hipMemcpy(ctx->vfield, host.data(), host.size(), hipMemcpyHostToDevice));
-        // the advective variant of k_ut exists for its default tile only
-        ctx->shape[K_UT] = default_shape(ctx, K_UT);
+        // the advective variant of k_ut exists for one tile
+        ctx->shape[K_UT] = adv_shape(ctx);
     }
     // a captured step loop holds the old constants
     if (ctx->gexec) (void)hipGraphExecDestroy(ctx->gexec);

@@ -45,6 +45,11 @@ enum { K_PHI = 0, K_UT = 1 };
 // within one block) and 32x8 with 16-bit ones; FP64 has 64x2 and 32x4 only.
 constexpr int kDefaultShape[2][4] = {{3, 3, 3, 2}, {1, 3, 3, 2}};
 constexpr int kDefaultZslab[2][4] = {{6, 8, 8, 4}, {6, 8, 8, 4}};
+// The one k_ut tile with the advection-diffusion variant: 32x8 (FP64 32x4).
+// Its wider halo terms (four values per node instead of one) would cost the
+// 64x4 FP32 tile a block per CU.
+constexpr int kAdvShape[4] = {3, 3, 3, 2};
+const char* const kAdvTileMsg = "advection runs k_ut on its advection tile only (32x8; FP64 32x4)";
 
 }  // namespace lbpf_rt
 
@@ -160,6 +165,8 @@ inline bool has_advection(const lbpf_ctx* ctx) {
 }
 
 inline int default_shape(const lbpf_ctx* ctx, int k) { return kDefaultShape[k][ctx->storage]; }
+
+inline int adv_shape(const lbpf_ctx* ctx) { return kAdvShape[ctx->storage]; }
 
 inline int total_tiles(const lbpf_ctx* ctx, int k) {
     const Shape sh = kShapes[ctx->shape[k]];

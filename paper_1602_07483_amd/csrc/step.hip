@@ -28,10 +28,10 @@ lbpf_status launch_ut(lbpf_ctx* ctx) {
     const Coef<T> c = make_coef<T>(ctx, K_UT);
     const int nb = total_tiles(ctx, K_UT);
     const int a = ctx->cur, b = 1 - ctx->cur;
-    // the advection-diffusion variant exists for the default k_ut tile only
-    constexpr int kDef = kDefaultShape[K_UT][LBPF_STEP_STORAGE];
-    constexpr bool kAdvTile = TX == kShapes[kDef].tx && TY == kShapes[kDef].ty;
-    if (c.has_adv && !kAdvTile) return fail(ctx, LBPF_EINVAL, "advection runs on the default k_ut tile only");
+    // the advection-diffusion variant exists for one tile
+    constexpr int kAdv = kAdvShape[LBPF_STEP_STORAGE];
+    constexpr bool kAdvTile = TX == kShapes[kAdv].tx && TY == kShapes[kAdv].ty;
+    if (c.has_adv && !kAdvTile) return fail(ctx, LBPF_EINVAL, kAdvTileMsg);
     return timed(ctx, K_UT, [&] {
         auto args = [&](auto kern) {
             hipLaunchKernelGGL(kern, dim3(nb), dim3(TX * TY), 0, ctx->stream, c, (const S*)ctx->pop[1][a],

@@ -183,14 +183,14 @@ def test_advection_matches_oracle(lattice, storage, tol):
 
 
 def test_advection_keeps_default_tile():
-    """With an advective velocity k_ut stays on its default tile (the only
+    """With an advective velocity k_ut stays on its advection tile (the only
     one with the advective variant); k_phi may take any."""
     pb = dataclasses.replace(ragged_problem(19, 0), vel=ADV_VEL)
     s = make_gpu(pb, storage="f32")
     ut = s.get_kernel_launch(1)
     phi = s.get_kernel_launch(0)
     other = (32, 16) if ut[:2] != (32, 16) else (32, 4)
-    with pytest.raises(lbpf.LbpfError, match="default k_ut tile"):
+    with pytest.raises(lbpf.LbpfError, match="advection tile"):
         s.set_launch(other[0], other[1], 4, 1)
     assert s.get_kernel_launch(1) == ut and s.get_kernel_launch(0) == phi   # all or nothing
     s.set_kernel_launch(0, other[0], other[1], 4, 1)                         # k_phi is free

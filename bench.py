@@ -66,7 +66,10 @@ def run_gpu(storage, steps, warmup, n, launch=None):
     pb.reduce_every = 0
     stream = torch.cuda.current_stream().cuda_stream
     s = lbpf.solver_for(pb, storage=storage, stream=stream)
-    s.set_fields(*pb.initial_fields())
+    fields0 = pb.initial_fields()
+    t_in = time.perf_counter()
+    s.set_fields(*fields0)          # host -> device copy and initial populations
+    t_in = time.perf_counter() - t_in
     if launch == "auto":
         # launch of each kernel picked by the library's autotuner (state restored after)
         s.autotune(6)
@@ -84,7 +87,9 @@ def run_gpu(storage, steps, warmup, n, launch=None):
     wall = time.perf_counter() - t0
     ms, cnt = s.kernel_times()
     s.set_timing(False)
-    _, _, _, red = s.read()
+    t_out = time.perf_counter()
+    _, _, _, red = s.read()          # device -> host copy of the fields and the reductions
+    t_out = time.perf_counter() - t_out
     s.close()
     lups = float(n) ** 3 * steps
     b = lbpf.lbpf_storage_bytes(lbpf.STORAGE[storage])
@@ -100,7 +105,11 @@ def run_gpu(storage, steps, warmup, n, launch=None):
                        for k, v in launches.items()},
             "algorithmic_GBps": lups * (bpl["k_phi"] + bpl["k_ut"]) / wall / 1e9,
             "kernels": kern, "solid_fraction": red["solid_fraction"],
-            "phi_range": [red["phi_min"], red["phi_max"]]}
+            "phi_range": [red["phi_min"], red["phi_max"]],
+            # the same steps with the host hand-over at both ends (fields in
+            # and out through lbpf_set_fields / lbpf_read); not the headline
+            "host_io": {"set_fields_ms": t_in * 1e3, "read_ms": t_out * 1e3,
+                        "mlups_with_host_io": lups / (wall + t_in + t_out) / 1e6}}
 
 
 def run_ensemble(steps, seq_steps, storage="f16", graph_steps=50):
@@ -293,6 +302,7 @@ def main():
         "algorithmic_GBps": res["algorithmic_GBps"],
         "launch": res["launch"],
         "kernels": res["kernels"],
+        "host_io": res["host_io"],
         "variants": variants,
         "roofline": roofline,
         "cpu_baseline": cpu,

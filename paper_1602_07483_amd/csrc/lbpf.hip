@@ -251,6 +251,17 @@ bool healthy(const lbpf_reductions& r) {
     return r.nonfinite == 0.0 && r.phi_max <= 1.0 + 1e-3 && r.phi_min >= -1.0 - 1e-3;
 }
 
+// Host staging between the caller's packed rows (nx values) and the device
+// layout (rows px values apart): one linear copy instead of a copy per row.
+void pack_rows(void* dst, const void* src, size_t row_bytes, size_t pitch_bytes, size_t rows) {
+    for (size_t r = 0; r < rows; ++r)
+        std::memcpy((char*)dst + r * pitch_bytes, (const char*)src + r * row_bytes, row_bytes);
+}
+void unpack_rows(void* dst, const void* src, size_t row_bytes, size_t pitch_bytes, size_t rows) {
+    for (size_t r = 0; r < rows; ++r)
+        std::memcpy((char*)dst + r * row_bytes, (const char*)src + r * pitch_bytes, row_bytes);
+}
+
 // Waits for the stream and moves the recorded launch events back to the
 // pool, adding their durations to ms[kind] and counts to n[kind] when given.
 lbpf_status drain_launches(lbpf_ctx* ctx, double* ms, int64_t* n) {
@@ -405,16 +416,17 @@ lbpf_status lbpf_set_fields(lbpf_ctx* ctx, const double* phi, const double* U, c
     ctx->cur = 0;
     const double* src[3] = {phi, U, theta};
     for (int f = 0; f < 3; ++f) {
-        const size_t nx = ctx->grid.nx, rows = (size_t)ctx->grid.ny * ctx->grid.nz;
+        const size_t nx = ctx->grid.nx, px = ctx->px, rows = (size_t)ctx->grid.ny * ctx->grid.nz;
         if (ctx->tbytes == 8) {
-            CHK(hipMemcpy2DAsync(ctx->fld[f][0], ctx->px * 8, src[f], nx * 8, nx * 8, rows,
-                                 hipMemcpyHostToDevice, ctx->stream));
+            std::vector<double> tmp(ctx->na, 0.0);
+            pack_rows(tmp.data(), src[f], nx * 8, px * 8, rows);
+            CHK(hipMemcpyAsync(ctx->fld[f][0], tmp.data(), ctx->na * 8, hipMemcpyHostToDevice, ctx->stream));
             CHK(hipStreamSynchronize(ctx->stream));
         } else {
-            std::vector<float> tmp(ctx->n);
-            for (size_t i = 0; i < ctx->n; ++i) tmp[i] = (float)src[f][i];
-            CHK(hipMemcpy2DAsync(ctx->fld[f][0], ctx->px * 4, tmp.data(), nx * 4, nx * 4, rows,
-                                 hipMemcpyHostToDevice, ctx->stream));
+            std::vector<float> tmp(ctx->na, 0.f);
+            for (size_t r = 0; r < rows; ++r)
+                for (size_t x = 0; x < nx; ++x) tmp[r * px + x] = (float)src[f][r * nx + x];
+            CHK(hipMemcpyAsync(ctx->fld[f][0], tmp.data(), ctx->na * 4, hipMemcpyHostToDevice, ctx->stream));
             CHK(hipStreamSynchronize(ctx->stream));
         }
     }
@@ -534,15 +546,16 @@ lbpf_status lbpf_read(lbpf_ctx* ctx, double* phi, double* U, double* theta, lbpf
     CHK(hipStreamSynchronize(ctx->stream));
     for (int f = 0; f < 3; ++f) {
         if (!dst[f]) continue;
-        const size_t nx = ctx->grid.nx, rows = (size_t)ctx->grid.ny * ctx->grid.nz;
+        const size_t nx = ctx->grid.nx, px = ctx->px, rows = (size_t)ctx->grid.ny * ctx->grid.nz;
         if (ctx->tbytes == 8) {
-            CHK(hipMemcpy2D(dst[f], nx * 8, ctx->fld[f][ctx->cur], ctx->px * 8, nx * 8, rows,
-                            hipMemcpyDeviceToHost));
+            std::vector<double> tmp(ctx->na);
+            CHK(hipMemcpy(tmp.data(), ctx->fld[f][ctx->cur], ctx->na * 8, hipMemcpyDeviceToHost));
+            unpack_rows(dst[f], tmp.data(), nx * 8, px * 8, rows);
         } else {
-            std::vector<float> tmp(ctx->n);
-            CHK(hipMemcpy2D(tmp.data(), nx * 4, ctx->fld[f][ctx->cur], ctx->px * 4, nx * 4, rows,
-                            hipMemcpyDeviceToHost));
-            for (size_t i = 0; i < ctx->n; ++i) dst[f][i] = (double)tmp[i];
+            std::vector<float> tmp(ctx->na);
+            CHK(hipMemcpy(tmp.data(), ctx->fld[f][ctx->cur], ctx->na * 4, hipMemcpyDeviceToHost));
+            for (size_t r = 0; r < rows; ++r)
+                for (size_t x = 0; x < nx; ++x) dst[f][r * nx + x] = (double)tmp[r * px + x];
         }
     }
     if (red) {
@@ -581,11 +594,14 @@ lbpf_status lbpf_read_populations(lbpf_ctx* ctx, int32_t field, void* dst) {
     if (!ctx) return LBPF_EINVAL;
     if (field < 0 || field > 2 || !dst) return fail(ctx, LBPF_EINVAL, "bad field or NULL dst");
     CHK(hipStreamSynchronize(ctx->stream));
-    const size_t arr = ctx->n * ctx->sbytes, w = ctx->grid.nx * ctx->sbytes;
+    const size_t arr = ctx->n * ctx->sbytes, w = ctx->grid.nx * ctx->sbytes, pw = ctx->px * ctx->sbytes;
     const size_t rows = (size_t)ctx->grid.ny * ctx->grid.nz;
-    for (int i = 0; i < ctx->q; ++i)
-        CHK(hipMemcpy2D((char*)dst + i * arr, w, (const char*)ctx->pop[field][ctx->cur] + i * ctx->np * ctx->sbytes,
-                        ctx->px * ctx->sbytes, w, rows, hipMemcpyDeviceToHost));
+    std::vector<char> tmp(ctx->na * ctx->sbytes);
+    for (int i = 0; i < ctx->q; ++i) {
+        CHK(hipMemcpy(tmp.data(), (const char*)ctx->pop[field][ctx->cur] + i * ctx->np * ctx->sbytes, tmp.size(),
+                      hipMemcpyDeviceToHost));
+        unpack_rows((char*)dst + i * arr, tmp.data(), w, pw, rows);
+    }
     return LBPF_OK;
 }
 
@@ -594,11 +610,14 @@ lbpf_status lbpf_write_populations(lbpf_ctx* ctx, int32_t field, const void* src
     if (field < 0 || field > 2 || !src) return fail(ctx, LBPF_EINVAL, "bad field or NULL src");
     if (!ctx->have_fields) return fail(ctx, LBPF_ESTATE, "lbpf_set_fields has not been called");
     CHK(hipStreamSynchronize(ctx->stream));
-    const size_t arr = ctx->n * ctx->sbytes, w = ctx->grid.nx * ctx->sbytes;
+    const size_t arr = ctx->n * ctx->sbytes, w = ctx->grid.nx * ctx->sbytes, pw = ctx->px * ctx->sbytes;
     const size_t rows = (size_t)ctx->grid.ny * ctx->grid.nz;
-    for (int i = 0; i < ctx->q; ++i)
-        CHK(hipMemcpy2D((char*)ctx->pop[field][ctx->cur] + i * ctx->np * ctx->sbytes, ctx->px * ctx->sbytes,
-                        (const char*)src + i * arr, w, w, rows, hipMemcpyHostToDevice));
+    std::vector<char> tmp(ctx->na * ctx->sbytes, 0);
+    for (int i = 0; i < ctx->q; ++i) {
+        pack_rows(tmp.data(), (const char*)src + i * arr, w, pw, rows);
+        CHK(hipMemcpy((char*)ctx->pop[field][ctx->cur] + i * ctx->np * ctx->sbytes, tmp.data(), tmp.size(),
+                      hipMemcpyHostToDevice));
+    }
     return LBPF_OK;
 }
 

@@ -110,6 +110,15 @@ typedef struct {
                                (FP64 32x4): lbpf_set_launch refuses other k_ut
                                tiles, lbpf_autotune does not try them. Refused by
                                lbpf_batch_create; non-finite -> LBPF_EINVAL. */
+    int32_t skip_U;         /* 1: pure substance (Mcinf must be 0, as in the
+                               thermal dendrites of Sec. 4.1 and 4.3, where U
+                               does not act on phi): U is not advanced, its
+                               field keeps the value lbpf_set_fields gave it and
+                               the h populations are left untouched; k_ut then
+                               moves only the theta populations.  Runs k_ut on
+                               its advection tile (32x8; FP64 32x4).  0: solve U.
+                               Other values, or 1 with Mcinf != 0, are
+                               LBPF_EINVAL; batches refuse 1. */
 } lbpf_params;
 
 /* Diagnostics of one state, accumulated in FP64 on the device.  The paper

@@ -602,8 +602,10 @@ __device__ __forceinline__ void phi_body(const Coef<T>& c, int block, const S* _
 // For i > 0 the pull needs only Z = P + C + S, theta + dphi/2 and K of the
 // source, so the halo terms in LDS are (Z, theta + dphi/2, Kx, Ky) and Kz;
 // the tile's own (P, C, S, r) sit in a separate two-plane array.
+// SU = false (pure substance, M c_inf = 0, where U does not act on phi):
+// only theta is advanced; U is carried over unchanged and h is not touched.
 // ==========================================================================
-template <class L, class T, class S, int TX, int TY, bool BUF, bool ADV = false>
+template <class L, class T, class S, int TX, int TY, bool BUF, bool ADV = false, bool SU = true>
 __device__ __forceinline__ void ut_body(const Coef<T>& c, int block, const S* __restrict__ hin,
                                         S* __restrict__ hout, const S* __restrict__ fin,
                                         S* __restrict__ fout, const T* __restrict__ phio,
@@ -658,7 +660,7 @@ __device__ __forceinline__ void ut_body(const Coef<T>& c, int block, const S* __
                     const int gx = clampi(tile.x0 - 1 + t % G::HX, nx), gy = clampi(tile.y0 - 1 + t / G::HX, ny);
                     const size_t gi = base + (size_t)gy * px + gx;
                     po_[kk] = phio[gi];
-                    pu[kk] = Un[gi];
+                    if constexpr (SU) pu[kk] = Un[gi];
                     pt[kk] = thn[gi];
                     if constexpr (ADV) {
                         if (c.advf) {
@@ -692,11 +694,11 @@ __device__ __forceinline__ void ut_body(const Coef<T>& c, int block, const S* __
                     // 128-byte lines, every line of a source row is read by
                     // this block alone, once.
                     constexpr int CP = ex == 0 && (TX * sizeof(S)) % 128 == 0 ? 2 : 0;
-                    ph_[I] = Raw<S>::template ld<CP>(rhin, vj, sj);
+                    if constexpr (SU) ph_[I] = Raw<S>::template ld<CP>(rhin, vj, sj);
                     pf_[I] = Raw<S>::template ld<CP>(rfin, vj, sj);
                 } else {
                     const unsigned so = cr ? xi : xi - (unsigned)off;
-                    ph_[I] = Raw<S>::ldg(hin + (size_t)I * np + so);
+                    if constexpr (SU) ph_[I] = Raw<S>::ldg(hin + (size_t)I * np + so);
                     pf_[I] = Raw<S>::ldg(fin + (size_t)I * np + so);
                 }
             });
@@ -747,8 +749,20 @@ __device__ __forceinline__ void ut_body(const Coef<T>& c, int block, const S* __
                         Fz = (nb[4].y - nb[5].y) * c.inv2dx;
                 const T gx_ = (nb[0].x - nb[1].x) * c.inv2dx, gy_ = (nb[2].x - nb[3].x) * c.inv2dx,
                         gz_ = (nb[4].x - nb[5].x) * c.inv2dx;
-                const T po = po_[kk], u = pu[kk], th = pt[kk];
+                const T po = po_[kk], u = SU ? pu[kk] : T(0), th = pt[kk];
                 const T dphi = p0 - po;
+                if constexpr (!SU) {   // theta terms only
+                    sa[t] = V4<T>{T(0), th + T(0.5) * dphi, T(0), T(0)};
+                    if constexpr (ADV) {
+                        const T ot = c.omT * th;
+                        const T ax = c.advf ? pv[0][kk] : c.adv[0], ay = c.advf ? pv[1][kk] : c.adv[1],
+                                az = c.advf ? pv[2][kk] : c.adv[2];
+                        sk[t] = V4<T>{T(0), ot * ax, ot * ay, ot * az};
+                    } else {
+                        sk[t] = T(0);
+                    }
+                    continue;
+                }
                 const T dtphi = dphi * c.inv_dt;
                 const T cu = T(1) + (T(1) - k) * u;
                 // anti-trapping current, eq. (AntiTrapping_Current)
@@ -807,7 +821,7 @@ __device__ __forceinline__ void ut_body(const Coef<T>& c, int block, const S* __
                 constexpr int I = decltype(ic)::value;
                 const Src s = source<L, I>(opaque_v(tile.x), opaque_v(tile.y), z, nx, ny, nz, c.symm);
                 const size_t si = ((size_t)s.sz * ny + s.sy) * px + s.sx;
-                const T dh = (T)Codec<S>::dec(hin[(size_t)s.j * np + si]);
+                const T dh = SU ? (T)Codec<S>::dec(hin[(size_t)s.j * np + si]) : T(0);
                 const T df = (T)Codec<S>::dec(fin[(size_t)s.j * np + si]);
                 const int tsl = (s.sz + 3) % 3, tl = (s.sy - tile.y0 + 1) * G::HX + (s.sx - tile.x0 + 1);
                 const V4<T> ta = sta[tsl][tl];
@@ -823,7 +837,7 @@ __device__ __forceinline__ void ut_body(const Coef<T>& c, int block, const S* __
                     eK += T(ejz) * stk[tsl][tl];
                 }
                 // I > 0 here: A_I = 0, B_I = w_I
-                vu = wi * (ta.x - Px + eK) + omU1 * dh;
+                if constexpr (SU) vu = wi * (ta.x - Px + eK) + omU1 * dh;
                 vt = wi * (ta.y - thx + eA) + omT1 * df;
             };
             auto fast = [&](auto ic, auto edge_c) {
@@ -833,10 +847,10 @@ __device__ __forceinline__ void ut_body(const Coef<T>& c, int block, const S* __
                 constexpr T wi = T(L::w(I));
                 const int tl = tile.lt - ex - ey * G::HX;
                 const V4<T> ta = sta[sl[1 - ez]][tl];
-                T vu, vt;
+                T vu = T(0), vt;
                 T eA = T(0);
                 if constexpr (I == 0) {
-                    vu = (wi - T(1)) * Cx + wi * Sx + omU1 * (T)Raw<S>::dec(ph_[I]);
+                    if constexpr (SU) vu = (wi - T(1)) * Cx + wi * Sx + omU1 * (T)Raw<S>::dec(ph_[I]);
                 } else {
                     T eK = T(ex) * ta.z + T(ey) * ta.w;
                     if constexpr (ADV) {
@@ -846,7 +860,7 @@ __device__ __forceinline__ void ut_body(const Coef<T>& c, int block, const S* __
                     } else {
                         if constexpr (ez != 0) eK += T(ez) * stk[sl[1 - ez]][tl];
                     }
-                    vu = wi * (ta.x - Px + eK) + omU1 * (T)Raw<S>::dec(ph_[I]);
+                    if constexpr (SU) vu = wi * (ta.x - Px + eK) + omU1 * (T)Raw<S>::dec(ph_[I]);
                 }
                 vt = wi * (ta.y - thx + eA) + omT1 * (T)Raw<S>::dec(pf_[I]);
                 if constexpr (EDGE && I != 0) {
@@ -860,7 +874,7 @@ __device__ __forceinline__ void ut_body(const Coef<T>& c, int block, const S* __
                 Unroll<0, L::Q>::run([&](auto ic) { fast(ic, std::false_type{}); });
             else
                 Unroll<0, L::Q>::run([&](auto ic) { fast(ic, std::true_type{}); });
-            Uout[xi] = Ux + du;
+            Uout[xi] = SU ? Ux + du : Ux;
             thout[xi] = thx + dth;
             // (r^o_x - r_x) U_x - r_x dU, with (r^o_x - r_x) U_x = -C_x / omega_U
             const T hb = -Cx * c.etaU - rx * du;
@@ -872,10 +886,10 @@ __device__ __forceinline__ void ut_body(const Coef<T>& c, int block, const S* __
                 const S hv = Codec<S>::enc(dhv), fv = Codec<S>::enc(it[I] - wi * dth);
                 if constexpr (BUF) {
                     const unsigned vx = xi * (unsigned)sizeof(S), sI = (unsigned)(I * np) * (unsigned)sizeof(S);
-                    buf_st(hv, rhout, vx, sI);
+                    if constexpr (SU) buf_st(hv, rhout, vx, sI);
                     buf_st(fv, rfout, vx, sI);
                 } else {
-                    st_nt(&hout[(size_t)I * np + xi], hv);
+                    if constexpr (SU) st_nt(&hout[(size_t)I * np + xi], hv);
                     st_nt(&fout[(size_t)I * np + xi], fv);
                 }
             });
@@ -897,12 +911,13 @@ __global__ __launch_bounds__(TX * TY, (sizeof(T) == 4 ? 4 : 1)) void k_phi(
     phi_body<L, T, S, TX, TY, BUF>(c, blockIdx.x, gin, gout, phin, Un, thn, phout);
 }
 
-template <class L, class T, class S, int TX, int TY, bool BUF, bool ADV = false>
+template <class L, class T, class S, int TX, int TY, bool BUF, bool ADV = false, bool SU = true>
 __global__ __launch_bounds__(TX * TY, (sizeof(T) == 4 ? 3 : 1)) void k_ut(
     const Coef<T> c, const S* __restrict__ hin, S* __restrict__ hout, const S* __restrict__ fin,
     S* __restrict__ fout, const T* __restrict__ phio, const T* __restrict__ phnew,
     const T* __restrict__ Un, const T* __restrict__ thn, T* __restrict__ Uout, T* __restrict__ thout) {
-    ut_body<L, T, S, TX, TY, BUF, ADV>(c, blockIdx.x, hin, hout, fin, fout, phio, phnew, Un, thn, Uout, thout);
+    ut_body<L, T, S, TX, TY, BUF, ADV, SU>(c, blockIdx.x, hin, hout, fin, fout, phio, phnew, Un, thn, Uout,
+                                           thout);
 }
 
 template <class T>

@@ -350,6 +350,9 @@ lbpf_status lbpf_create(const lbpf_grid* grid, const lbpf_params* params, void* 
     if (p.reduce_every < 0) return fail(nullptr, LBPF_EINVAL, "reduce_every < 0");
     if (!std::isfinite(p.vel[0]) || !std::isfinite(p.vel[1]) || !std::isfinite(p.vel[2]))
         return fail(nullptr, LBPF_EINVAL, "advective velocity must be finite");
+    if (p.skip_U != 0 && p.skip_U != 1) return fail(nullptr, LBPF_EINVAL, "skip_U must be 0 or 1");
+    if (p.skip_U && p.Mcinf != 0.0)
+        return fail(nullptr, LBPF_EINVAL, "skip_U needs Mcinf = 0 (otherwise U acts on phi)");
 
     lbpf_ctx* ctx = new (std::nothrow) lbpf_ctx();
     if (!ctx) return fail(nullptr, LBPF_ENOMEM, "host allocation failed");
@@ -373,7 +376,7 @@ lbpf_status lbpf_create(const lbpf_grid* grid, const lbpf_params* params, void* 
         ctx->zslab[k] = kDefaultZslab[k][g.storage];
         ctx->remap[k] = 1;
     }
-    if (has_advection(ctx)) ctx->shape[K_UT] = adv_shape(ctx);
+    if (ut_pinned(ctx)) ctx->shape[K_UT] = adv_shape(ctx);
     ctx->n = (size_t)g.nx * g.ny * g.nz;
     // rows start on 128-byte lines (FP32): a tile row then reads whole lines
     ctx->px = (g.nx + 31) / 32 * 32;
@@ -679,7 +682,7 @@ lbpf_status lbpf_set_kernel_launch(lbpf_ctx* ctx, int32_t kernel, int32_t tile_x
         if (kShapes[i].tx != tile_x || kShapes[i].ty != tile_y) continue;
         const bool ok = ctx->storage == LBPF_F64 ? (i == 0 || i == 2) : true;
         if (!ok) return fail(ctx, LBPF_EINVAL, "tile shape not available for FP64 storage");
-        if (kernel == K_UT && has_advection(ctx) && i != adv_shape(ctx))
+        if (kernel == K_UT && ut_pinned(ctx) && i != adv_shape(ctx))
             return fail(ctx, LBPF_EINVAL, kAdvTileMsg);
         ctx->shape[kernel] = i;
         ctx->zslab[kernel] = zslab;
@@ -758,7 +761,7 @@ lbpf_status lbpf_autotune(lbpf_ctx* ctx, int32_t steps_per_candidate, double* be
                 ctx->zslab[k] = zsl;
                 ctx->remap[k] = zi / NZ;
             }
-            if (has_advection(ctx)) ctx->shape[K_UT] = adv_shape(ctx);
+            if (ut_pinned(ctx)) ctx->shape[K_UT] = adv_shape(ctx);
             for (int w = 0; w < 2 && !st; ++w) st = launch_step(ctx);
             if (!st) st = drain_launches(ctx, nullptr, nullptr);
             for (int k = 0; k < steps_per_candidate && !st; ++k) st = launch_step(ctx);
@@ -1031,6 +1034,7 @@ lbpf_status lbpf_batch_create(int32_t n, const lbpf_grid* grids, const lbpf_para
             return bfail(nullptr, LBPF_EINVAL, "batched domains use D3Q15 or D3Q19");
         if (params[i].vel[0] != 0.0 || params[i].vel[1] != 0.0 || params[i].vel[2] != 0.0)
             return bfail(nullptr, LBPF_EINVAL, "batched domains have no advective velocity");
+        if (params[i].skip_U) return bfail(nullptr, LBPF_EINVAL, "batched domains solve U");
     }
     lbpf_batch* b = new (std::nothrow) lbpf_batch();
     if (!b) return bfail(nullptr, LBPF_ENOMEM, "host allocation failed");

@@ -70,7 +70,7 @@ def main(argv=None):
     args = ap.parse_args(argv)
     pb = problem(args.case, args.n)
     steps = args.steps or pb.steps
-    s = lbpf.solver_for(pb, storage=args.storage)
+    s = lbpf.solver_for(pb, storage=args.storage, skip_U=1)   # pure substance: theta only
     s.set_fields(*pb.initial_fields())
     chunk = max(1, steps // args.records)
     done, stepping = 0, 0.0

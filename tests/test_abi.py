@@ -72,3 +72,17 @@ def test_storage_bytes_and_invalid_arguments_without_gpu():
     assert L.lbpf_batch_create(1, grids, params, None, ctypes.byref(h)) == lbpf.LBPF_EINVAL
     assert b"advective velocity" in L.lbpf_batch_last_error(None)
     assert not h.value
+    # skip_U: 0 or 1, only for a pure substance, never in a batch
+    p.vel[0] = 0.0
+    p.Mcinf = 1.0
+    p.skip_U = 2
+    assert L.lbpf_create(ctypes.byref(g), ctypes.byref(p), None, ctypes.byref(h)) == lbpf.LBPF_EINVAL
+    p.skip_U = 1
+    assert L.lbpf_create(ctypes.byref(g), ctypes.byref(p), None, ctypes.byref(h)) == lbpf.LBPF_EINVAL
+    assert b"Mcinf" in L.lbpf_last_error(None)
+    p.Mcinf = 0.0
+    grids = (lbpf.lbpf_grid * 1)(g)
+    params = (lbpf.lbpf_params * 1)(p)
+    assert L.lbpf_batch_create(1, grids, params, None, ctypes.byref(h)) == lbpf.LBPF_EINVAL
+    assert b"solve U" in L.lbpf_batch_last_error(None)
+    assert not h.value

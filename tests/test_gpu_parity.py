@@ -291,3 +291,27 @@ def test_degenerate_domains_match_oracle(shape, walls, lattice):
     for field in range(3):
         assert np.array_equal(s.read_populations(field).view(np.float64), o.pops(field))
     s.step(0)                                     # zero steps is a no-op
+
+
+# ------------------------------------------------------------- pure substance, theta only
+@pytest.mark.parametrize("lattice,storage,tol,vel", [(19, "f64", 1e-11, (0.0, 0.0, 0.0)),
+                                                     (7, "f64", 1e-11, (0.0, 0.0, 0.0)),
+                                                     (19, "f32", 1e-5, (0.0, 0.0, 0.0)),
+                                                     (19, "f64", 1e-11, ADV_VEL)])
+def test_skip_U_matches_oracle(lattice, storage, tol, vel):
+    """Pure substance (M c_inf = 0: U does not act on phi) with skip_U: phi and
+    theta as the oracle's full step, U left exactly as set."""
+    pb = dataclasses.replace(ragged_problem(lattice, 0), Mcinf=0.0, vel=vel)
+    s = lbpf.solver_for(pb, storage=storage, skip_U=1)
+    s.set_fields(*pb.initial_fields())
+    U0 = s.read(reductions=False)[1]
+    o = make_oracle(pb)
+    s.step(60)
+    o.step(60)
+    gphi, gU, gth, _ = s.read(reductions=False)
+    ophi, _, oth = o.fields()
+    ephi, eth = maxabs(gphi, ophi), maxabs(gth, oth)
+    print("%s q%d skip_U: max|dphi| %.3e max|dtheta| %.3e" % (storage, lattice, ephi, eth))
+    assert max(ephi, eth) <= tol
+    assert np.array_equal(gU, U0)
+    assert s.launches()["k_ut"][:2] == ((32, 4) if storage == "f64" else (32, 8))

@@ -321,7 +321,7 @@ def test_preferred_growth_direction_sec_4_3(aniso, eps, delta, steps):
     pb = Problem("sec4.3", n, n, n, 19, walls, dx=0.01, dt=1.5e-5, W0=0.0125, tau0=1.5625e-4,
                  lam=10.0, Mcinf=0.0, k=0.15, D=1.0, kappa=1.0, aniso=aniso, eps=eps, delta=delta,
                  centres=[(-0.5, -0.5, -0.5)], radius=8.0, U0=0.0, theta0=-0.25)
-    s = make_gpu(pb, "f32")
+    s = make_gpu(pb, "f32", skip_U=1)          # pure substance: U does not act on phi
     s.step(steps)
     phi, _, _, red = s.read(check=False)
     s.close()

@@ -33,6 +33,7 @@ class OrcParams(ctypes.Structure):
         ("k", ctypes.c_double), ("D", ctypes.c_double), ("kappa", ctypes.c_double),
         ("aniso", ctypes.c_int32), ("eps", ctypes.c_double), ("delta", ctypes.c_double),
         ("vel", ctypes.c_double * 3),
+        ("skip_theta", ctypes.c_int32),
     ]
 
 
@@ -146,7 +147,7 @@ class Oracle:
 
     def __init__(self, nx, ny, nz, lattice=19, walls=(0,) * 6, dx=1.0, dt=1.0,
                  W0=1.0, tau0=1.0, lam=3.2, Mcinf=1.0, k=0.15, D=2.0, kappa=20.0,
-                 aniso=ANISO_CUBIC, eps=0.05, delta=0.0, vel=(0.0, 0.0, 0.0)):
+                 aniso=ANISO_CUBIC, eps=0.05, delta=0.0, vel=(0.0, 0.0, 0.0), skip_theta=0):
         lib = _load()
         p = OrcParams()
         p.nx, p.ny, p.nz = int(nx), int(ny), int(nz)
@@ -158,6 +159,7 @@ class Oracle:
         p.aniso, p.eps, p.delta = int(aniso), eps, delta
         for a in range(3):
             p.vel[a] = float(vel[a])
+        p.skip_theta = int(skip_theta)
         self.params = p
         self.shape = (int(nz), int(ny), int(nx))
         self.q = int(lattice)

@@ -40,6 +40,9 @@ typedef struct {
     double eps, delta;        /* anisotropy strengths */
     double vel[3];            /* uniform advective velocity of the heat equation
                                  (advection-diffusion equilibrium, Sec. 3.1) */
+    int32_t skip_theta;       /* 1: isothermal (Sec. 4.2 benchmark): theta is
+                                 held at its initial value, the heat equation
+                                 is not solved */
 } orc_params;
 
 typedef struct orc_ctx orc_ctx;

@@ -471,3 +471,42 @@ def test_sheared_gaussian_moments(lattice):
         s.init(phi0, U0, th0)
         s.step(5)
     assert all(np.array_equal(p, q) for p, q in zip(f.fields(), u.fields()))
+
+
+@pytest.mark.parametrize("q", [19, 7])
+def test_isothermal_uniform_recurrence(q):
+    """Isothermal runs (the alloy benchmark of Sec. 4.2 has theta = 0): with
+    the heat equation off, a uniform state follows the scalar recurrence
+    phi' = phi + dt/tau0 Q(phi, U, theta0), U' = U + [1 + (1-k)U](phi' - phi)
+    / (2 zeta(phi')) with theta0 fixed, and a growing seed leaves theta
+    bit-identical to its initial field."""
+    pb = dict(lattice=q, walls=(NOFLUX, SYMMETRY, NOFLUX, NOFLUX, SYMMETRY, NOFLUX), dx=1.0,
+              dt=0.15, W0=1.0, tau0=1.0, lam=3.2, Mcinf=1.0, k=0.15, D=2.0, kappa=20.0,
+              skip_theta=1)
+    o = Oracle(5, 4, 3, **pb)
+    phi, U, th = 0.3, -0.4, -0.2
+    o.init(np.full((3, 4, 5), phi), np.full((3, 4, 5), U), np.full((3, 4, 5), th))
+    k = pb["k"]
+    zeta = lambda f: 0.5 * (1 + k) - 0.5 * (1 - k) * f
+    for _ in range(150):
+        Q = (phi - pb["lam"] * (pb["Mcinf"] * U + th) * (1 - phi ** 2)) * (1 - phi ** 2)
+        p1 = phi + pb["dt"] / pb["tau0"] * Q
+        U = U + (1 + (1 - k) * U) * (p1 - phi) / (2 * zeta(p1))
+        phi = p1
+        o.step(1)
+        f = o.fields()
+        assert np.allclose(f[0], phi, atol=1e-13, rtol=0)
+        assert np.allclose(f[1], U, atol=1e-13, rtol=0)
+        assert np.array_equal(f[2], np.full((3, 4, 5), -0.2))
+    assert phi > 0.99
+    # a growing seed: theta untouched, phi and U differ from the thermal run
+    seed = Problem("iso", 20, 18, 16, q, (NOFLUX,) * 6, dt=0.11 if q == 7 else 0.15,
+                   centres=[(9.5, 8.5, 7.5)], radius=5.0, U0=-0.55, theta0=0.0)
+    a = Oracle(20, 18, 16, **dict(seed.model_kwargs(), skip_theta=1))
+    b = Oracle(20, 18, 16, **seed.model_kwargs())
+    for o2 in (a, b):
+        o2.init(*seed.initial_fields())
+        o2.step(40)
+    fa, fb = a.fields(), b.fields()
+    assert np.array_equal(fa[2], seed.initial_fields()[2])
+    assert np.max(np.abs(fa[0] - fb[0])) > 1e-3

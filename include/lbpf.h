@@ -119,6 +119,15 @@ typedef struct {
                                its advection tile (32x8; FP64 32x4).  0: solve U.
                                Other values, or 1 with Mcinf != 0, are
                                LBPF_EINVAL; batches refuse 1. */
+    int32_t skip_theta;     /* 1: isothermal (the alloy benchmark of Sec. 4.2
+                               has theta = 0): the heat equation is not solved,
+                               theta keeps the value lbpf_set_fields gave it
+                               and the f populations are left untouched; k_ut
+                               then moves only the U populations.  Runs k_ut on
+                               its advection tile.  0: solve theta.  Other
+                               values, 1 together with skip_U = 1 or with an
+                               advective velocity, are LBPF_EINVAL; batches
+                               refuse 1. */
 } lbpf_params;
 
 /* Diagnostics of one state, accumulated in FP64 on the device.  The paper

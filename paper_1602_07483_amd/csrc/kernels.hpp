@@ -604,8 +604,11 @@ __device__ __forceinline__ void phi_body(const Coef<T>& c, int block, const S* _
 // the tile's own (P, C, S, r) sit in a separate two-plane array.
 // SU = false (pure substance, M c_inf = 0, where U does not act on phi):
 // only theta is advanced; U is carried over unchanged and h is not touched.
+// ST = false (isothermal, theta = 0 in the alloy benchmark of Sec. 4.2): only
+// U is advanced; theta is carried over unchanged and f is not touched.
 // ==========================================================================
-template <class L, class T, class S, int TX, int TY, bool BUF, bool ADV = false, bool SU = true>
+template <class L, class T, class S, int TX, int TY, bool BUF, bool ADV = false, bool SU = true,
+          bool ST = true>
 __device__ __forceinline__ void ut_body(const Coef<T>& c, int block, const S* __restrict__ hin,
                                         S* __restrict__ hout, const S* __restrict__ fin,
                                         S* __restrict__ fout, const T* __restrict__ phio,
@@ -661,7 +664,7 @@ __device__ __forceinline__ void ut_body(const Coef<T>& c, int block, const S* __
                     const size_t gi = base + (size_t)gy * px + gx;
                     po_[kk] = phio[gi];
                     if constexpr (SU) pu[kk] = Un[gi];
-                    pt[kk] = thn[gi];
+                    if constexpr (ST) pt[kk] = thn[gi];
                     if constexpr (ADV) {
                         if (c.advf) {
                             pv[0][kk] = c.advf[gi];
@@ -695,11 +698,11 @@ __device__ __forceinline__ void ut_body(const Coef<T>& c, int block, const S* __
                     // this block alone, once.
                     constexpr int CP = ex == 0 && (TX * sizeof(S)) % 128 == 0 ? 2 : 0;
                     if constexpr (SU) ph_[I] = Raw<S>::template ld<CP>(rhin, vj, sj);
-                    pf_[I] = Raw<S>::template ld<CP>(rfin, vj, sj);
+                    if constexpr (ST) pf_[I] = Raw<S>::template ld<CP>(rfin, vj, sj);
                 } else {
                     const unsigned so = cr ? xi : xi - (unsigned)off;
                     if constexpr (SU) ph_[I] = Raw<S>::ldg(hin + (size_t)I * np + so);
-                    pf_[I] = Raw<S>::ldg(fin + (size_t)I * np + so);
+                    if constexpr (ST) pf_[I] = Raw<S>::ldg(fin + (size_t)I * np + so);
                 }
             });
         }
@@ -749,7 +752,7 @@ __device__ __forceinline__ void ut_body(const Coef<T>& c, int block, const S* __
                         Fz = (nb[4].y - nb[5].y) * c.inv2dx;
                 const T gx_ = (nb[0].x - nb[1].x) * c.inv2dx, gy_ = (nb[2].x - nb[3].x) * c.inv2dx,
                         gz_ = (nb[4].x - nb[5].x) * c.inv2dx;
-                const T po = po_[kk], u = SU ? pu[kk] : T(0), th = pt[kk];
+                const T po = po_[kk], u = SU ? pu[kk] : T(0), th = ST ? pt[kk] : T(0);
                 const T dphi = p0 - po;
                 if constexpr (!SU) {   // theta terms only
                     sa[t] = V4<T>{T(0), th + T(0.5) * dphi, T(0), T(0)};
@@ -822,7 +825,7 @@ __device__ __forceinline__ void ut_body(const Coef<T>& c, int block, const S* __
                 const Src s = source<L, I>(opaque_v(tile.x), opaque_v(tile.y), z, nx, ny, nz, c.symm);
                 const size_t si = ((size_t)s.sz * ny + s.sy) * px + s.sx;
                 const T dh = SU ? (T)Codec<S>::dec(hin[(size_t)s.j * np + si]) : T(0);
-                const T df = (T)Codec<S>::dec(fin[(size_t)s.j * np + si]);
+                const T df = ST ? (T)Codec<S>::dec(fin[(size_t)s.j * np + si]) : T(0);
                 const int tsl = (s.sz + 3) % 3, tl = (s.sy - tile.y0 + 1) * G::HX + (s.sx - tile.x0 + 1);
                 const V4<T> ta = sta[tsl][tl];
                 constexpr T wi = T(L::w(I));
@@ -838,7 +841,7 @@ __device__ __forceinline__ void ut_body(const Coef<T>& c, int block, const S* __
                 }
                 // I > 0 here: A_I = 0, B_I = w_I
                 if constexpr (SU) vu = wi * (ta.x - Px + eK) + omU1 * dh;
-                vt = wi * (ta.y - thx + eA) + omT1 * df;
+                if constexpr (ST) vt = wi * (ta.y - thx + eA) + omT1 * df;
             };
             auto fast = [&](auto ic, auto edge_c) {
                 constexpr int I = decltype(ic)::value;
@@ -847,7 +850,7 @@ __device__ __forceinline__ void ut_body(const Coef<T>& c, int block, const S* __
                 constexpr T wi = T(L::w(I));
                 const int tl = tile.lt - ex - ey * G::HX;
                 const V4<T> ta = sta[sl[1 - ez]][tl];
-                T vu = T(0), vt;
+                T vu = T(0), vt = T(0);
                 T eA = T(0);
                 if constexpr (I == 0) {
                     if constexpr (SU) vu = (wi - T(1)) * Cx + wi * Sx + omU1 * (T)Raw<S>::dec(ph_[I]);
@@ -862,7 +865,7 @@ __device__ __forceinline__ void ut_body(const Coef<T>& c, int block, const S* __
                     }
                     if constexpr (SU) vu = wi * (ta.x - Px + eK) + omU1 * (T)Raw<S>::dec(ph_[I]);
                 }
-                vt = wi * (ta.y - thx + eA) + omT1 * (T)Raw<S>::dec(pf_[I]);
+                if constexpr (ST) vt = wi * (ta.y - thx + eA) + omT1 * (T)Raw<S>::dec(pf_[I]);
                 if constexpr (EDGE && I != 0) {
                     if (crosses<L, I>(f)) wall_link(ic, vu, vt);
                     __builtin_amdgcn_sched_barrier(0);   // one wall link at a time
@@ -875,7 +878,7 @@ __device__ __forceinline__ void ut_body(const Coef<T>& c, int block, const S* __
             else
                 Unroll<0, L::Q>::run([&](auto ic) { fast(ic, std::true_type{}); });
             Uout[xi] = SU ? Ux + du : Ux;
-            thout[xi] = thx + dth;
+            thout[xi] = ST ? thx + dth : thx;
             // (r^o_x - r_x) U_x - r_x dU, with (r^o_x - r_x) U_x = -C_x / omega_U
             const T hb = -Cx * c.etaU - rx * du;
             Unroll<0, L::Q>::run([&](auto ic) {
@@ -887,10 +890,10 @@ __device__ __forceinline__ void ut_body(const Coef<T>& c, int block, const S* __
                 if constexpr (BUF) {
                     const unsigned vx = xi * (unsigned)sizeof(S), sI = (unsigned)(I * np) * (unsigned)sizeof(S);
                     if constexpr (SU) buf_st(hv, rhout, vx, sI);
-                    buf_st(fv, rfout, vx, sI);
+                    if constexpr (ST) buf_st(fv, rfout, vx, sI);
                 } else {
                     if constexpr (SU) st_nt(&hout[(size_t)I * np + xi], hv);
-                    st_nt(&fout[(size_t)I * np + xi], fv);
+                    if constexpr (ST) st_nt(&fout[(size_t)I * np + xi], fv);
                 }
             });
         }
@@ -911,13 +914,14 @@ __global__ __launch_bounds__(TX * TY, (sizeof(T) == 4 ? 4 : 1)) void k_phi(
     phi_body<L, T, S, TX, TY, BUF>(c, blockIdx.x, gin, gout, phin, Un, thn, phout);
 }
 
-template <class L, class T, class S, int TX, int TY, bool BUF, bool ADV = false, bool SU = true>
+template <class L, class T, class S, int TX, int TY, bool BUF, bool ADV = false, bool SU = true,
+          bool ST = true>
 __global__ __launch_bounds__(TX * TY, (sizeof(T) == 4 ? 3 : 1)) void k_ut(
     const Coef<T> c, const S* __restrict__ hin, S* __restrict__ hout, const S* __restrict__ fin,
     S* __restrict__ fout, const T* __restrict__ phio, const T* __restrict__ phnew,
     const T* __restrict__ Un, const T* __restrict__ thn, T* __restrict__ Uout, T* __restrict__ thout) {
-    ut_body<L, T, S, TX, TY, BUF, ADV, SU>(c, blockIdx.x, hin, hout, fin, fout, phio, phnew, Un, thn, Uout,
-                                           thout);
+    ut_body<L, T, S, TX, TY, BUF, ADV, SU, ST>(c, blockIdx.x, hin, hout, fin, fout, phio, phnew, Un, thn,
+                                               Uout, thout);
 }
 
 template <class T>

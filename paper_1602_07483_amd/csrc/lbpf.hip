@@ -353,6 +353,10 @@ lbpf_status lbpf_create(const lbpf_grid* grid, const lbpf_params* params, void* 
     if (p.skip_U != 0 && p.skip_U != 1) return fail(nullptr, LBPF_EINVAL, "skip_U must be 0 or 1");
     if (p.skip_U && p.Mcinf != 0.0)
         return fail(nullptr, LBPF_EINVAL, "skip_U needs Mcinf = 0 (otherwise U acts on phi)");
+    if (p.skip_theta != 0 && p.skip_theta != 1) return fail(nullptr, LBPF_EINVAL, "skip_theta must be 0 or 1");
+    if (p.skip_theta && p.skip_U) return fail(nullptr, LBPF_EINVAL, "skip_U and skip_theta leave nothing to solve");
+    if (p.skip_theta && (p.vel[0] != 0.0 || p.vel[1] != 0.0 || p.vel[2] != 0.0))
+        return fail(nullptr, LBPF_EINVAL, "advection needs the heat equation (skip_theta = 0)");
 
     lbpf_ctx* ctx = new (std::nothrow) lbpf_ctx();
     if (!ctx) return fail(nullptr, LBPF_ENOMEM, "host allocation failed");
@@ -832,6 +836,8 @@ lbpf_status convert_field(lbpf_ctx* ctx, const void* in, int32_t in_f64, bool in
 lbpf_status lbpf_set_velocity_field(lbpf_ctx* ctx, const double* vx, const double* vy, const double* vz) {
     if (!ctx) return LBPF_EINVAL;
     if (ctx->in_batch) return fail(ctx, LBPF_ESTATE, "batched domains have no advective velocity");
+    if (ctx->prm.skip_theta && (vx || vy || vz))
+        return fail(ctx, LBPF_EINVAL, "advection needs the heat equation (skip_theta = 0)");
     const size_t n = ctx->n;
     if (!vx && !vy && !vz) {
         CHK(hipStreamSynchronize(ctx->stream));
@@ -1034,7 +1040,8 @@ lbpf_status lbpf_batch_create(int32_t n, const lbpf_grid* grids, const lbpf_para
             return bfail(nullptr, LBPF_EINVAL, "batched domains use D3Q15 or D3Q19");
         if (params[i].vel[0] != 0.0 || params[i].vel[1] != 0.0 || params[i].vel[2] != 0.0)
             return bfail(nullptr, LBPF_EINVAL, "batched domains have no advective velocity");
-        if (params[i].skip_U) return bfail(nullptr, LBPF_EINVAL, "batched domains solve U");
+        if (params[i].skip_U || params[i].skip_theta)
+            return bfail(nullptr, LBPF_EINVAL, "batched domains solve U and theta");
     }
     lbpf_batch* b = new (std::nothrow) lbpf_batch();
     if (!b) return bfail(nullptr, LBPF_ENOMEM, "host allocation failed");

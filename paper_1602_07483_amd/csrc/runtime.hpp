@@ -50,7 +50,7 @@ constexpr int kDefaultZslab[2][4] = {{6, 8, 8, 4}, {6, 8, 8, 4}};
 // 64x4 FP32 tile a block per CU.
 constexpr int kAdvShape[4] = {3, 3, 3, 2};
 const char* const kAdvTileMsg =
-    "advection and skip_U run k_ut on its advection tile only (32x8; FP64 32x4)";
+    "advection, skip_U and skip_theta run k_ut on its advection tile only (32x8; FP64 32x4)";
 
 }  // namespace lbpf_rt
 
@@ -169,9 +169,11 @@ inline int default_shape(const lbpf_ctx* ctx, int k) { return kDefaultShape[k][c
 
 inline int adv_shape(const lbpf_ctx* ctx) { return kAdvShape[ctx->storage]; }
 
-// k_ut needs one of its variants (advection, or theta alone), which exist on
-// the advection tile only.
-inline bool ut_pinned(const lbpf_ctx* ctx) { return has_advection(ctx) || ctx->prm.skip_U != 0; }
+// k_ut needs one of its variants (advection, theta alone or U alone), which
+// exist on the advection tile only.
+inline bool ut_pinned(const lbpf_ctx* ctx) {
+    return has_advection(ctx) || ctx->prm.skip_U != 0 || ctx->prm.skip_theta != 0;
+}
 
 inline int total_tiles(const lbpf_ctx* ctx, int k) {
     const Shape sh = kShapes[ctx->shape[k]];

@@ -28,11 +28,11 @@ lbpf_status launch_ut(lbpf_ctx* ctx) {
     const Coef<T> c = make_coef<T>(ctx, K_UT);
     const int nb = total_tiles(ctx, K_UT);
     const int a = ctx->cur, b = 1 - ctx->cur;
-    // the advection-diffusion and theta-only variants exist for one tile
+    // the advection-diffusion, theta-only and U-only variants exist for one tile
     constexpr int kAdv = kAdvShape[LBPF_STEP_STORAGE];
     constexpr bool kAdvTile = TX == kShapes[kAdv].tx && TY == kShapes[kAdv].ty;
-    const bool su = ctx->prm.skip_U == 0;
-    if ((c.has_adv || !su) && !kAdvTile) return fail(ctx, LBPF_EINVAL, kAdvTileMsg);
+    const bool su = ctx->prm.skip_U == 0, sth = ctx->prm.skip_theta == 0;
+    if ((c.has_adv || !su || !sth) && !kAdvTile) return fail(ctx, LBPF_EINVAL, kAdvTileMsg);
     return timed(ctx, K_UT, [&] {
         auto args = [&](auto kern) {
             hipLaunchKernelGGL(kern, dim3(nb), dim3(TX * TY), 0, ctx->stream, c, (const S*)ctx->pop[1][a],
@@ -41,11 +41,12 @@ lbpf_status launch_ut(lbpf_ctx* ctx) {
                                (const T*)ctx->fld[2][a], (T*)ctx->fld[1][b], (T*)ctx->fld[2][b]);
         };
         if constexpr (kAdvTile) {
-            if (c.has_adv && su) return args(k_ut<L, T, S, TX, TY, BUF, true, true>);
-            if (c.has_adv) return args(k_ut<L, T, S, TX, TY, BUF, true, false>);
-            if (!su) return args(k_ut<L, T, S, TX, TY, BUF, false, false>);
+            if (c.has_adv && su) return args(k_ut<L, T, S, TX, TY, BUF, true, true, true>);
+            if (c.has_adv) return args(k_ut<L, T, S, TX, TY, BUF, true, false, true>);
+            if (!su) return args(k_ut<L, T, S, TX, TY, BUF, false, false, true>);
+            if (!sth) return args(k_ut<L, T, S, TX, TY, BUF, false, true, false>);
         }
-        args(k_ut<L, T, S, TX, TY, BUF, false, true>);
+        args(k_ut<L, T, S, TX, TY, BUF, false, true, true>);
     });
 }
 

@@ -36,7 +36,8 @@ class lbpf_params(ctypes.Structure):
                 ("k", ctypes.c_double), ("D", ctypes.c_double), ("kappa", ctypes.c_double),
                 ("aniso", ctypes.c_int32), ("eps", ctypes.c_double), ("delta", ctypes.c_double),
                 ("reduce_every", ctypes.c_int32), ("centre", ctypes.c_double * 3),
-                ("vel", ctypes.c_double * 3), ("skip_U", ctypes.c_int32)]
+                ("vel", ctypes.c_double * 3), ("skip_U", ctypes.c_int32),
+                ("skip_theta", ctypes.c_int32)]
 
 
 class lbpf_reductions(ctypes.Structure):
@@ -152,7 +153,7 @@ def lbpf_bench_copy(dst_ptr, src_ptr, nbytes, stream_ptr=0):
 def make_structs(nx, ny, nz, lattice=19, walls=(0,) * 6, storage="f32", dx=1.0, dt=1.0,
                  W0=1.0, tau0=1.0, lam=3.2, Mcinf=1.0, k=0.15, D=2.0, kappa=20.0, aniso=0,
                  eps=0.05, delta=0.0, reduce_every=0, centre=(0.0, 0.0, 0.0),
-                 vel=(0.0, 0.0, 0.0), skip_U=0):
+                 vel=(0.0, 0.0, 0.0), skip_U=0, skip_theta=0):
     """(lbpf_grid, lbpf_params) filled from keyword arguments."""
     g = lbpf_grid()
     g.nx, g.ny, g.nz, g.lattice = int(nx), int(ny), int(nz), int(lattice)
@@ -168,6 +169,7 @@ def make_structs(nx, ny, nz, lattice=19, walls=(0,) * 6, storage="f32", dx=1.0, 
         p.centre[i] = float(centre[i])
         p.vel[i] = float(vel[i])
     p.skip_U = int(skip_U)
+    p.skip_theta = int(skip_theta)
     return g, p
 
 
@@ -190,11 +192,12 @@ class Solver:
     def __init__(self, nx, ny, nz, lattice=19, walls=(0,) * 6, storage="f32", dx=1.0, dt=1.0,
                  W0=1.0, tau0=1.0, lam=3.2, Mcinf=1.0, k=0.15, D=2.0, kappa=20.0, aniso=0,
                  eps=0.05, delta=0.0, reduce_every=0, centre=(0.0, 0.0, 0.0),
-                 vel=(0.0, 0.0, 0.0), skip_U=0, stream=0):
+                 vel=(0.0, 0.0, 0.0), skip_U=0, skip_theta=0, stream=0):
         self._lib = lib()
         self._owner = None
         g, p = make_structs(nx, ny, nz, lattice, walls, storage, dx, dt, W0, tau0, lam, Mcinf, k,
-                            D, kappa, aniso, eps, delta, reduce_every, centre, vel, skip_U)
+                            D, kappa, aniso, eps, delta, reduce_every, centre, vel, skip_U,
+                            skip_theta)
         self.grid, self.params = g, p
         self.shape = (int(nz), int(ny), int(nx))
         self.q = int(lattice)

@@ -84,5 +84,16 @@ def test_storage_bytes_and_invalid_arguments_without_gpu():
     grids = (lbpf.lbpf_grid * 1)(g)
     params = (lbpf.lbpf_params * 1)(p)
     assert L.lbpf_batch_create(1, grids, params, None, ctypes.byref(h)) == lbpf.LBPF_EINVAL
-    assert b"solve U" in L.lbpf_batch_last_error(None)
+    assert b"solve U and theta" in L.lbpf_batch_last_error(None)
+    assert not h.value
+    # skip_theta: 0 or 1, not with skip_U, not with an advective velocity
+    p.skip_U = 0
+    p.skip_theta = 2
+    assert L.lbpf_create(ctypes.byref(g), ctypes.byref(p), None, ctypes.byref(h)) == lbpf.LBPF_EINVAL
+    p.skip_theta, p.skip_U = 1, 1
+    assert L.lbpf_create(ctypes.byref(g), ctypes.byref(p), None, ctypes.byref(h)) == lbpf.LBPF_EINVAL
+    assert b"nothing to solve" in L.lbpf_last_error(None)
+    p.skip_U, p.vel[2] = 0, 0.5
+    assert L.lbpf_create(ctypes.byref(g), ctypes.byref(p), None, ctypes.byref(h)) == lbpf.LBPF_EINVAL
+    assert b"heat equation" in L.lbpf_last_error(None)
     assert not h.value

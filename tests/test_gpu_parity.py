@@ -315,3 +315,26 @@ def test_skip_U_matches_oracle(lattice, storage, tol, vel):
     assert max(ephi, eth) <= tol
     assert np.array_equal(gU, U0)
     assert s.launches()["k_ut"][:2] == ((32, 4) if storage == "f64" else (32, 8))
+
+
+# ------------------------------------------------------------- isothermal, U only
+@pytest.mark.parametrize("lattice,storage,tol", [(19, "f64", 1e-11), (15, "f64", 1e-11),
+                                                 (7, "f64", 1e-11), (19, "f32", 1e-5)])
+def test_skip_theta_matches_oracle(lattice, storage, tol):
+    """Isothermal alloy (theta held, as in the alloy benchmark of Sec. 4.2)
+    with skip_theta: phi and U against the oracle's isothermal mode, theta
+    left exactly as set."""
+    pb = dataclasses.replace(ragged_problem(lattice, 0), theta0=0.0)
+    s = lbpf.solver_for(pb, storage=storage, skip_theta=1)
+    s.set_fields(*pb.initial_fields())
+    th0 = s.read(reductions=False)[2]
+    o = Oracle(pb.nx, pb.ny, pb.nz, **dict(pb.model_kwargs(), skip_theta=1))
+    o.init(*pb.initial_fields())
+    s.step(60)
+    o.step(60)
+    gphi, gU, gth, _ = s.read(reductions=False)
+    ophi, oU, _ = o.fields()
+    ephi, eU = maxabs(gphi, ophi), maxabs(gU, oU)
+    print("%s q%d skip_theta: max|dphi| %.3e max|dU| %.3e" % (storage, lattice, ephi, eU))
+    assert max(ephi, eU) <= tol
+    assert np.array_equal(gth, th0)

@@ -44,6 +44,7 @@ class FdoParams(ctypes.Structure):
         ("lam", ctypes.c_double), ("Mcinf", ctypes.c_double), ("k", ctypes.c_double),
         ("D", ctypes.c_double), ("kappa", ctypes.c_double),
         ("aniso", ctypes.c_int32), ("eps", ctypes.c_double), ("delta", ctypes.c_double),
+        ("skip_theta", ctypes.c_int32),
     ]
 
 
@@ -230,12 +231,14 @@ class FDOracle:
     (mirror and no-flux walls coincide for this discretisation)."""
 
     def __init__(self, nx, ny, nz, dx=1.0, W0=1.0, tau0=1.0, lam=3.2, Mcinf=1.0, k=0.15,
-                 D=2.0, kappa=20.0, aniso=ANISO_CUBIC, eps=0.05, delta=0.0, **_ignored):
+                 D=2.0, kappa=20.0, aniso=ANISO_CUBIC, eps=0.05, delta=0.0, skip_theta=0,
+                 **_ignored):
         lib = _load()
         p = FdoParams()
         p.nx, p.ny, p.nz = int(nx), int(ny), int(nz)
         p.dx, p.W0, p.tau0, p.lam, p.Mcinf, p.k = dx, W0, tau0, lam, Mcinf, k
         p.D, p.kappa, p.aniso, p.eps, p.delta = D, kappa, int(aniso), eps, delta
+        p.skip_theta = int(skip_theta)
         self.shape = (int(nz), int(ny), int(nx))
         self._h = lib.fdo_create(ctypes.byref(p))
         if not self._h:

@@ -39,6 +39,7 @@ typedef struct {
     double dx, W0, tau0, lambda, Mcinf, k, D, kappa;
     int32_t aniso;          /* 0: cubic, 1: K41/K61 */
     double eps, delta;
+    int32_t skip_theta;     /* 1: isothermal (Sec. 4.2 benchmark): theta held */
 } fdo_params;
 
 typedef struct {
@@ -235,7 +236,7 @@ void fdo_step(fdo_ctx* c, double dt, int64_t nsteps) {
                         c->th[IDX(clampi(x + 1, nx), y, z)] + c->th[IDX(clampi(x - 1, nx), y, z)] +
                         c->th[IDX(x, clampi(y + 1, ny), z)] + c->th[IDX(x, clampi(y - 1, ny), z)] +
                         c->th[IDX(x, y, clampi(z + 1, nz))] + c->th[IDX(x, y, clampi(z - 1, nz))] - 6.0 * t0;
-                    c->thn[i] = t0 + dt * p->kappa * lap / (dx * dx) + 0.5 * dphi;
+                    c->thn[i] = p->skip_theta ? t0 : t0 + dt * p->kappa * lap / (dx * dx) + 0.5 * dphi;
                 }
         double* t;
         t = c->phi; c->phi = c->phin; c->phin = t;

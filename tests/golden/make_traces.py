@@ -13,6 +13,8 @@ fd2d, fd3d -- the LB oracle and the finite-difference discretisation of the
               same PDEs side by side (dx/W0 = 0.4, dt/tau0 = 0.02 for LB and
               0.01 for FD): a 200^2 quadrant slab over 4000 steps and a 64^3
               octant over 1500 steps; tip positions every 200 / 100 steps
+fd3d_iso   -- the same 64^3 octant as the paper's isothermal alloy benchmark
+              (theta = 0 and held in both), 1500 steps, tips every 50
 """
 import json
 import os
@@ -31,17 +33,19 @@ KEYS = (("solid_fraction", oracle.R_SOLID), ("solute_mass", oracle.R_MASS),
         ("enthalpy", oracle.R_ENTHALPY), ("phi_min", oracle.R_PHIMIN),
         ("phi_max", oracle.R_PHIMAX), ("nonfinite", oracle.R_NONFINITE))
 
-def fd_problem(n, nz):
+def fd_problem(n, nz, iso=False):
     """Alloy + heat dendrite at the resolution of the paper's alloy benchmark
     (Sec. 4.2: dx/W0 = 0.4, dt/tau0 = 0.02, D = 2, k = 0.15, eps = 0.03,
     lambda = 3.2, U0 = -0.55), with theta0 = -0.55 and kappa = D; seed of
-    radius 10 dx at the mirror corner."""
+    radius 10 dx at the mirror corner.  iso: the benchmark itself, isothermal
+    (theta = 0 and held, skip_theta in both discretisations)."""
     walls = (inputs.SYMMETRY, inputs.NOFLUX, inputs.SYMMETRY, inputs.NOFLUX,
              inputs.SYMMETRY, inputs.SYMMETRY if nz == 1 else inputs.NOFLUX)
     cz = 0.0 if nz == 1 else -0.5
-    return inputs.Problem("fd-%dx%d" % (n, nz), n, n, nz, 19, walls, dx=0.4, dt=0.02, W0=1.0,
-                          tau0=1.0, lam=3.2, Mcinf=1.0, k=0.15, D=2.0, kappa=2.0, eps=0.03,
-                          centres=[(-0.5, -0.5, cz)], radius=10.0, U0=-0.55, theta0=-0.55)
+    return inputs.Problem("fd-%dx%d%s" % (n, nz, "-iso" if iso else ""), n, n, nz, 19, walls, dx=0.4,
+                          dt=0.02, W0=1.0, tau0=1.0, lam=3.2, Mcinf=1.0, k=0.15, D=2.0, kappa=2.0,
+                          eps=0.03, centres=[(-0.5, -0.5, cz)], radius=10.0, U0=-0.55,
+                          theta0=0.0 if iso else -0.55)
 
 
 def tip_along_x(phi, cx):
@@ -56,13 +60,13 @@ def tip_along_x(phi, cx):
     return float(xs.max()) - cx
 
 
-def fd_trace(pb, steps, every, log=print):
+def fd_trace(pb, steps, every, log=print, skip_theta=0):
     """Tip positions of the LB oracle and of the FD discretisation (two FD
     steps of dt/2 per LB step) from the same initial fields."""
     f0 = pb.initial_fields()
-    o = oracle.Oracle(pb.nx, pb.ny, pb.nz, **pb.model_kwargs())
+    o = oracle.Oracle(pb.nx, pb.ny, pb.nz, skip_theta=skip_theta, **pb.model_kwargs())
     o.init(*f0)
-    fd = oracle.FDOracle(pb.nx, pb.ny, pb.nz, **pb.model_kwargs())
+    fd = oracle.FDOracle(pb.nx, pb.ny, pb.nz, skip_theta=skip_theta, **pb.model_kwargs())
     fd.set(*f0)
     out = []
     t0 = time.time()
@@ -84,8 +88,9 @@ def fd_trace(pb, steps, every, log=print):
     return out
 
 
-FD_CASES = {"fd2d": (lambda: fd_problem(200, 1), 4000, 200),
-            "fd3d": (lambda: fd_problem(64, 64), 1500, 100)}
+FD_CASES = {"fd2d": (lambda: fd_problem(200, 1), 4000, 200, 0),
+            "fd3d": (lambda: fd_problem(64, 64), 1500, 100, 0),
+            "fd3d_iso": (lambda: fd_problem(64, 64, iso=True), 1500, 50, 1)}
 
 WORKLOADS = {
     "thermal2d": lambda: inputs.workload_thermal2d(),
@@ -118,11 +123,12 @@ def trace(pb, log=print):
 def main(names):
     for name in names or list(WORKLOADS) + list(FD_CASES):
         if name in FD_CASES:
-            factory, steps, every = FD_CASES[name]
+            factory, steps, every, skip_theta = FD_CASES[name]
             pb = factory()
             rec = {"workload": pb.name, "problem": {k: v for k, v in pb.__dict__.items()},
-                   "lb_dt": pb.dt, "fd_dt": pb.dt / 2.0, "every": every,
-                   "oracle_threads": oracle.num_threads(), "trace": fd_trace(pb, steps, every)}
+                   "lb_dt": pb.dt, "fd_dt": pb.dt / 2.0, "every": every, "skip_theta": skip_theta,
+                   "oracle_threads": oracle.num_threads(),
+                   "trace": fd_trace(pb, steps, every, skip_theta=skip_theta)}
             path = os.path.join(HERE, "trace_%s.json" % name)
             with open(path, "w") as fh:
                 json.dump(rec, fh, indent=0)

@@ -336,3 +336,53 @@ def test_preferred_growth_direction_sec_4_3(aniso, eps, delta, steps):
         assert r100 > 1.1 * r110 and r100 > 1.1 * r111
     else:
         assert r110 > 1.1 * r100 and r110 > 1.1 * r111
+
+
+def _tip_along_x(phi, cx):
+    """Largest phi = 0 crossing along +x over all rows (linear interpolation),
+    minus cx: the tip measure of the stored LB-versus-FD traces."""
+    a, b = phi[..., :-1], phi[..., 1:]
+    m = (a > 0) & (b <= 0)
+    if not m.any():
+        return float("nan")
+    x = np.arange(phi.shape[-1] - 1, dtype=np.float64)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        xs = np.where(m, x + a / np.where(m, a - b, 1.0), -np.inf)
+    return float(xs.max()) - cx
+
+
+@pytest.mark.parametrize("storage,tol", [("f32", 0.02), ("f16", 0.2)])
+def test_isothermal_alloy_benchmark_matches_oracle(storage, tol):
+    """The paper's isothermal alloy benchmark (Sec. 4.2: dx/W0 = 0.4,
+    dt/tau0 = 0.02, U0 = -0.55, D = 2, k = 0.15, eps = 0.03, lambda = 3.2,
+    R_s = 10, theta = 0) in a 64^3 octant with skip_theta: the tip position
+    every 50 steps against the FP64 oracle's isothermal run stored in
+    tests/golden/trace_fd3d_iso.json (tol nodes), and the free-growth tip
+    velocity within 1 %."""
+    from paper_1602_07483_amd.inputs import Problem
+    g = golden("fd3d_iso")
+    p = dict(g["problem"])
+    pb = Problem(**{k: (tuple(v) if isinstance(v, list) and k == "walls" else v) for k, v in p.items()})
+    pb.centres = [tuple(c) for c in pb.centres]
+    s = make_gpu(pb, storage, skip_theta=1)
+    cx = pb.centres[0][0]
+    gpu, ref, steps = [], [], []
+    done = 0
+    for rec in g["trace"]:
+        s.step(rec["step"] - done)
+        done = rec["step"]
+        phi = s.read(reductions=False)[0]
+        gpu.append(_tip_along_x(phi, cx))
+        ref.append(rec["lb_tip"])
+        steps.append(done)
+    s.close()
+    gpu, ref, steps = np.array(gpu), np.array(ref), np.array(steps, dtype=float)
+    gap = np.max(np.abs(gpu - ref))
+    free = np.nonzero(ref < 0.7 * pb.nx)[0]
+    sel = np.arange(len(ref) // 4, free[-1] + 1)
+    vg = np.polyfit(steps[sel], gpu[sel], 1)[0]
+    vr = np.polyfit(steps[sel], ref[sel], 1)[0]
+    print("isothermal benchmark %s: max tip gap %.4f nodes, velocity GPU %.5f oracle %.5f (%.3f %%)"
+          % (storage, gap, vg, vr, 100 * (vg / vr - 1)))
+    assert gap <= tol
+    assert abs(vg / vr - 1) < 0.01

@@ -75,7 +75,7 @@ def test_trace_start_reproduces(name, factory, steps):
     assert abs(r[oracle.R_ENTHALPY] - rec["enthalpy"]) < 1e-9 * max(1.0, abs(rec["enthalpy"]))
 
 
-@pytest.mark.parametrize("name", ["fd2d", "fd3d"])
+@pytest.mark.parametrize("name", ["fd2d", "fd3d", "fd3d_iso"])
 def test_lb_oracle_matches_finite_differences(name):
     """The LB oracle against the independent finite-difference discretisation
     of the same PDEs (oracle/fd_oracle.c), as the paper compares its LB

@@ -144,6 +144,11 @@ typedef struct {
     double phi_min, phi_max;
     double nonfinite;         /* count of non-finite phi, U, theta values */
     double sum_U, sum_phi;    /* sums of U and phi, times dx^3 */
+    double tip_vel[3];        /* tip velocity along +x,+y,+z since the previous
+                                 record of the history: (tip - tip_prev) dx /
+                                 ((step - step_prev) dt), physical units (times
+                                 tau0/W0 it is the dimensionless V_p of Sec.
+                                 4.1).  NaN without an earlier record. */
 } lbpf_reductions;
 
 /* Create a context: validates the parameters, allocates the populations

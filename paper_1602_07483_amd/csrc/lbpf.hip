@@ -245,6 +245,14 @@ void unpack_record(const double* r, lbpf_reductions* out) {
     out->nonfinite = r[9];
     out->sum_U = r[10];
     out->sum_phi = r[11];
+    for (int a = 0; a < 3; ++a) out->tip_vel[a] = std::nan("");
+}
+
+// Tip velocity of cur from the record prev made before it (physical units).
+void set_tip_vel(lbpf_reductions* cur, const lbpf_reductions& prev, const lbpf_params& p) {
+    if (cur->step <= prev.step) return;
+    const double s = p.dx / ((double)(cur->step - prev.step) * p.dt);
+    for (int a = 0; a < 3; ++a) cur->tip_vel[a] = (cur->tip[a] - prev.tip[a]) * s;
 }
 
 bool healthy(const lbpf_reductions& r) {
@@ -575,6 +583,18 @@ lbpf_status lbpf_read(lbpf_ctx* ctx, double* phi, double* U, double* theta, lbpf
         CHK(hipMemcpyAsync(r, ctx->fresh, sizeof(r), hipMemcpyDeviceToHost, ctx->stream));
         CHK(hipStreamSynchronize(ctx->stream));
         unpack_record(r, red);
+        // tip velocity against the latest history record made before this step
+        for (int64_t back = 1; back <= 2 && back <= ctx->hist_count && back <= HIST_CAP; ++back) {
+            double h[RED_STRIDE];
+            CHK(hipMemcpy(h, ctx->hist + (size_t)((ctx->hist_count - back) % HIST_CAP) * RED_STRIDE, sizeof(h),
+                          hipMemcpyDeviceToHost));
+            lbpf_reductions prev;
+            unpack_record(h, &prev);
+            if (prev.step < red->step) {
+                set_tip_vel(red, prev, ctx->prm);
+                break;
+            }
+        }
         if (!healthy(*red))
             return fail(ctx, LBPF_EUNSTABLE, "health check failed at step " + std::to_string(red->step));
     }
@@ -592,6 +612,7 @@ lbpf_status lbpf_history(lbpf_ctx* ctx, lbpf_reductions* out, int32_t max_record
     for (int64_t i = 0; i < m; ++i) {
         const int64_t k = (first + i) % HIST_CAP;
         unpack_record(&buf[(size_t)k * RED_STRIDE], &out[i]);
+        if (i > 0) set_tip_vel(&out[i], out[i - 1], ctx->prm);
     }
     *count = (int32_t)m;
     return LBPF_OK;

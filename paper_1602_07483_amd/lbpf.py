@@ -45,13 +45,15 @@ class lbpf_reductions(ctypes.Structure):
                 ("solute_mass", ctypes.c_double), ("enthalpy", ctypes.c_double),
                 ("tip", ctypes.c_double * 3), ("phi_min", ctypes.c_double),
                 ("phi_max", ctypes.c_double), ("nonfinite", ctypes.c_double),
-                ("sum_U", ctypes.c_double), ("sum_phi", ctypes.c_double)]
+                ("sum_U", ctypes.c_double), ("sum_phi", ctypes.c_double),
+                ("tip_vel", ctypes.c_double * 3)]
 
     def as_dict(self):
         return {"step": self.step, "solid_fraction": self.solid_fraction,
                 "solute_mass": self.solute_mass, "enthalpy": self.enthalpy,
                 "tip": tuple(self.tip), "phi_min": self.phi_min, "phi_max": self.phi_max,
-                "nonfinite": self.nonfinite, "sum_U": self.sum_U, "sum_phi": self.sum_phi}
+                "nonfinite": self.nonfinite, "sum_U": self.sum_U, "sum_phi": self.sum_phi,
+                "tip_vel": tuple(self.tip_vel)}
 
 
 # Exported symbols, in header order (a CPU test checks each one is exported).

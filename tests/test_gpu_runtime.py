@@ -208,6 +208,16 @@ def test_reductions_and_tip_velocity_match_oracle():
     rel = np.abs(vg[ok] - vo[ok]) / np.abs(vo[ok])
     print("tip velocity rel. error FP32:", rel.max())
     assert rel.max() < 0.01
+    # the library's own tip velocity: the same difference in physical units
+    assert all(np.isnan(hist[0]["tip_vel"]))
+    for h0, h1 in zip(hist[:-1], hist[1:]):
+        for a in range(3):
+            expect = (h1["tip"][a] - h0["tip"][a]) * pb.dx / ((h1["step"] - h0["step"]) * pb.dt)
+            assert h1["tip_vel"][a] == pytest.approx(expect, rel=1e-12, abs=1e-15)
+    s.step(25)                                   # lbpf_read: against the last record (step 400)
+    red = s.read()[3]
+    assert red["tip_vel"][0] == pytest.approx((red["tip"][0] - hist[-1]["tip"][0]) * pb.dx / (25 * pb.dt),
+                                              rel=1e-12, abs=1e-15)
 
 
 @pytest.mark.parametrize("storage,bound", [("f16", 0.02), ("bf16", 0.1)])

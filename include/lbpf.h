@@ -319,7 +319,7 @@ lbpf_status lbpf_bench_copy(void* dst, const void* src, int64_t nbytes, void* hi
 const char* lbpf_last_error(const lbpf_ctx* ctx);
 
 /* ---- Ensembles of independent domains ------------------------------------
- * A batch holds n domains (own grid, lattice D3Q15 or D3Q19, parameters;
+ * A batch holds n domains (own grid, lattice D3Q7, D3Q15 or D3Q19, parameters;
  * one storage type for all) on one stream.  Each domain is an lbpf_ctx
  * reached with lbpf_batch_domain, through which its fields are set and read
  * with the calls above (lbpf_step on it is refused: ESTATE).  lbpf_batch_step

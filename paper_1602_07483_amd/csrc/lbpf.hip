@@ -101,8 +101,8 @@ struct lbpf_batch {
     int storage = LBPF_F32;
     int shape = 3, zslab = 6;
     void* d_desc = nullptr;        // DomainDesc<T>[ndom]
-    int2* d_work[2] = {};          // work tables of the D3Q15 and D3Q19 domains
-    int nwork[2] = {0, 0};
+    int2* d_work[3] = {};          // work tables of the D3Q7, D3Q15 and D3Q19 domains
+    int nwork[3] = {0, 0, 0};
     bool built = false;
     int graph_steps = 0;
     hipGraphExec_t gexec = nullptr;
@@ -964,7 +964,7 @@ template <class T>
 lbpf_status batch_build_t(lbpf_batch* b) {
     const int nd = (int)b->dom.size();
     std::vector<DomainDesc<T>> desc(nd);
-    std::vector<std::vector<int2>> items(2);
+    std::vector<std::vector<int2>> items(3);
     for (int d = 0; d < nd; ++d) {
         lbpf_ctx* c = b->dom[d];
         for (int k = 0; k < 2; ++k) {   // one tiling for both batch kernels
@@ -978,13 +978,13 @@ lbpf_status batch_build_t(lbpf_batch* b) {
                 desc[d].pop[f][par] = c->pop[f][par];
                 desc[d].fld[f][par] = (T*)c->fld[f][par];
             }
-        const int li = c->q == 15 ? 0 : 1;
+        const int li = c->q == 7 ? 0 : c->q == 15 ? 1 : 2;
         const int nt = total_tiles(c, K_PHI);
         for (int t = 0; t < nt; ++t) items[li].push_back(int2{d, t});
     }
     if (!b->d_desc) BCHK(hipMalloc(&b->d_desc, sizeof(DomainDesc<T>) * nd));
     BCHK(hipMemcpy(b->d_desc, desc.data(), sizeof(DomainDesc<T>) * nd, hipMemcpyHostToDevice));
-    for (int li = 0; li < 2; ++li) {
+    for (int li = 0; li < 3; ++li) {
         std::vector<int2>& it = items[li];
         if (b->d_work[li]) { (void)hipFree(b->d_work[li]); b->d_work[li] = nullptr; }
         b->nwork[li] = 0;
@@ -1023,10 +1023,12 @@ lbpf_status batch_launch_u(lbpf_batch* b, int li, int par) {
 // One time step of every domain: phase field of all domains, then U/theta.
 template <class T, class S, int TX, int TY>
 lbpf_status batch_step_t(lbpf_batch* b, int par) {
-    lbpf_status st = batch_launch_l<D3Q15, T, S, TX, TY>(b, 0, par);
-    if (!st) st = batch_launch_l<D3Q19, T, S, TX, TY>(b, 1, par);
-    if (!st) st = batch_launch_u<D3Q15, T, S, TX, TY>(b, 0, par);
-    if (!st) st = batch_launch_u<D3Q19, T, S, TX, TY>(b, 1, par);
+    lbpf_status st = batch_launch_l<D3Q7, T, S, TX, TY>(b, 0, par);
+    if (!st) st = batch_launch_l<D3Q15, T, S, TX, TY>(b, 1, par);
+    if (!st) st = batch_launch_l<D3Q19, T, S, TX, TY>(b, 2, par);
+    if (!st) st = batch_launch_u<D3Q7, T, S, TX, TY>(b, 0, par);
+    if (!st) st = batch_launch_u<D3Q15, T, S, TX, TY>(b, 1, par);
+    if (!st) st = batch_launch_u<D3Q19, T, S, TX, TY>(b, 2, par);
     return st;
 }
 
@@ -1057,8 +1059,8 @@ lbpf_status lbpf_batch_create(int32_t n, const lbpf_grid* grids, const lbpf_para
         if (grids[i].storage != grids[0].storage)
             return bfail(nullptr, LBPF_EINVAL, "all domains of a batch share one storage type");
     for (int i = 0; i < n; ++i) {
-        if (grids[i].lattice != LBPF_D3Q15 && grids[i].lattice != LBPF_D3Q19)
-            return bfail(nullptr, LBPF_EINVAL, "batched domains use D3Q15 or D3Q19");
+        if (grids[i].lattice != LBPF_D3Q7 && grids[i].lattice != LBPF_D3Q15 && grids[i].lattice != LBPF_D3Q19)
+            return bfail(nullptr, LBPF_EINVAL, "batched domains use D3Q7, D3Q15 or D3Q19");
         if (params[i].vel[0] != 0.0 || params[i].vel[1] != 0.0 || params[i].vel[2] != 0.0)
             return bfail(nullptr, LBPF_EINVAL, "batched domains have no advective velocity");
         if (params[i].skip_U || params[i].skip_theta)
@@ -1175,7 +1177,7 @@ lbpf_status lbpf_batch_destroy(lbpf_batch* b) {
     (void)hipStreamSynchronize(b->stream);
     if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
     if (b->d_desc) (void)hipFree(b->d_desc);
-    for (int li = 0; li < 2; ++li)
+    for (int li = 0; li < 3; ++li)
         if (b->d_work[li]) (void)hipFree(b->d_work[li]);
     for (lbpf_ctx* c : b->dom) {
         c->in_batch = false;

@@ -55,12 +55,12 @@ def test_storage_bytes_and_invalid_arguments_without_gpu():
     assert not h.value
     assert L.lbpf_bench_copy(None, None, 16, None) == lbpf.LBPF_EINVAL
     assert L.lbpf_destroy(None) == lbpf.LBPF_OK
-    # batches hold D3Q15/D3Q19 domains only; checked before any device call
-    g.nx, g.lattice = 8, 7
+    # batched domains take the single-domain lattices; checked before any device call
+    g.nx, g.lattice = 8, 17
     grids = (lbpf.lbpf_grid * 1)(g)
     params = (lbpf.lbpf_params * 1)(p)
     assert L.lbpf_batch_create(1, grids, params, None, ctypes.byref(h)) == lbpf.LBPF_EINVAL
-    assert b"D3Q15 or D3Q19" in L.lbpf_batch_last_error(None)
+    assert b"D3Q7, D3Q15 or D3Q19" in L.lbpf_batch_last_error(None)
     # an imposed velocity must be finite, and batches carry none
     g.lattice = 19
     p.vel[0] = float("nan")

@@ -1,6 +1,8 @@
 """GPU runtime features through the C ABI: launch shapes, graph replay,
 batched ensembles, checkpoint/restore, health checks and the FP64 reductions
 against the oracle."""
+import dataclasses
+
 import numpy as np
 import pytest
 
@@ -79,12 +81,13 @@ def _batch_problems():
             ragged(19, (40, 35, 24), eps=0.06, U0=-0.6, seed=12),
             ragged(15, (64, 8, 9), eps=0.02, U0=-0.45, seed=13, walls=(NOFLUX,) * 6),
             ragged(19, (17, 40, 33), aniso=1, eps=0.0, delta=-0.02, seed=14),
-            ragged(19, (29, 29, 29), eps=0.07, U0=-0.65, seed=15, walls=(SYMMETRY,) * 6)]
+            ragged(19, (29, 29, 29), eps=0.07, U0=-0.65, seed=15, walls=(SYMMETRY,) * 6),
+            dataclasses.replace(ragged(7, (37, 21, 19), eps=0.04, U0=-0.5, seed=16), dt=0.11)]
 
 
 @pytest.mark.parametrize("graph_steps", [0, 6])
 def test_batch_matches_domains_stepped_alone(graph_steps):
-    """Each domain of a mixed D3Q15/D3Q19 batch against the same domain
+    """Each domain of a mixed D3Q7/D3Q15/D3Q19 batch against the same domain
     stepped alone.  The batch kernels are compiled separately (coefficients
     come from a descriptor), so contraction into FMAs may differ: after 25
     steps the fields agree to a few ulp of values of order one."""
@@ -125,7 +128,7 @@ def test_batch_graph_and_chunking_are_bit_exact():
 
 
 def test_batch_fp64_matches_oracle():
-    probs = _batch_problems()[:3]
+    probs = _batch_problems()[:3] + _batch_problems()[5:]   # D3Q15, D3Q19, D3Q7
     b = lbpf.Batch([lbpf.problem_kwargs(p) for p in probs], storage="f64")
     for d, p in zip(b.domains, probs):
         d.set_fields(*p.initial_fields())

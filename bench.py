@@ -112,6 +112,38 @@ def run_gpu(storage, steps, warmup, n, launch=None):
                         "mlups_with_host_io": lups / (wall + t_in + t_out) / 1e6}}
 
 
+def run_single_field(steps, warmup, n, storage="f32"):
+    """The same 256^3 seed with one transport field: a pure substance
+    (M c_inf = 0, skip_U: theta alone) and an isothermal alloy (theta held,
+    skip_theta: U alone), as in the paper's thermal and alloy benchmarks."""
+    import dataclasses
+    import torch
+    from paper_1602_07483_amd import lbpf
+    from paper_1602_07483_amd.inputs import workload_centred
+
+    out = {"storage": storage, "steps": steps}
+    base = workload_centred(n=n)
+    base.reduce_every = 0
+    stream = torch.cuda.current_stream().cuda_stream
+    for name, pb, kw in (("skip_U (pure substance, Mcinf = 0)", dataclasses.replace(base, Mcinf=0.0),
+                          {"skip_U": 1}),
+                         ("skip_theta (isothermal, theta = 0)", dataclasses.replace(base, theta0=0.0),
+                          {"skip_theta": 1})):
+        s = lbpf.solver_for(pb, storage=storage, stream=stream, **kw)
+        s.set_fields(*pb.initial_fields())
+        s.step(warmup)
+        s.sync()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s.step(steps)
+        s.sync()
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        s.close()
+        out[name] = {"mlups": float(n) ** 3 * steps / wall / 1e6}
+    return out
+
+
 def run_ensemble(steps, seq_steps, storage="f16", graph_steps=50):
     """Batched ensemble of 64 uneven domains (mixed D3Q15/D3Q19, per-domain
     eps, Delta and noise seed) replayed from a HIP graph, against the same
@@ -272,6 +304,9 @@ def main():
                             "speedup_vs_f32": r["mlups"] / res["mlups"],
                             "kernels": r["kernels"]}
     copy_gbs = copy_bandwidth()
+    single_field = None
+    if not args.no_variants:
+        single_field = run_single_field(max(args.steps // 3, 1), args.warmup, args.n)
     multiseed = None
     if not args.no_multiseed:
         multiseed = run_multiseed(args.multiseed_steps)
@@ -306,6 +341,7 @@ def main():
         "variants": variants,
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "single_field": single_field,
         "ensemble": ensemble,
         "multiseed": multiseed,
         "health": {"solid_fraction": res["solid_fraction"], "phi_range": res["phi_range"]},

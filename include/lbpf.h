@@ -153,9 +153,13 @@ typedef struct {
 
 /* Create a context: validates the parameters, allocates the populations
  * (two lattices per field), the fields and the reduction buffers on the
- * current device.  Errors: EINVAL (n < 1, unsupported lattice or storage,
- * k not in (0,1), dx, dt, W0, tau0 <= 0, D or kappa < 0, eps outside
- * [0, 0.25]), ENOMEM, EDEVICE.  *out is NULL on error. */
+ * current device.  Device arrays have their rows padded to a multiple of 32
+ * values; that layout stays inside the library (every copy in or out uses
+ * the packed [nz][ny][nx] layout).  Errors: EINVAL (n < 1, unsupported
+ * lattice, storage, wall or anisotropy, k not in (0,1), dx, dt, W0,
+ * tau0 <= 0, D or kappa < 0, eps outside [0, 0.25], reduce_every < 0,
+ * non-finite vel, skip_U or skip_theta not 0/1 or in a refused combination),
+ * ENOMEM, EDEVICE.  *out is NULL on error. */
 lbpf_status lbpf_create(const lbpf_grid* grid, const lbpf_params* params,
                         void* hip_stream, lbpf_ctx** out);
 
@@ -255,8 +259,8 @@ lbpf_status lbpf_debug_stream_only(lbpf_ctx* ctx, int64_t nsteps);
  * start there).  Puts k_ut on its advection tile (32x8; FP64 32x4), the
  * only one with the advective variant, and drops a captured step graph.
  * Removing the field leaves k_ut's launch as it is.  Synchronises.
- * Errors: EINVAL (one or two NULL, non-finite value), ESTATE (a batch
- * member), ENOMEM. */
+ * Errors: EINVAL (one or two NULL, non-finite value, skip_theta set),
+ * ESTATE (a batch member), ENOMEM. */
 lbpf_status lbpf_set_velocity_field(lbpf_ctx* ctx, const double* vx, const double* vy, const double* vz);
 
 /* Per-kernel timing with HIP events recorded on the context stream around

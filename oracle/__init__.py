@@ -34,6 +34,7 @@ class OrcParams(ctypes.Structure):
         ("aniso", ctypes.c_int32), ("eps", ctypes.c_double), ("delta", ctypes.c_double),
         ("vel", ctypes.c_double * 3),
         ("skip_theta", ctypes.c_int32),
+        ("lattice_ut", ctypes.c_int32),
     ]
 
 
@@ -148,7 +149,8 @@ class Oracle:
 
     def __init__(self, nx, ny, nz, lattice=19, walls=(0,) * 6, dx=1.0, dt=1.0,
                  W0=1.0, tau0=1.0, lam=3.2, Mcinf=1.0, k=0.15, D=2.0, kappa=20.0,
-                 aniso=ANISO_CUBIC, eps=0.05, delta=0.0, vel=(0.0, 0.0, 0.0), skip_theta=0):
+                 aniso=ANISO_CUBIC, eps=0.05, delta=0.0, vel=(0.0, 0.0, 0.0), skip_theta=0,
+                 lattice_ut=0):
         lib = _load()
         p = OrcParams()
         p.nx, p.ny, p.nz = int(nx), int(ny), int(nz)
@@ -161,9 +163,11 @@ class Oracle:
         for a in range(3):
             p.vel[a] = float(vel[a])
         p.skip_theta = int(skip_theta)
+        p.lattice_ut = int(lattice_ut)
         self.params = p
         self.shape = (int(nz), int(ny), int(nx))
         self.q = int(lattice)
+        self.q_ut = int(lattice_ut) or self.q
         self._h = lib.orc_create(ctypes.byref(p))
         if not self._h:
             raise ValueError("oracle rejected the parameters")
@@ -211,12 +215,12 @@ class Oracle:
         return out
 
     def pops(self, field):
-        out = np.zeros((self.q,) + self.shape)
+        out = np.zeros((self.q if field == 0 else self.q_ut,) + self.shape)
         self._lib.orc_get_pops(self._h, int(field), _dptr(out))
         return out
 
     def set_pops(self, field, arr):
-        a = _f64(arr).reshape((self.q,) + self.shape)
+        a = _f64(arr).reshape((self.q if field == 0 else self.q_ut,) + self.shape)
         self._lib.orc_set_pops(self._h, int(field), _dptr(a))
 
     def reduce(self, centre=(0.0, 0.0, 0.0)):

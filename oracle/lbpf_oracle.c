@@ -45,6 +45,10 @@
  *  R21 Isothermal runs (the alloy benchmark of Sec. 4.2 sets theta = 0):
  *      with skip_theta the heat equation is not solved and theta keeps its
  *      initial value everywhere.
+ *  R22 Separate lattices (lattice_ut): the U and theta schemes may run on
+ *      another lattice than the phase field, as the 2D validation of Sec.
+ *      4.1 uses D2Q9 for phi and D2Q5 for theta; each scheme takes the e^2,
+ *      weights and A_i, B_i of its own lattice.
  */
 #include "lbpf_oracle.h"
 
@@ -58,13 +62,19 @@
 #define MAXQ 19
 #define SMIN 1e-12
 
-struct orc_ctx {
-    orc_params p;
+/* One lattice: vectors, weights, A_i, B_i, e^2, opposite and reflected links. */
+typedef struct {
     int q;
     int e[MAXQ][3];
     double w[MAXQ], A[MAXQ], B[MAXQ], e2;
     int opp[MAXQ];
     int refl[8][MAXQ];   /* refl[mask][i]: e_i with the components in mask flipped */
+} orc_lat;
+
+struct orc_ctx {
+    orc_params p;
+    orc_lat lg;          /* lattice of g (phase field) */
+    orc_lat lt;          /* lattice of h and f (U, theta): lg unless lattice_ut is set */
     size_t n;
     double *pop[3];      /* g, h, f: post-streaming populations */
     double *star[3];     /* post-collision populations */
@@ -120,12 +130,32 @@ int orc_lattice(int q, int32_t* e, double* w, double* A, double* B, double* e2)
 }
 
 /* Index of the direction whose vector equals (x,y,z); -1 if none. */
-static int find_dir(const orc_ctx* c, int x, int y, int z)
+static int find_dir(const orc_lat* L, int x, int y, int z)
 {
     int i;
-    for (i = 0; i < c->q; ++i)
-        if (c->e[i][0] == x && c->e[i][1] == y && c->e[i][2] == z) return i;
+    for (i = 0; i < L->q; ++i)
+        if (L->e[i][0] == x && L->e[i][1] == y && L->e[i][2] == z) return i;
     return -1;
+}
+
+/* The lattice table of q (7, 15 or 19) with its opposite and reflected links. */
+static void lat_init(orc_lat* L, int q)
+{
+    int32_t e[3*MAXQ];
+    int i, mask;
+    L->q = q;
+    orc_lattice(q, e, L->w, L->A, L->B, &L->e2);
+    for (i = 0; i < q; ++i) {
+        L->e[i][0] = e[3*i]; L->e[i][1] = e[3*i+1]; L->e[i][2] = e[3*i+2];
+    }
+    for (i = 0; i < q; ++i) {
+        L->opp[i] = find_dir(L, -L->e[i][0], -L->e[i][1], -L->e[i][2]);
+        for (mask = 0; mask < 8; ++mask)
+            L->refl[mask][i] = find_dir(L,
+                (mask & 1) ? -L->e[i][0] : L->e[i][0],
+                (mask & 2) ? -L->e[i][1] : L->e[i][1],
+                (mask & 4) ? -L->e[i][2] : L->e[i][2]);
+    }
 }
 
 /* ------------------------------------------------------------------------- */
@@ -266,32 +296,23 @@ void orc_destroy(orc_ctx* c)
 orc_ctx* orc_create(const orc_params* p)
 {
     orc_ctx* c;
-    int32_t e[3*MAXQ];
-    int i, k, mask;
+    int i, k;
     if (!p || p->nx < 1 || p->ny < 1 || p->nz < 1) return NULL;
     if (p->lattice != 7 && p->lattice != 15 && p->lattice != 19) return NULL;
+    if (p->lattice_ut != 0 && p->lattice_ut != 7 && p->lattice_ut != 15 && p->lattice_ut != 19)
+        return NULL;
     if (!(p->dx > 0) || !(p->dt > 0) || !(p->tau0 > 0) || !(p->W0 > 0)) return NULL;
     if (!(p->k > 0 && p->k < 1)) return NULL;
     c = (orc_ctx*)calloc(1, sizeof(orc_ctx));
     if (!c) return NULL;
     c->p = *p;
-    c->q = p->lattice;
-    orc_lattice(c->q, e, c->w, c->A, c->B, &c->e2);
-    for (i = 0; i < c->q; ++i) {
-        c->e[i][0] = e[3*i]; c->e[i][1] = e[3*i+1]; c->e[i][2] = e[3*i+2];
-    }
-    for (i = 0; i < c->q; ++i) {
-        c->opp[i] = find_dir(c, -c->e[i][0], -c->e[i][1], -c->e[i][2]);
-        for (mask = 0; mask < 8; ++mask)
-            c->refl[mask][i] = find_dir(c,
-                (mask & 1) ? -c->e[i][0] : c->e[i][0],
-                (mask & 2) ? -c->e[i][1] : c->e[i][1],
-                (mask & 4) ? -c->e[i][2] : c->e[i][2]);
-    }
+    lat_init(&c->lg, p->lattice);
+    lat_init(&c->lt, p->lattice_ut ? p->lattice_ut : p->lattice);
     c->n = (size_t)p->nx * (size_t)p->ny * (size_t)p->nz;
     for (k = 0; k < 3; ++k) {
-        c->pop[k]  = (double*)calloc((size_t)c->q * c->n, sizeof(double));
-        c->star[k] = (double*)calloc((size_t)c->q * c->n, sizeof(double));
+        const int qk = k == 0 ? c->lg.q : c->lt.q;
+        c->pop[k]  = (double*)calloc((size_t)qk * c->n, sizeof(double));
+        c->star[k] = (double*)calloc((size_t)qk * c->n, sizeof(double));
         if (!c->pop[k] || !c->star[k]) { orc_destroy(c); return NULL; }
     }
 #define ALLOC(ptr, cnt, type) do { ptr = (type*)calloc((cnt), sizeof(type)); \
@@ -310,8 +331,8 @@ orc_ctx* orc_create(const orc_params* p)
         for (y = 0; y < p->ny; ++y)
         for (x = 0; x < p->nx; ++x) {
             int b = 0;
-            for (i = 1; i < c->q; ++i) {
-                int t[3] = {x + c->e[i][0], y + c->e[i][1], z + c->e[i][2]};
+            for (i = 1; i < c->lg.q; ++i) {
+                int t[3] = {x + c->lg.e[i][0], y + c->lg.e[i][1], z + c->lg.e[i][2]};
                 int nf;
                 if (crossed(c, t, &nf) && nf) b = 1;
             }
@@ -336,7 +357,7 @@ int orc_num_threads(void)
 /* Streaming, Sec. 3.4 eq. (Deplacement_STD), with the walls of reading R4.   */
 /* Push form: population i leaving x goes to x+e_i.                           */
 /* ------------------------------------------------------------------------- */
-static void stream(const orc_ctx* c, const double* src, double* dst)
+static void stream(const orc_ctx* c, const orc_lat* L, const double* src, double* dst)
 {
     const int nx = c->p.nx, ny = c->p.ny, nz = c->p.nz;
     const size_t n = c->n;
@@ -346,18 +367,18 @@ static void stream(const orc_ctx* c, const double* src, double* dst)
     for (int y = 0; y < ny; ++y)
     for (int x = 0; x < nx; ++x) {
         const size_t s = nidx(c, x, y, z);
-        for (int i = 0; i < c->q; ++i) {
-            int t[3] = {x + c->e[i][0], y + c->e[i][1], z + c->e[i][2]};
+        for (int i = 0; i < L->q; ++i) {
+            int t[3] = {x + L->e[i][0], y + L->e[i][1], z + L->e[i][2]};
             int nf;
             const int mask = crossed(c, t, &nf);
             if (!mask) {
                 dst[(size_t)i*n + nidx(c, t[0], t[1], t[2])] = src[(size_t)i*n + s];
             } else if (nf) {
                 /* half-way bounce-back: back into x along the opposite link */
-                dst[(size_t)c->opp[i]*n + s] = src[(size_t)i*n + s];
+                dst[(size_t)L->opp[i]*n + s] = src[(size_t)i*n + s];
             } else {
                 /* specular reflection on symmetry walls */
-                const int j = c->refl[mask][i];
+                const int j = L->refl[mask][i];
                 dst[(size_t)j*n + nidx(c, clampi(t[0], nx), clampi(t[1], ny), clampi(t[2], nz))]
                     = src[(size_t)i*n + s];
             }
@@ -365,14 +386,14 @@ static void stream(const orc_ctx* c, const double* src, double* dst)
     }
 }
 
-static void moment0(const orc_ctx* c, const double* pop, double* fld)
+static void moment0(const orc_ctx* c, const orc_lat* L, const double* pop, double* fld)
 {
     const size_t n = c->n;
     long long s;
 #pragma omp parallel for schedule(static)
     for (s = 0; s < (long long)n; ++s) {
         double acc = 0.0;
-        for (int i = 0; i < c->q; ++i) acc += pop[(size_t)i*n + (size_t)s];
+        for (int i = 0; i < L->q; ++i) acc += pop[(size_t)i*n + (size_t)s];
         fld[s] = acc;
     }
 }
@@ -396,7 +417,7 @@ static void phi_terms(orc_ctx* c, const double* phi, const double* U, const doub
             orc_anisotropy(p->aniso, p->eps, p->delta, g, &a, N);
         c->as2[s] = a * a;
         c->Nvec[3*s+0] = N[0]; c->Nvec[3*s+1] = N[1]; c->Nvec[3*s+2] = N[2];
-        c->eta[s] = a*a * p->W0*p->W0 * p->dt / (c->e2 * p->tau0 * p->dx*p->dx) + 0.5;
+        c->eta[s] = a*a * p->W0*p->W0 * p->dt / (c->lg.e2 * p->tau0 * p->dx*p->dx) + 0.5;
         {
             const double f = phi[s];
             const double om = 1.0 - f*f;
@@ -422,8 +443,9 @@ static void phi_collide(orc_ctx* c)
         const size_t s = nidx(c, x, y, z);
         const double a2 = c->bnode[s] ? 1.0 : c->as2[s];
         const double* N = &c->Nvec[3*s];
-        for (int i = 0; i < c->q; ++i) {
-            int t[3] = {x + c->e[i][0], y + c->e[i][1], z + c->e[i][2]};
+        const orc_lat* L = &c->lg;
+        for (int i = 0; i < L->q; ++i) {
+            int t[3] = {x + L->e[i][0], y + L->e[i][1], z + L->e[i][2]};
             int nf;
             const int mask = crossed(c, t, &nf);
             double nl;
@@ -432,14 +454,14 @@ static void phi_collide(orc_ctx* c)
             else if (nf)
                 nl = 0.0;   /* boundary node: coefficient (1 - a2) is zero */
             else
-                nl = g[(size_t)c->refl[mask][i]*n
+                nl = g[(size_t)L->refl[mask][i]*n
                        + nidx(c, clampi(t[0], p->nx), clampi(t[1], p->ny), clampi(t[2], p->nz))];
             {
-                const double eN = c->e[i][0]*N[0] + c->e[i][1]*N[1] + c->e[i][2]*N[2];
-                const double geq = c->w[i] * (c->phi[s] - eN * cphi / c->e2);
+                const double eN = L->e[i][0]*N[0] + L->e[i][1]*N[1] + L->e[i][2]*N[2];
+                const double geq = L->w[i] * (c->phi[s] - eN * cphi / L->e2);
                 const double gi = g[(size_t)i*n + s];
                 gs[(size_t)i*n + s] = (gi - (1.0 - a2) * nl - (gi - geq) / c->eta[s]
-                                       + c->w[i] * c->Qphi[s] * p->dt / p->tau0) / a2;
+                                       + L->w[i] * c->Qphi[s] * p->dt / p->tau0) / a2;
             }
         }
     }
@@ -528,8 +550,9 @@ static double theta_eq(const orc_ctx* c, int i, size_t s, double t)
     double v[3] = {p->vel[0], p->vel[1], p->vel[2]};
     if (c->vfield)
         for (int a = 0; a < 3; ++a) v[a] = c->vfield[(size_t)a * c->n + s];
-    const double ev = c->e[i][0]*v[0] + c->e[i][1]*v[1] + c->e[i][2]*v[2];
-    return c->w[i] * t * (1.0 + ev * p->dt / (c->e2 * p->dx));
+    const orc_lat* L = &c->lt;
+    const double ev = L->e[i][0]*v[0] + L->e[i][1]*v[1] + L->e[i][2]*v[2];
+    return L->w[i] * t * (1.0 + ev * p->dt / (L->e2 * p->dx));
 }
 
 int orc_set_velocity_field(orc_ctx* c, const double* vx, const double* vy, const double* vz)
@@ -554,21 +577,22 @@ static void ut_collide(orc_ctx* c)
 {
     const orc_params* p = &c->p;
     const size_t n = c->n;
-    const double etaU = p->D * p->dt / (c->e2 * p->dx * p->dx) + 0.5;
-    const double etaT = p->kappa * p->dt / (c->e2 * p->dx * p->dx) + 0.5;
+    const orc_lat* L = &c->lt;
+    const double etaU = p->D * p->dt / (L->e2 * p->dx * p->dx) + 0.5;
+    const double etaT = p->kappa * p->dt / (L->e2 * p->dx * p->dx) + 0.5;
     long long s;
 #pragma omp parallel for schedule(static)
     for (s = 0; s < (long long)n; ++s) {
         const double u = c->U[s], t = c->th[s];
         const double* J = &c->J[3*s];
-        for (int i = 0; i < c->q; ++i) {
+        for (int i = 0; i < L->q; ++i) {
             const size_t o = (size_t)i*n + (size_t)s;
-            const double eJ = c->e[i][0]*J[0] + c->e[i][1]*J[1] + c->e[i][2]*J[2];
-            const double heq = c->A[i]*u + c->B[i]*(c->r[s]*u + eJ * p->dt / (c->e2 * p->dx));
+            const double eJ = L->e[i][0]*J[0] + L->e[i][1]*J[1] + L->e[i][2]*J[2];
+            const double heq = L->A[i]*u + L->B[i]*(c->r[s]*u + eJ * p->dt / (L->e2 * p->dx));
             const double feq = theta_eq(c, i, (size_t)s, t);
             const double hi = c->pop[1][o], fi = c->pop[2][o];
-            c->star[1][o] = hi - (hi - heq) / etaU + c->w[i] * c->srcU[s] * p->dt;
-            c->star[2][o] = fi - (fi - feq) / etaT + c->w[i] * c->Qth[s] * p->dt;
+            c->star[1][o] = hi - (hi - heq) / etaU + L->w[i] * c->srcU[s] * p->dt;
+            c->star[2][o] = fi - (fi - feq) / etaT + L->w[i] * c->Qth[s] * p->dt;
         }
     }
 }
@@ -589,10 +613,11 @@ int orc_init(orc_ctx* c, const double* phi, const double* U, const double* theta
     ut_terms(c, c->phi, c->phi, c->U, c->th);
     for (size_t s = 0; s < n; ++s) {
         double geq[MAXQ], heq[MAXQ];
-        orc_geq(c->q, c->phi[s], &c->Nvec[3*s], cphi, geq);
-        orc_heq(c->q, c->U[s], c->r[s], &c->J[3*s], p->dt / p->dx, heq);
-        for (int i = 0; i < c->q; ++i) {
+        orc_geq(c->lg.q, c->phi[s], &c->Nvec[3*s], cphi, geq);
+        orc_heq(c->lt.q, c->U[s], c->r[s], &c->J[3*s], p->dt / p->dx, heq);
+        for (int i = 0; i < c->lg.q; ++i)
             c->pop[0][(size_t)i*n + s] = geq[i];
+        for (int i = 0; i < c->lt.q; ++i) {
             c->pop[1][(size_t)i*n + s] = heq[i];
             c->pop[2][(size_t)i*n + s] = theta_eq(c, i, s, c->th[s]);
         }
@@ -607,17 +632,17 @@ int orc_step(orc_ctx* c, int64_t nsteps)
         /* 1. phase field at time n */
         phi_terms(c, c->phi, c->U, c->th);
         phi_collide(c);
-        stream(c, c->star[0], c->pop[0]);
+        stream(c, &c->lg, c->star[0], c->pop[0]);
         memcpy(c->phi_old, c->phi, c->n * sizeof(double));
-        moment0(c, c->pop[0], c->phi);
+        moment0(c, &c->lg, c->pop[0], c->phi);
         /* 2. supersaturation and temperature with the new phase field */
         ut_terms(c, c->phi, c->phi_old, c->U, c->th);
         ut_collide(c);
-        stream(c, c->star[1], c->pop[1]);
-        moment0(c, c->pop[1], c->U);
+        stream(c, &c->lt, c->star[1], c->pop[1]);
+        moment0(c, &c->lt, c->pop[1], c->U);
         if (!c->p.skip_theta) {   /* isothermal runs hold theta */
-            stream(c, c->star[2], c->pop[2]);
-            moment0(c, c->pop[2], c->th);
+            stream(c, &c->lt, c->star[2], c->pop[2]);
+            moment0(c, &c->lt, c->pop[2], c->th);
         }
         c->steps++;
     }
@@ -629,7 +654,7 @@ int orc_stream_only(orc_ctx* c, int64_t nsteps)
     for (int64_t it = 0; it < nsteps; ++it) {
         for (int k = 0; k < 3; ++k) {
             double* tmp;
-            stream(c, c->pop[k], c->star[k]);
+            stream(c, k == 0 ? &c->lg : &c->lt, c->pop[k], c->star[k]);
             tmp = c->pop[k]; c->pop[k] = c->star[k]; c->star[k] = tmp;
         }
     }
@@ -645,14 +670,15 @@ void orc_fields(const orc_ctx* c, double* phi, double* U, double* theta)
 
 void orc_get_pops(const orc_ctx* c, int field, double* out)
 {
-    memcpy(out, c->pop[field], (size_t)c->q * c->n * sizeof(double));
+    memcpy(out, c->pop[field], (size_t)(field == 0 ? c->lg.q : c->lt.q) * c->n * sizeof(double));
 }
 
 void orc_set_pops(orc_ctx* c, int field, const double* in)
 {
     double* fld = field == 0 ? c->phi : (field == 1 ? c->U : c->th);
-    memcpy(c->pop[field], in, (size_t)c->q * c->n * sizeof(double));
-    moment0(c, c->pop[field], fld);
+    const orc_lat* L = field == 0 ? &c->lg : &c->lt;
+    memcpy(c->pop[field], in, (size_t)L->q * c->n * sizeof(double));
+    moment0(c, L, c->pop[field], fld);
 }
 
 /* ------------------------------------------------------------------------- */

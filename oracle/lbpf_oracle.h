@@ -43,6 +43,10 @@ typedef struct {
     int32_t skip_theta;       /* 1: isothermal (Sec. 4.2 benchmark): theta is
                                  held at its initial value, the heat equation
                                  is not solved */
+    int32_t lattice_ut;       /* lattice of the U and theta schemes (7, 15 or
+                                 19); 0: the phase field's.  Sec. 4.1 runs its
+                                 2D validation with D2Q9 for phi and D2Q5 for
+                                 theta */
 } orc_params;
 
 typedef struct orc_ctx orc_ctx;

@@ -510,3 +510,57 @@ def test_isothermal_uniform_recurrence(q):
     fa, fb = a.fields(), b.fields()
     assert np.array_equal(fa[2], seed.initial_fields()[2])
     assert np.max(np.abs(fa[0] - fb[0])) > 1e-3
+
+
+def test_separate_lattices():
+    """U and theta on their own lattice (the 2D validation of Sec. 4.1 uses
+    D2Q9 for phi and D2Q5 for theta): (i) the uniform-state recurrence does
+    not depend on the lattices; (ii) in a uniform liquid (phi = -1, where phi
+    does not act on U and theta) a Gaussian in U and theta evolves as on the
+    all-D3Q7 scheme (to rounding) and matches the diffusion closed form; (iii) the
+    permutation of streaming holds per field with the two lattices."""
+    kw = dict(walls=(NOFLUX, SYMMETRY, NOFLUX, NOFLUX, SYMMETRY, NOFLUX), dx=1.0, dt=0.11, W0=1.0,
+              tau0=1.0, lam=3.2, Mcinf=1.0, k=0.15, D=2.0, kappa=20.0)
+    o = Oracle(5, 4, 3, lattice=19, lattice_ut=7, **kw)
+    phi, U, th = 0.3, -0.4, -0.2
+    o.init(np.full((3, 4, 5), phi), np.full((3, 4, 5), U), np.full((3, 4, 5), th))
+    k = kw["k"]
+    zeta = lambda f: 0.5 * (1 + k) - 0.5 * (1 - k) * f
+    for _ in range(100):
+        Q = (phi - kw["lam"] * (kw["Mcinf"] * U + th) * (1 - phi ** 2)) * (1 - phi ** 2)
+        p1 = phi + kw["dt"] / kw["tau0"] * Q
+        th = th + 0.5 * (p1 - phi)
+        U = U + (1 + (1 - k) * U) * (p1 - phi) / (2 * zeta(p1))
+        phi = p1
+        o.step(1)
+        f = o.fields()
+        for fld, ref in zip(f, (phi, U, th)):
+            assert np.allclose(fld, ref, atol=1e-13, rtol=0)
+    # (ii) liquid: the Gaussian sees only the D3Q7 transport schemes
+    nx, sigma0, steps, D, kappa = 120, 6.0, 150, 0.1, 0.3
+    x = np.arange(nx) - (nx - 1) / 2.0
+    G = np.exp(-x ** 2 / (2 * sigma0 ** 2)).reshape(1, 1, nx)
+    base = dict(walls=(NOFLUX, NOFLUX) + (SYMMETRY,) * 4, dx=1.0, dt=1.0, W0=1.0, tau0=1.0,
+                lam=3.2, Mcinf=1.0, k=0.15, D=D, kappa=kappa)
+    runs = []
+    for lat, lut in ((19, 7), (7, 0)):
+        r = Oracle(nx, 1, 1, lattice=lat, lattice_ut=lut, **base)
+        r.init(np.full((1, 1, nx), -1.0), -0.5 + 0.2 * G, -0.3 + 0.1 * G)
+        r.step(steps)
+        runs.append(r.fields())
+    # equal up to the rounding of phi = -1 as a sum of 19 or 7 weighted populations
+    assert np.max(np.abs(runs[0][1] - runs[1][1])) < 1e-13
+    assert np.max(np.abs(runs[0][2] - runs[1][2])) < 1e-13
+    for fld, b0, amp, diff in ((runs[0][1], -0.5, 0.2, D), (runs[0][2], -0.3, 0.1, kappa)):
+        s2 = sigma0 ** 2 + 2 * diff * steps
+        exact = b0 + amp * np.sqrt(sigma0 ** 2 / s2) * np.exp(-x ** 2 / (2 * s2))
+        err = np.sqrt(np.mean((fld.ravel() - exact) ** 2)) / amp
+        assert err < 5e-3, err
+    # (iii) streaming is a permutation of each field's own lattice
+    s = Oracle(6, 5, 4, lattice=15, lattice_ut=7, **kw)
+    for field, q in ((0, 15), (1, 7), (2, 7)):
+        tags = np.random.default_rng(field).permutation(q * 120).astype(float).reshape(q, 4, 5, 6)
+        s.set_pops(field, tags)
+    s.stream_only(5)
+    for field, q in ((0, 15), (1, 7), (2, 7)):
+        assert np.array_equal(np.sort(s.pops(field).ravel()), np.arange(q * 120.0))

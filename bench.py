@@ -144,6 +144,34 @@ def run_single_field(steps, warmup, n, storage="f32"):
     return out
 
 
+def run_separate_lattices(steps, warmup, n):
+    """The same 256^3 seed with phi on D3Q19 and U, theta on D3Q7 (each
+    scheme on its own lattice, as Sec. 4.1 runs phi on D2Q9 and theta on
+    D2Q5), at dt/tau0 = 0.11, inside the D3Q7 U scheme's stable window."""
+    import dataclasses
+    import torch
+    from paper_1602_07483_amd import lbpf
+    from paper_1602_07483_amd.inputs import workload_centred
+
+    pb = dataclasses.replace(workload_centred(n=n), dt=0.11, reduce_every=0)
+    out = {"lattices": "phi D3Q19, U and theta D3Q7", "dt_over_tau0": 0.11, "steps": steps}
+    stream = torch.cuda.current_stream().cuda_stream
+    for storage in ("f32", "f16"):
+        s = lbpf.solver_for(pb, storage=storage, stream=stream, lattice_ut=7)
+        s.set_fields(*pb.initial_fields())
+        s.step(warmup)
+        s.sync()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s.step(steps)
+        s.sync()
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        s.close()
+        out[storage] = {"mlups": float(n) ** 3 * steps / wall / 1e6}
+    return out
+
+
 def run_ensemble(steps, seq_steps, storage="f16", graph_steps=50):
     """Batched ensemble of 64 uneven domains (mixed D3Q15/D3Q19, per-domain
     eps, Delta and noise seed) replayed from a HIP graph, against the same
@@ -304,9 +332,10 @@ def main():
                             "speedup_vs_f32": r["mlups"] / res["mlups"],
                             "kernels": r["kernels"]}
     copy_gbs = copy_bandwidth()
-    single_field = None
+    single_field = separate_lattices = None
     if not args.no_variants:
         single_field = run_single_field(max(args.steps // 3, 1), args.warmup, args.n)
+        separate_lattices = run_separate_lattices(max(args.steps // 3, 1), args.warmup, args.n)
     multiseed = None
     if not args.no_multiseed:
         multiseed = run_multiseed(args.multiseed_steps)
@@ -342,6 +371,7 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "single_field": single_field,
+        "separate_lattices": separate_lattices,
         "ensemble": ensemble,
         "multiseed": multiseed,
         "health": {"solid_fraction": res["solid_fraction"], "phi_range": res["phi_range"]},

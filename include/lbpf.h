@@ -87,6 +87,10 @@ typedef struct {
     int32_t lattice;        /* lbpf_lattice */
     int32_t wall[6];        /* lbpf_wall for faces -x,+x,-y,+y,-z,+z */
     int32_t storage;        /* lbpf_storage */
+    int32_t lattice_ut;     /* lattice of U and theta: 0 = that of phi, else an
+                               lbpf_lattice.  Each scheme then takes the e^2 of
+                               its own lattice (Sec. 4.1 runs phi on D2Q9 and
+                               theta on D2Q5).  Single contexts only. */
 } lbpf_grid;
 
 typedef struct {

@@ -965,7 +965,8 @@ __global__ __launch_bounds__(TX * TY, (sizeof(T) == 4 ? 3 : 1)) void k_ut_batch(
 template <class L, class T, class S>
 __global__ __launch_bounds__(256) void k_init(const Coef<T> c, S* __restrict__ g, S* __restrict__ h,
                                               S* __restrict__ f, const T* __restrict__ phi,
-                                              const T* __restrict__ U, const T* __restrict__ th) {
+                                              const T* __restrict__ U, const T* __restrict__ th,
+                                              int parts) {   // bit 0: g, bit 1: h and f (on lattice L)
     const int nx = c.nx, ny = c.ny, nz = c.nz, px = c.px;
     const size_t n = (size_t)nx * ny * nz;
     const size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x;   // node number
@@ -1002,11 +1003,11 @@ __global__ __launch_bounds__(256) void k_init(const Coef<T> c, S* __restrict__ g
         const T eN = T(L::ex(I)) * Nx + T(L::ey(I)) * Ny + T(L::ez(I)) * Nz;
         const T eJ = T(L::ex(I)) * Jx + T(L::ey(I)) * Jy + T(L::ez(I)) * Jz;
         const size_t o = (size_t)I * c.np + s;
-        g[o] = Codec<S>::enc(-wi * eN * c.cphi_e2);
-        h[o] = Codec<S>::enc((I == 0) ? T(0) : wi * eJ * c.jt);
+        if (parts & 1) g[o] = Codec<S>::enc(-wi * eN * c.cphi_e2);
+        if (parts & 2) h[o] = Codec<S>::enc((I == 0) ? T(0) : wi * eJ * c.jt);
         // f = w_i theta [1 + e_i . v dt / (e^2 dx)]: deviation w_i theta e_i . v'
         const T ev = T(L::ex(I)) * ax + T(L::ey(I)) * ay + T(L::ez(I)) * az;
-        f[o] = Codec<S>::enc(c.has_adv ? wi * th[s] * ev : T(0));
+        if (parts & 2) f[o] = Codec<S>::enc(c.has_adv ? wi * th[s] * ev : T(0));
     });
 }
 

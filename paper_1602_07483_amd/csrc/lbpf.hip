@@ -113,33 +113,54 @@ struct lbpf_batch {
 namespace {
 
 
+// part 0: the whole step on one lattice; 1: k_phi alone; 2: k_ut alone
 template <class L>
-lbpf_status launch_step_l(lbpf_ctx* ctx) {
+lbpf_status launch_step_l(lbpf_ctx* ctx, int part) {
     switch (ctx->storage) {
-        case LBPF_F32: return launch_step_s<L, float, float>(ctx);
-        case LBPF_F16_DEV: return launch_step_s<L, float, __half>(ctx);
-        case LBPF_BF16_DEV: return launch_step_s<L, float, __hip_bfloat16>(ctx);
-        case LBPF_F64: return launch_step_s<L, double, double>(ctx);
+        case LBPF_F32:
+            return part == 0 ? launch_step_s<L, float, float>(ctx)
+                             : part == 1 ? launch_phi_s<L, float, float>(ctx) : launch_ut_s<L, float, float>(ctx);
+        case LBPF_F16_DEV:
+            return part == 0 ? launch_step_s<L, float, __half>(ctx)
+                             : part == 1 ? launch_phi_s<L, float, __half>(ctx) : launch_ut_s<L, float, __half>(ctx);
+        case LBPF_BF16_DEV:
+            return part == 0   ? launch_step_s<L, float, __hip_bfloat16>(ctx)
+                   : part == 1 ? launch_phi_s<L, float, __hip_bfloat16>(ctx)
+                               : launch_ut_s<L, float, __hip_bfloat16>(ctx);
+        case LBPF_F64:
+            return part == 0 ? launch_step_s<L, double, double>(ctx)
+                             : part == 1 ? launch_phi_s<L, double, double>(ctx) : launch_ut_s<L, double, double>(ctx);
     }
     return fail(ctx, LBPF_EINVAL, "bad storage");
 }
 
-lbpf_status launch_step(lbpf_ctx* ctx) {
-    switch (ctx->q) {
-        case 7: return launch_step_l<D3Q7>(ctx);
-        case 15: return launch_step_l<D3Q15>(ctx);
-        default: return launch_step_l<D3Q19>(ctx);
+lbpf_status launch_step_q(lbpf_ctx* ctx, int q, int part) {
+    switch (q) {
+        case 7: return launch_step_l<D3Q7>(ctx, part);
+        case 15: return launch_step_l<D3Q15>(ctx, part);
+        default: return launch_step_l<D3Q19>(ctx, part);
     }
 }
 
+lbpf_status launch_step(lbpf_ctx* ctx) {
+    if (ctx->q_ut == ctx->q) return launch_step_q(ctx, ctx->q, 0);
+    // phase field and transport fields on different lattices (Sec. 4.1's 2D validation)
+    lbpf_status st = launch_step_q(ctx, ctx->q, 1);
+    if (!st) st = launch_step_q(ctx, ctx->q_ut, 2);
+    if (!st) ctx->cur = 1 - ctx->cur;
+    return st;
+}
+
+// Initial populations of the sets whose lattice is L.
 template <class L, class T, class S>
 lbpf_status launch_init_t(lbpf_ctx* ctx) {
     const Coef<T> c = make_coef<T>(ctx);
     const int nb = (int)((ctx->n + 255) / 256);
     const int a = ctx->cur;
+    const int parts = (ctx->q == L::Q ? 1 : 0) | (ctx->q_ut == L::Q ? 2 : 0);
     hipLaunchKernelGGL((k_init<L, T, S>), dim3(nb), dim3(256), 0, ctx->stream, c, (S*)ctx->pop[0][a],
                        (S*)ctx->pop[1][a], (S*)ctx->pop[2][a], (const T*)ctx->fld[0][a],
-                       (const T*)ctx->fld[1][a], (const T*)ctx->fld[2][a]);
+                       (const T*)ctx->fld[1][a], (const T*)ctx->fld[2][a], parts);
     CHK(hipGetLastError());
     return LBPF_OK;
 }
@@ -172,26 +193,42 @@ lbpf_status init_or_decode_l(lbpf_ctx* ctx, int what, int field, double* dout) {
     return fail(ctx, LBPF_EINVAL, "bad storage");
 }
 
-lbpf_status init_or_decode(lbpf_ctx* ctx, int what, int field, double* dout) {
-    switch (ctx->q) {
+lbpf_status init_or_decode_q(lbpf_ctx* ctx, int q, int what, int field, double* dout) {
+    switch (q) {
         case 7: return init_or_decode_l<D3Q7>(ctx, what, field, dout);
         case 15: return init_or_decode_l<D3Q15>(ctx, what, field, dout);
         default: return init_or_decode_l<D3Q19>(ctx, what, field, dout);
     }
 }
 
+// what 0: initial populations of every set (one launch per lattice in use);
+// what 1: decode one field's populations on its lattice.
+lbpf_status init_or_decode(lbpf_ctx* ctx, int what, int field, double* dout) {
+    if (what == 1) return init_or_decode_q(ctx, field == 0 ? ctx->q : ctx->q_ut, 1, field, dout);
+    lbpf_status st = init_or_decode_q(ctx, ctx->q, 0, field, dout);
+    if (!st && ctx->q_ut != ctx->q) st = init_or_decode_q(ctx, ctx->q_ut, 0, field, dout);
+    return st;
+}
+
+// Streams the population sets of the fields in [f0, f1) on lattice L.
 template <class L, class B>
-lbpf_status stream_only_t(lbpf_ctx* ctx) {
+lbpf_status stream_only_t(lbpf_ctx* ctx, int f0, int f1) {
     int symm = 0;
     for (int f = 0; f < 6; ++f)
         if (ctx->grid.wall[f] == LBPF_WALL_SYMMETRY) symm |= 1 << f;
     const int nb = (int)((ctx->n + 255) / 256);
     const int a = ctx->cur, b = 1 - ctx->cur;
-    for (int f = 0; f < 3; ++f)
+    for (int f = f0; f < f1; ++f)
         hipLaunchKernelGGL((k_stream_only<L, B>), dim3(nb), dim3(256), 0, ctx->stream, ctx->grid.nx,
                            ctx->grid.ny, ctx->grid.nz, ctx->px, symm, (long long)ctx->np,
                            (const B*)ctx->pop[f][a], (B*)ctx->pop[f][b]);
     CHK(hipGetLastError());
+    return LBPF_OK;
+}
+
+// The fields follow the populations' parity unchanged.
+lbpf_status stream_only_fields(lbpf_ctx* ctx) {
+    const int a = ctx->cur, b = 1 - ctx->cur;
     // the fields follow the populations' parity unchanged
     for (int f = 0; f < 3; ++f)
         CHK(hipMemcpyAsync(ctx->fld[f][b], ctx->fld[f][a], ctx->na * ctx->tbytes,
@@ -201,13 +238,21 @@ lbpf_status stream_only_t(lbpf_ctx* ctx) {
 }
 
 template <class L>
-lbpf_status stream_only_l(lbpf_ctx* ctx) {
+lbpf_status stream_only_l(lbpf_ctx* ctx, int f0, int f1) {
     switch (ctx->sbytes) {
-        case 2: return stream_only_t<L, uint16_t>(ctx);
-        case 4: return stream_only_t<L, uint32_t>(ctx);
-        case 8: return stream_only_t<L, uint64_t>(ctx);
+        case 2: return stream_only_t<L, uint16_t>(ctx, f0, f1);
+        case 4: return stream_only_t<L, uint32_t>(ctx, f0, f1);
+        case 8: return stream_only_t<L, uint64_t>(ctx, f0, f1);
     }
     return fail(ctx, LBPF_EINVAL, "bad storage");
+}
+
+lbpf_status stream_only_q(lbpf_ctx* ctx, int q, int f0, int f1) {
+    switch (q) {
+        case 7: return stream_only_l<D3Q7>(ctx, f0, f1);
+        case 15: return stream_only_l<D3Q15>(ctx, f0, f1);
+        default: return stream_only_l<D3Q19>(ctx, f0, f1);
+    }
 }
 
 template <class T>
@@ -342,6 +387,9 @@ lbpf_status lbpf_create(const lbpf_grid* grid, const lbpf_params* params, void* 
     if ((double)g.nx * g.ny * g.nz > 2.0e9) return fail(nullptr, LBPF_EINVAL, "grid too large");
     if (g.lattice != LBPF_D3Q7 && g.lattice != LBPF_D3Q15 && g.lattice != LBPF_D3Q19)
         return fail(nullptr, LBPF_EINVAL, "lattice must be 7, 15 or 19");
+    if (g.lattice_ut != 0 && g.lattice_ut != LBPF_D3Q7 && g.lattice_ut != LBPF_D3Q15 &&
+        g.lattice_ut != LBPF_D3Q19)
+        return fail(nullptr, LBPF_EINVAL, "lattice_ut must be 0, 7, 15 or 19");
     if (lbpf_storage_bytes(g.storage) == 0) return fail(nullptr, LBPF_EINVAL, "bad storage");
     for (int f = 0; f < 6; ++f)
         if (g.wall[f] != LBPF_WALL_NOFLUX && g.wall[f] != LBPF_WALL_SYMMETRY)
@@ -380,6 +428,7 @@ lbpf_status lbpf_create(const lbpf_grid* grid, const lbpf_params* params, void* 
         ctx->own_stream = true;
     }
     ctx->q = g.lattice;
+    ctx->q_ut = g.lattice_ut ? g.lattice_ut : g.lattice;
     ctx->storage = g.storage;
     ctx->sbytes = (size_t)lbpf_storage_bytes(g.storage);
     ctx->tbytes = g.storage == LBPF_F64 ? 8 : 4;
@@ -397,7 +446,7 @@ lbpf_status lbpf_create(const lbpf_grid* grid, const lbpf_params* params, void* 
     hipError_t e = hipSuccess;
     for (int f = 0; f < 3 && e == hipSuccess; ++f)
         for (int par = 0; par < 2 && e == hipSuccess; ++par) {
-            e = hipMalloc(&ctx->pop[f][par], ctx->np * ctx->q * ctx->sbytes);
+            e = hipMalloc(&ctx->pop[f][par], ctx->np * lattice_of(ctx, f) * ctx->sbytes);
             if (e == hipSuccess) e = hipMalloc(&ctx->fld[f][par], ctx->na * ctx->tbytes);
         }
     if (e == hipSuccess) e = hipMalloc((void**)&ctx->part, RED_BLOCKS * RED_STRIDE * sizeof(double));
@@ -625,7 +674,7 @@ lbpf_status lbpf_read_populations(lbpf_ctx* ctx, int32_t field, void* dst) {
     const size_t arr = ctx->n * ctx->sbytes, w = ctx->grid.nx * ctx->sbytes, pw = ctx->px * ctx->sbytes;
     const size_t rows = (size_t)ctx->grid.ny * ctx->grid.nz;
     std::vector<char> tmp(ctx->na * ctx->sbytes);
-    for (int i = 0; i < ctx->q; ++i) {
+    for (int i = 0; i < lattice_of(ctx, field); ++i) {
         CHK(hipMemcpy(tmp.data(), (const char*)ctx->pop[field][ctx->cur] + i * ctx->np * ctx->sbytes, tmp.size(),
                       hipMemcpyDeviceToHost));
         unpack_rows((char*)dst + i * arr, tmp.data(), w, pw, rows);
@@ -641,7 +690,7 @@ lbpf_status lbpf_write_populations(lbpf_ctx* ctx, int32_t field, const void* src
     const size_t arr = ctx->n * ctx->sbytes, w = ctx->grid.nx * ctx->sbytes, pw = ctx->px * ctx->sbytes;
     const size_t rows = (size_t)ctx->grid.ny * ctx->grid.nz;
     std::vector<char> tmp(ctx->na * ctx->sbytes, 0);
-    for (int i = 0; i < ctx->q; ++i) {
+    for (int i = 0; i < lattice_of(ctx, field); ++i) {
         pack_rows(tmp.data(), (const char*)src + i * arr, w, pw, rows);
         CHK(hipMemcpy((char*)ctx->pop[field][ctx->cur] + i * ctx->np * ctx->sbytes, tmp.data(), tmp.size(),
                       hipMemcpyHostToDevice));
@@ -654,7 +703,7 @@ lbpf_status lbpf_read_populations_f64(lbpf_ctx* ctx, int32_t field, double* dst)
     if (field < 0 || field > 2 || !dst) return fail(ctx, LBPF_EINVAL, "bad field or NULL dst");
     if (!ctx->have_fields) return fail(ctx, LBPF_ESTATE, "lbpf_set_fields has not been called");
     double* d = nullptr;
-    const size_t bytes = ctx->n * ctx->q * sizeof(double);
+    const size_t bytes = ctx->n * lattice_of(ctx, field) * sizeof(double);
     CHK(hipStreamSynchronize(ctx->stream));
     CHK(hipMalloc((void**)&d, bytes));
     lbpf_status st = init_or_decode(ctx, 1, field, d);
@@ -672,9 +721,9 @@ lbpf_status lbpf_debug_stream_only(lbpf_ctx* ctx, int64_t nsteps) {
     if (nsteps < 0) return fail(ctx, LBPF_EINVAL, "nsteps < 0");
     if (!ctx->have_fields) return fail(ctx, LBPF_ESTATE, "lbpf_set_fields has not been called");
     for (int64_t s = 0; s < nsteps; ++s) {
-        lbpf_status st = ctx->q == 7    ? stream_only_l<D3Q7>(ctx)
-                         : ctx->q == 15 ? stream_only_l<D3Q15>(ctx)
-                                        : stream_only_l<D3Q19>(ctx);
+        lbpf_status st = stream_only_q(ctx, ctx->q, 0, 1);
+        if (!st) st = stream_only_q(ctx, ctx->q_ut, 1, 3);
+        if (!st) st = stream_only_fields(ctx);
         if (st) return st;
     }
     return LBPF_OK;
@@ -754,12 +803,16 @@ lbpf_status lbpf_autotune(lbpf_ctx* ctx, int32_t steps_per_candidate, double* be
     if (!ctx->have_fields) return fail(ctx, LBPF_ESTATE, "lbpf_set_fields has not been called");
     CHK(hipStreamSynchronize(ctx->stream));
     // snapshot of the current state (populations and fields of parity cur)
-    const size_t pbytes = ctx->np * ctx->q * ctx->sbytes, fbytes = ctx->na * ctx->tbytes;
+    // (one slot per population set, sized for the larger lattice)
+    const size_t pbytes = ctx->np * std::max(ctx->q, ctx->q_ut) * ctx->sbytes, fbytes = ctx->na * ctx->tbytes;
+    size_t pset[3];
+    for (int f = 0; f < 3; ++f) pset[f] = ctx->np * lattice_of(ctx, f) * ctx->sbytes;
     void* snap = nullptr;
     CHK(hipMalloc(&snap, 3 * (pbytes + fbytes)));
     const int cur0 = ctx->cur;
     for (int f = 0; f < 3; ++f) {
-        CHK(hipMemcpyAsync((char*)snap + f * pbytes, ctx->pop[f][cur0], pbytes, hipMemcpyDeviceToDevice, ctx->stream));
+        CHK(hipMemcpyAsync((char*)snap + f * pbytes, ctx->pop[f][cur0], pset[f], hipMemcpyDeviceToDevice,
+                           ctx->stream));
         CHK(hipMemcpyAsync((char*)snap + 3 * pbytes + f * fbytes, ctx->fld[f][cur0], fbytes,
                            hipMemcpyDeviceToDevice, ctx->stream));
     }
@@ -808,7 +861,8 @@ lbpf_status lbpf_autotune(lbpf_ctx* ctx, int32_t steps_per_candidate, double* be
     // restore the state and keep the best launch of each kernel
     ctx->cur = cur0;
     for (int f = 0; f < 3; ++f) {
-        (void)hipMemcpyAsync(ctx->pop[f][cur0], (char*)snap + f * pbytes, pbytes, hipMemcpyDeviceToDevice, ctx->stream);
+        (void)hipMemcpyAsync(ctx->pop[f][cur0], (char*)snap + f * pbytes, pset[f], hipMemcpyDeviceToDevice,
+                             ctx->stream);
         (void)hipMemcpyAsync(ctx->fld[f][cur0], (char*)snap + 3 * pbytes + f * fbytes, fbytes,
                              hipMemcpyDeviceToDevice, ctx->stream);
     }
@@ -866,7 +920,7 @@ lbpf_status lbpf_set_velocity_field(lbpf_ctx* ctx, const double* vx, const doubl
         ctx->vfield = nullptr;
     } else {
         if (!vx || !vy || !vz) return fail(ctx, LBPF_EINVAL, "give all three velocity components or none");
-        const double scale = ctx->prm.dt / (lattice_e2(ctx->q) * ctx->prm.dx);
+        const double scale = ctx->prm.dt / (lattice_e2(ctx->q_ut) * ctx->prm.dx);   // theta's lattice
         // device layout: three arrays of na values with the fields' row pitch
         const size_t na = ctx->na, nx = ctx->grid.nx;
         std::vector<char> host(3 * na * ctx->tbytes, 0);
@@ -1061,6 +1115,8 @@ lbpf_status lbpf_batch_create(int32_t n, const lbpf_grid* grids, const lbpf_para
     for (int i = 0; i < n; ++i) {
         if (grids[i].lattice != LBPF_D3Q7 && grids[i].lattice != LBPF_D3Q15 && grids[i].lattice != LBPF_D3Q19)
             return bfail(nullptr, LBPF_EINVAL, "batched domains use D3Q7, D3Q15 or D3Q19");
+        if (grids[i].lattice_ut != 0 && grids[i].lattice_ut != grids[i].lattice)
+            return bfail(nullptr, LBPF_EINVAL, "batched domains run every field on one lattice");
         if (params[i].vel[0] != 0.0 || params[i].vel[1] != 0.0 || params[i].vel[2] != 0.0)
             return bfail(nullptr, LBPF_EINVAL, "batched domains have no advective velocity");
         if (params[i].skip_U || params[i].skip_theta)

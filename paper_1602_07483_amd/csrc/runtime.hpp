@@ -63,7 +63,8 @@ struct lbpf_ctx {
     int graph_steps = 0;     // >0: replay the step loop from a captured HIP graph
     hipGraphExec_t gexec = nullptr;
     int g_shape[2] = {-1, -1}, g_zslab[2] = {-1, -1}, g_remap[2] = {-1, -1}, g_cur = -1;
-    int q = 19;
+    int q = 19;              // lattice of g (phase field)
+    int q_ut = 19;           // lattice of h and f (U, theta)
     int storage = LBPF_F32;
     size_t sbytes = 4;       // bytes per stored population
     size_t tbytes = 4;       // bytes per field value (compute type)
@@ -114,7 +115,8 @@ template <class T>
 Coef<T> make_coef(const lbpf_ctx* ctx, int k = K_PHI) {
     const lbpf_params& p = ctx->prm;
     const lbpf_grid& g = ctx->grid;
-    const double kE2 = lattice_e2(ctx->q);
+    // each scheme takes the e^2 of its own lattice
+    const double e2g = lattice_e2(ctx->q), kE2 = lattice_e2(ctx->q_ut);
     const Shape sh = kShapes[ctx->shape[k]];
     Coef<T> c{};
     c.nx = g.nx; c.ny = g.ny; c.nz = g.nz;
@@ -133,8 +135,8 @@ Coef<T> make_coef(const lbpf_ctx* ctx, int k = K_PHI) {
     c.delta = (T)p.delta;
     c.inv2dx = (T)(1.0 / (2.0 * p.dx));
     c.smin = (T)(1e-12 / (p.dx * p.dx));
-    c.eta_c = (T)(p.W0 * p.W0 * p.dt / (kE2 * p.tau0 * p.dx * p.dx));
-    c.cphi_e2 = (T)(p.dt * p.W0 * p.W0 / (p.dx * p.tau0 * kE2));
+    c.eta_c = (T)(p.W0 * p.W0 * p.dt / (e2g * p.tau0 * p.dx * p.dx));
+    c.cphi_e2 = (T)(p.dt * p.W0 * p.W0 / (p.dx * p.tau0 * e2g));
     c.dt_tau0 = (T)(p.dt / p.tau0);
     c.lambda = (T)p.lambda;
     c.Mcinf = (T)p.Mcinf;
@@ -164,6 +166,9 @@ inline bool has_advection(const lbpf_ctx* ctx) {
     return ctx->vfield != nullptr || ctx->prm.vel[0] != 0.0 || ctx->prm.vel[1] != 0.0 ||
            ctx->prm.vel[2] != 0.0;
 }
+
+// Lattice of field f's populations (0: phi; 1, 2: U, theta).
+inline int lattice_of(const lbpf_ctx* ctx, int f) { return f == 0 ? ctx->q : ctx->q_ut; }
 
 inline int default_shape(const lbpf_ctx* ctx, int k) { return kDefaultShape[k][ctx->storage]; }
 
@@ -217,5 +222,11 @@ lbpf_status timed(lbpf_ctx* ctx, int kind, F&& launch) {
 // storage S; defined in step.hip, instantiated once per pair.
 template <class L, class T, class S>
 lbpf_status launch_step_s(lbpf_ctx* ctx);
+// The two kernels alone, for a phase field and transport fields on different
+// lattices (the caller flips the parity after both).
+template <class L, class T, class S>
+lbpf_status launch_phi_s(lbpf_ctx* ctx);
+template <class L, class T, class S>
+lbpf_status launch_ut_s(lbpf_ctx* ctx);
 
 }  // namespace lbpf_rt

@@ -96,6 +96,12 @@ lbpf_status launch_step_s(lbpf_ctx* ctx) {
     return LBPF_OK;
 }
 
+template <class L, class T, class S>
+lbpf_status launch_phi_s(lbpf_ctx* ctx) { return launch_k<L, T, S, K_PHI>(ctx); }
+
+template <class L, class T, class S>
+lbpf_status launch_ut_s(lbpf_ctx* ctx) { return launch_k<L, T, S, K_UT>(ctx); }
+
 #if LBPF_STEP_Q == 7
 using StepL = D3Q7;
 #elif LBPF_STEP_Q == 15
@@ -107,15 +113,18 @@ using StepL = D3Q19;
 #endif
 
 #if LBPF_STEP_STORAGE == 0
-template lbpf_status launch_step_s<StepL, float, float>(lbpf_ctx*);
+#define LBPF_STEP_TYPES float, float
 #elif LBPF_STEP_STORAGE == 1
-template lbpf_status launch_step_s<StepL, float, __half>(lbpf_ctx*);
+#define LBPF_STEP_TYPES float, __half
 #elif LBPF_STEP_STORAGE == 2
-template lbpf_status launch_step_s<StepL, float, __hip_bfloat16>(lbpf_ctx*);
+#define LBPF_STEP_TYPES float, __hip_bfloat16
 #elif LBPF_STEP_STORAGE == 3
-template lbpf_status launch_step_s<StepL, double, double>(lbpf_ctx*);
+#define LBPF_STEP_TYPES double, double
 #else
 #error "LBPF_STEP_STORAGE must be an lbpf_storage value"
 #endif
+template lbpf_status launch_step_s<StepL, LBPF_STEP_TYPES>(lbpf_ctx*);
+template lbpf_status launch_phi_s<StepL, LBPF_STEP_TYPES>(lbpf_ctx*);
+template lbpf_status launch_ut_s<StepL, LBPF_STEP_TYPES>(lbpf_ctx*);
 
 }  // namespace lbpf_rt

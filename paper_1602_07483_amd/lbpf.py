@@ -26,7 +26,7 @@ _POP_DTYPE = {LBPF_F32: np.uint32, LBPF_F16_DEV: np.uint16, LBPF_BF16_DEV: np.ui
 class lbpf_grid(ctypes.Structure):
     _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
                 ("lattice", ctypes.c_int32), ("wall", ctypes.c_int32 * 6),
-                ("storage", ctypes.c_int32)]
+                ("storage", ctypes.c_int32), ("lattice_ut", ctypes.c_int32)]
 
 
 class lbpf_params(ctypes.Structure):
@@ -155,13 +155,14 @@ def lbpf_bench_copy(dst_ptr, src_ptr, nbytes, stream_ptr=0):
 def make_structs(nx, ny, nz, lattice=19, walls=(0,) * 6, storage="f32", dx=1.0, dt=1.0,
                  W0=1.0, tau0=1.0, lam=3.2, Mcinf=1.0, k=0.15, D=2.0, kappa=20.0, aniso=0,
                  eps=0.05, delta=0.0, reduce_every=0, centre=(0.0, 0.0, 0.0),
-                 vel=(0.0, 0.0, 0.0), skip_U=0, skip_theta=0):
+                 vel=(0.0, 0.0, 0.0), skip_U=0, skip_theta=0, lattice_ut=0):
     """(lbpf_grid, lbpf_params) filled from keyword arguments."""
     g = lbpf_grid()
     g.nx, g.ny, g.nz, g.lattice = int(nx), int(ny), int(nz), int(lattice)
     for i, w in enumerate(walls):
         g.wall[i] = int(w)
     g.storage = STORAGE[storage] if isinstance(storage, str) else int(storage)
+    g.lattice_ut = int(lattice_ut)
     p = lbpf_params()
     p.dx, p.dt, p.W0, p.tau0 = dx, dt, W0, tau0
     p.lam, p.Mcinf, p.k, p.D, p.kappa = lam, Mcinf, k, D, kappa
@@ -186,6 +187,7 @@ class Solver:
         self.grid, self.params = grid, params
         self.shape = (grid.nz, grid.ny, grid.nx)
         self.q = grid.lattice
+        self.q_ut = grid.lattice_ut or grid.lattice
         self.storage = grid.storage
         self._h = ctypes.c_void_p(handle)
         self._owner = owner          # the batch keeps the memory; never destroyed here
@@ -194,15 +196,16 @@ class Solver:
     def __init__(self, nx, ny, nz, lattice=19, walls=(0,) * 6, storage="f32", dx=1.0, dt=1.0,
                  W0=1.0, tau0=1.0, lam=3.2, Mcinf=1.0, k=0.15, D=2.0, kappa=20.0, aniso=0,
                  eps=0.05, delta=0.0, reduce_every=0, centre=(0.0, 0.0, 0.0),
-                 vel=(0.0, 0.0, 0.0), skip_U=0, skip_theta=0, stream=0):
+                 vel=(0.0, 0.0, 0.0), skip_U=0, skip_theta=0, lattice_ut=0, stream=0):
         self._lib = lib()
         self._owner = None
         g, p = make_structs(nx, ny, nz, lattice, walls, storage, dx, dt, W0, tau0, lam, Mcinf, k,
                             D, kappa, aniso, eps, delta, reduce_every, centre, vel, skip_U,
-                            skip_theta)
+                            skip_theta, lattice_ut)
         self.grid, self.params = g, p
         self.shape = (int(nz), int(ny), int(nx))
         self.q = int(lattice)
+        self.q_ut = int(lattice_ut) or int(lattice)
         self.storage = g.storage
         h = ctypes.c_void_p()
         st = self._lib.lbpf_create(ctypes.byref(g), ctypes.byref(p), ctypes.c_void_p(stream),
@@ -275,19 +278,23 @@ class Solver:
         self._check(self._lib.lbpf_history(self._h, buf, int(max_records), ctypes.byref(cnt)))
         return [buf[i].as_dict() for i in range(cnt.value)]
 
+    def lattice_of(self, field):
+        """Directions of field's populations (0: phi; 1, 2: U, theta)."""
+        return self.q if int(field) == 0 else self.q_ut
+
     def read_populations(self, field):
-        out = np.empty((self.q,) + self.shape, dtype=_POP_DTYPE[self.storage])
+        out = np.empty((self.lattice_of(field),) + self.shape, dtype=_POP_DTYPE[self.storage])
         self._check(self._lib.lbpf_read_populations(self._h, int(field),
                                                     out.ctypes.data_as(ctypes.c_void_p)))
         return out
 
     def read_populations_f64(self, field):
-        out = np.empty((self.q,) + self.shape)
+        out = np.empty((self.lattice_of(field),) + self.shape)
         self._check(self._lib.lbpf_read_populations_f64(self._h, int(field), _dptr(out)))
         return out
 
     def write_populations(self, field, arr):
-        a = np.ascontiguousarray(arr).view(_POP_DTYPE[self.storage]).reshape((self.q,) + self.shape)
+        a = np.ascontiguousarray(arr).view(_POP_DTYPE[self.storage]).reshape((self.lattice_of(field),) + self.shape)
         self._check(self._lib.lbpf_write_populations(self._h, int(field),
                                                      a.ctypes.data_as(ctypes.c_void_p)))
 

@@ -372,3 +372,55 @@ def test_mixed_storage_variants_report(storage, bound):
         checked = [e for i, e in enumerate(errs) if not (name == "skip_U" and i == 1)]
         assert max(checked) <= bound, name
         s.close()
+
+
+# ------------------------------------------------------------- separate lattices
+# phi on one lattice, U and theta on another (Sec. 4.1 validates with D2Q9
+# for phi and D2Q5 for theta); each scheme takes its own lattice's e^2.
+def _mixed_problem(lattice):
+    # dt/tau0 = 0.11: inside the window of the coupled U scheme on D3Q7
+    return dataclasses.replace(ragged_problem(lattice, 0), dt=STABLE_DT[7])
+
+
+@pytest.mark.parametrize("lattice,lattice_ut", [(19, 7), (15, 7), (7, 19)])
+@pytest.mark.parametrize("storage", ["f32", "f64"])
+def test_separate_lattices_stream_only_bitexact(lattice, lattice_ut, storage):
+    pb = _mixed_problem(lattice)
+    s = make_gpu(pb, storage=storage, lattice_ut=lattice_ut)
+    o = Oracle(pb.nx, pb.ny, pb.nz, **dict(pb.model_kwargs(), lattice_ut=lattice_ut))
+    o.init(*pb.initial_fields())
+    rng = np.random.default_rng(100 + lattice)
+    fdt = np.float32 if storage == "f32" else np.float64
+    for field in range(3):
+        q = lattice if field == 0 else lattice_ut
+        assert s.lattice_of(field) == q
+        tags = rng.permutation(q * pb.nodes).reshape((q,) + pb.shape)
+        s.write_populations(field, tags.astype(fdt))
+        o.set_pops(field, tags.astype(np.float64))
+    s.debug_stream_only(7)
+    o.stream_only(7)
+    for field in range(3):
+        g = s.read_populations(field).view(fdt).astype(np.float64)
+        assert np.array_equal(g, o.pops(field)), "field %d" % field
+
+
+@pytest.mark.parametrize("lattice,lattice_ut,storage,tol", [(19, 7, "f64", 1e-11), (15, 7, "f64", 1e-11),
+                                                            (7, 19, "f64", 1e-11), (19, 7, "f32", 1e-5)])
+def test_separate_lattices_match_oracle(lattice, lattice_ut, storage, tol):
+    """phi, U and theta against the oracle's separate-lattice mode after 60
+    steps of the ragged case; the decoded populations of each field too."""
+    pb = _mixed_problem(lattice)
+    s = make_gpu(pb, storage=storage, lattice_ut=lattice_ut)
+    o = Oracle(pb.nx, pb.ny, pb.nz, **dict(pb.model_kwargs(), lattice_ut=lattice_ut))
+    o.init(*pb.initial_fields())
+    s.step(60)
+    o.step(60)
+    gphi, gU, gth, _ = s.read(reductions=False)
+    ophi, oU, oth = o.fields()
+    ephi, eU, eth = maxabs(gphi, ophi), maxabs(gU, oU), maxabs(gth, oth)
+    print("%s q%d/q%d: max|dphi| %.3e max|dU| %.3e max|dtheta| %.3e"
+          % (storage, lattice, lattice_ut, ephi, eU, eth))
+    assert max(ephi, eU, eth) <= tol
+    if storage == "f64":
+        for field in range(3):
+            assert maxabs(s.read_populations_f64(field), o.pops(field)) <= tol, field

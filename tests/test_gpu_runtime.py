@@ -288,3 +288,38 @@ def test_device_field_io_matches_host_io(storage, dtype):
     finally:
         for b in bufs:
             hip.hipFree(b)
+
+
+def test_separate_lattices_runtime_paths():
+    """phi on D3Q19 with U and theta on D3Q7: graph replay, the autotuner
+    (which restores the state it found) and checkpoint/restore of the
+    population sets of both lattices all give the plain launches' fields bit
+    for bit."""
+    pb = dataclasses.replace(ragged(), dt=0.11)
+    plain = make_gpu(pb, "f32", lattice_ut=7)
+    graph = make_gpu(pb, "f32", lattice_ut=7)
+    graph.set_graph(4)
+    for chunk in (3, 8, 5):
+        plain.step(chunk)
+        graph.step(chunk)
+        for x, y in zip(fields(plain), fields(graph)):
+            assert np.array_equal(x, y), chunk
+    launches, best = graph.autotune(1)
+    assert best > 0 and set(launches) == {"k_phi", "k_ut"}
+    for x, y in zip(fields(plain), fields(graph)):
+        assert np.array_equal(x, y), "state after autotune"
+    pops = [plain.read_populations(f) for f in range(3)]
+    assert [p.shape[0] for p in pops] == [19, 7, 7]
+    state = fields(plain)
+    for s in (plain, graph):
+        s.step(12)
+    want = fields(plain)
+    for x, y in zip(want, fields(graph)):
+        assert np.array_equal(x, y), "after autotune, 12 steps"
+    r = lbpf.solver_for(pb, storage="f32", lattice_ut=7)
+    r.set_fields(*state)
+    for f in range(3):
+        r.write_populations(f, pops[f])
+    r.step(12)
+    for x, y in zip(want, fields(r)):
+        assert np.array_equal(x, y), "restored"

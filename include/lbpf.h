@@ -237,19 +237,22 @@ lbpf_status lbpf_read_fields_device(lbpf_ctx* ctx, void* phi, void* U, void* the
  * (A_i + B_i q(phi)/zeta(phi)) U, w_i theta), so the stored state is the pair
  * (fields, deviations): a checkpoint is lbpf_read of the fields plus these
  * three arrays; a restore is lbpf_set_fields of the saved fields followed by
- * the three writes.  The size of dst/src is Q*nx*ny*nz*lbpf_storage_bytes.
+ * the three writes.  Q is the field's lattice (lbpf_grid.lattice for phi,
+ * lattice_ut, when set, for U and theta); the size of dst/src is
+ * Q*nx*ny*nz*lbpf_storage_bytes.
  * Both synchronise; the fields are not changed by a write.
  * Errors: EINVAL (bad field, NULL), ESTATE (write before set_fields). */
 lbpf_status lbpf_read_populations(lbpf_ctx* ctx, int32_t field, void* dst);
 lbpf_status lbpf_write_populations(lbpf_ctx* ctx, int32_t field, const void* src);
 
 /* Full populations (deviation + rest equilibrium) of one field in FP64,
- * layout [Q][nz][ny][nx], for inspection.  Allocates a temporary device
- * buffer of Q*nx*ny*nz doubles; synchronises.  Errors as above, ENOMEM. */
+ * layout [Q][nz][ny][nx] (Q as above), for inspection.  Allocates a
+ * temporary device buffer of Q*nx*ny*nz doubles; synchronises.  Errors as above, ENOMEM. */
 lbpf_status lbpf_read_populations_f64(lbpf_ctx* ctx, int32_t field, double* dst);
 
 /* Streaming only (collision = identity) of all three population sets, raw
- * bits, with the wall rules: checks the index mapping.  Asynchronous. */
+ * bits, with the wall rules, each set on its own lattice: checks the index
+ * mapping.  Asynchronous. */
 lbpf_status lbpf_debug_stream_only(lbpf_ctx* ctx, int64_t nsteps);
 
 /* Per-node advective velocity of the heat equation (Sec. 3.1: the theta

@@ -108,3 +108,32 @@ def test_storage_bytes_and_invalid_arguments_without_gpu():
     assert L.lbpf_batch_create(1, grids, params, None, ctypes.byref(h)) == lbpf.LBPF_EINVAL
     assert b"one lattice" in L.lbpf_batch_last_error(None)
     assert not h.value
+
+
+# C names of the binding's fields where they differ ("lambda" is a Python keyword)
+_C_NAME = {"lam": "lambda"}
+
+
+@pytest.mark.parametrize("struct", [lbpf.lbpf_grid, lbpf.lbpf_params, lbpf.lbpf_reductions])
+def test_struct_layout_matches_header(struct, tmp_path):
+    """The binding's ctypes structures have the header's size and the same
+    offset for every field, as the C compiler lays them out."""
+    import subprocess
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    name = struct.__name__
+    lines = ['#include <stddef.h>', '#include <stdio.h>', '#include "lbpf.h"', 'int main(void) {',
+             '    printf("size %%zu\\n", sizeof(%s));' % name]
+    for fname, _ in struct._fields_:
+        c = _C_NAME.get(fname, fname)
+        lines.append('    printf("%s %%zu\\n", offsetof(%s, %s));' % (fname, name, c))
+    lines += ['    return 0;', '}']
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c11", "-I", os.path.join(root, "include"), "-o", str(exe), str(src)],
+                   check=True)
+    got = dict(l.split() for l in subprocess.run([str(exe)], check=True, capture_output=True,
+                                                 text=True).stdout.splitlines())
+    assert int(got["size"]) == ctypes.sizeof(struct)
+    for fname, _ in struct._fields_:
+        assert int(got[fname]) == getattr(struct, fname).offset, fname

@@ -90,7 +90,7 @@ typedef struct {
     int32_t lattice_ut;     /* lattice of U and theta: 0 = that of phi, else an
                                lbpf_lattice.  Each scheme then takes the e^2 of
                                its own lattice (Sec. 4.1 runs phi on D2Q9 and
-                               theta on D2Q5).  Single contexts only. */
+                               theta on D2Q5).  Batches take it per domain. */
 } lbpf_grid;
 
 typedef struct {
@@ -330,11 +330,13 @@ lbpf_status lbpf_bench_copy(void* dst, const void* src, int64_t nbytes, void* hi
 const char* lbpf_last_error(const lbpf_ctx* ctx);
 
 /* ---- Ensembles of independent domains ------------------------------------
- * A batch holds n domains (own grid, lattice D3Q7, D3Q15 or D3Q19, parameters;
+ * A batch holds n domains (own grid, lattices D3Q7, D3Q15 or D3Q19 for phi
+ * and for U, theta (lattice_ut), parameters;
  * one storage type for all) on one stream.  Each domain is an lbpf_ctx
  * reached with lbpf_batch_domain, through which its fields are set and read
  * with the calls above (lbpf_step on it is refused: ESTATE).  lbpf_batch_step
- * advances every domain with one launch per lattice type and kernel: a work
+ * advances every domain with one launch per lattice type and kernel (k_phi
+ * grouped by the phi lattice, k_ut by the U/theta lattice): a work
  * table maps each block to a (domain, tile) pair, ordered so that each XCD
  * receives a contiguous run of tiles; with lbpf_batch_set_graph the loop is
  * replayed from a captured graph.  A domain follows the same arithmetic as

@@ -101,8 +101,10 @@ struct lbpf_batch {
     int storage = LBPF_F32;
     int shape = 3, zslab = 6;
     void* d_desc = nullptr;        // DomainDesc<T>[ndom]
-    int2* d_work[3] = {};          // work tables of the D3Q7, D3Q15 and D3Q19 domains
-    int nwork[3] = {0, 0, 0};
+    // work tables of k_phi [0] and k_ut [1] over the domains whose phi
+    // (resp. U, theta) lattice is D3Q7, D3Q15, D3Q19
+    int2* d_work[2][3] = {};
+    int nwork[2][3] = {};
     bool built = false;
     int graph_steps = 0;
     hipGraphExec_t gexec = nullptr;
@@ -1018,7 +1020,7 @@ template <class T>
 lbpf_status batch_build_t(lbpf_batch* b) {
     const int nd = (int)b->dom.size();
     std::vector<DomainDesc<T>> desc(nd);
-    std::vector<std::vector<int2>> items(3);
+    std::vector<int2> items[2][3];
     for (int d = 0; d < nd; ++d) {
         lbpf_ctx* c = b->dom[d];
         for (int k = 0; k < 2; ++k) {   // one tiling for both batch kernels
@@ -1032,25 +1034,29 @@ lbpf_status batch_build_t(lbpf_batch* b) {
                 desc[d].pop[f][par] = c->pop[f][par];
                 desc[d].fld[f][par] = (T*)c->fld[f][par];
             }
-        const int li = c->q == 7 ? 0 : c->q == 15 ? 1 : 2;
-        const int nt = total_tiles(c, K_PHI);
-        for (int t = 0; t < nt; ++t) items[li].push_back(int2{d, t});
+        const int nt = total_tiles(c, K_PHI);   // both kernels tile alike
+        for (int k = 0; k < 2; ++k) {
+            const int q = k == K_PHI ? c->q : c->q_ut;
+            const int li = q == 7 ? 0 : q == 15 ? 1 : 2;
+            for (int t = 0; t < nt; ++t) items[k][li].push_back(int2{d, t});
+        }
     }
     if (!b->d_desc) BCHK(hipMalloc(&b->d_desc, sizeof(DomainDesc<T>) * nd));
     BCHK(hipMemcpy(b->d_desc, desc.data(), sizeof(DomainDesc<T>) * nd, hipMemcpyHostToDevice));
-    for (int li = 0; li < 3; ++li) {
-        std::vector<int2>& it = items[li];
-        if (b->d_work[li]) { (void)hipFree(b->d_work[li]); b->d_work[li] = nullptr; }
-        b->nwork[li] = 0;
+    for (int kl = 0; kl < 6; ++kl) {
+        const int k = kl / 3, li = kl % 3;
+        std::vector<int2>& it = items[k][li];
+        if (b->d_work[k][li]) { (void)hipFree(b->d_work[k][li]); b->d_work[k][li] = nullptr; }
+        b->nwork[k][li] = 0;
         if (it.empty()) continue;
         while (it.size() % 8) it.push_back(int2{-1, 0});
         // block k*8 + x runs on XCD x: give each XCD a contiguous run of tiles
         const size_t m = it.size() / 8;
         std::vector<int2> w(it.size());
         for (size_t blk = 0; blk < it.size(); ++blk) w[blk] = it[(blk % 8) * m + blk / 8];
-        BCHK(hipMalloc((void**)&b->d_work[li], sizeof(int2) * w.size()));
-        BCHK(hipMemcpy(b->d_work[li], w.data(), sizeof(int2) * w.size(), hipMemcpyHostToDevice));
-        b->nwork[li] = (int)w.size();
+        BCHK(hipMalloc((void**)&b->d_work[k][li], sizeof(int2) * w.size()));
+        BCHK(hipMemcpy(b->d_work[k][li], w.data(), sizeof(int2) * w.size(), hipMemcpyHostToDevice));
+        b->nwork[k][li] = (int)w.size();
     }
     b->built = true;
     return LBPF_OK;
@@ -1058,18 +1064,18 @@ lbpf_status batch_build_t(lbpf_batch* b) {
 
 template <class L, class T, class S, int TX, int TY>
 lbpf_status batch_launch_l(lbpf_batch* b, int li, int par) {
-    if (!b->nwork[li]) return LBPF_OK;
-    hipLaunchKernelGGL((k_phi_batch<L, T, S, TX, TY>), dim3(b->nwork[li]), dim3(TX * TY), 0, b->stream,
-                       (const DomainDesc<T>*)b->d_desc, (const int2*)b->d_work[li], par);
+    if (!b->nwork[K_PHI][li]) return LBPF_OK;
+    hipLaunchKernelGGL((k_phi_batch<L, T, S, TX, TY>), dim3(b->nwork[K_PHI][li]), dim3(TX * TY), 0, b->stream,
+                       (const DomainDesc<T>*)b->d_desc, (const int2*)b->d_work[K_PHI][li], par);
     BCHK(hipGetLastError());
     return LBPF_OK;
 }
 
 template <class L, class T, class S, int TX, int TY>
 lbpf_status batch_launch_u(lbpf_batch* b, int li, int par) {
-    if (!b->nwork[li]) return LBPF_OK;
-    hipLaunchKernelGGL((k_ut_batch<L, T, S, TX, TY>), dim3(b->nwork[li]), dim3(TX * TY), 0, b->stream,
-                       (const DomainDesc<T>*)b->d_desc, (const int2*)b->d_work[li], par);
+    if (!b->nwork[K_UT][li]) return LBPF_OK;
+    hipLaunchKernelGGL((k_ut_batch<L, T, S, TX, TY>), dim3(b->nwork[K_UT][li]), dim3(TX * TY), 0, b->stream,
+                       (const DomainDesc<T>*)b->d_desc, (const int2*)b->d_work[K_UT][li], par);
     BCHK(hipGetLastError());
     return LBPF_OK;
 }
@@ -1115,8 +1121,9 @@ lbpf_status lbpf_batch_create(int32_t n, const lbpf_grid* grids, const lbpf_para
     for (int i = 0; i < n; ++i) {
         if (grids[i].lattice != LBPF_D3Q7 && grids[i].lattice != LBPF_D3Q15 && grids[i].lattice != LBPF_D3Q19)
             return bfail(nullptr, LBPF_EINVAL, "batched domains use D3Q7, D3Q15 or D3Q19");
-        if (grids[i].lattice_ut != 0 && grids[i].lattice_ut != grids[i].lattice)
-            return bfail(nullptr, LBPF_EINVAL, "batched domains run every field on one lattice");
+        if (grids[i].lattice_ut != 0 && grids[i].lattice_ut != LBPF_D3Q7 && grids[i].lattice_ut != LBPF_D3Q15 &&
+            grids[i].lattice_ut != LBPF_D3Q19)
+            return bfail(nullptr, LBPF_EINVAL, "lattice_ut must be 0, 7, 15 or 19");
         if (params[i].vel[0] != 0.0 || params[i].vel[1] != 0.0 || params[i].vel[2] != 0.0)
             return bfail(nullptr, LBPF_EINVAL, "batched domains have no advective velocity");
         if (params[i].skip_U || params[i].skip_theta)
@@ -1147,7 +1154,7 @@ lbpf_status lbpf_batch_create(int32_t n, const lbpf_grid* grids, const lbpf_para
         }
         c->in_batch = true;
         b->dom.push_back(c);
-        if ((size_t)c->q * c->np * c->sbytes >= ((size_t)1 << 32) - 256) {
+        if ((size_t)std::max(c->q, c->q_ut) * c->np * c->sbytes >= ((size_t)1 << 32) - 256) {
             for (lbpf_ctx* d : b->dom) { d->in_batch = false; lbpf_destroy(d); }
             if (b->own_stream) (void)hipStreamDestroy(b->stream);
             delete b;
@@ -1233,8 +1240,9 @@ lbpf_status lbpf_batch_destroy(lbpf_batch* b) {
     (void)hipStreamSynchronize(b->stream);
     if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
     if (b->d_desc) (void)hipFree(b->d_desc);
-    for (int li = 0; li < 3; ++li)
-        if (b->d_work[li]) (void)hipFree(b->d_work[li]);
+    for (int k = 0; k < 2; ++k)
+        for (int li = 0; li < 3; ++li)
+            if (b->d_work[k][li]) (void)hipFree(b->d_work[k][li]);
     for (lbpf_ctx* c : b->dom) {
         c->in_batch = false;
         lbpf_destroy(c);

@@ -323,3 +323,45 @@ def test_separate_lattices_runtime_paths():
     r.step(12)
     for x, y in zip(want, fields(r)):
         assert np.array_equal(x, y), "restored"
+
+
+def _mixed_lattice_batch():
+    """(problem, lattice_ut) pairs: phi and U/theta lattices mixed within and
+    across domains, at dt/tau0 = 0.11 (inside the D3Q7 and D3Q15 windows)."""
+    def r(lat, n, seed, **kw):
+        return dataclasses.replace(ragged(lat, n, seed=seed, **kw), dt=0.11)
+    return [(r(19, (33, 21, 19), 21), 7), (r(15, (40, 17, 24), 22, eps=0.03), 7),
+            (r(7, (29, 29, 13), 23), 19), (r(19, (17, 40, 33), 24, aniso=1, eps=0.0, delta=-0.02), 0),
+            (r(19, (37, 21, 19), 25, U0=-0.45), 15)]
+
+
+def test_batch_separate_lattices_match():
+    """A batch whose domains put U and theta on another lattice than phi:
+    FP64 against the oracle's separate-lattice mode (1e-11), FP32 against
+    the domains stepped alone (1e-6, as for one-lattice batches), with graph
+    replay."""
+    pairs = _mixed_lattice_batch()
+    specs = [dict(lbpf.problem_kwargs(p), lattice_ut=lu) for p, lu in pairs]
+    b = lbpf.Batch(specs, storage="f64")
+    for d, (p, lu) in zip(b.domains, pairs):
+        d.set_fields(*p.initial_fields())
+    b.step(30)
+    for d, (p, lu) in zip(b.domains, pairs):
+        o = Oracle(p.nx, p.ny, p.nz, **dict(p.model_kwargs(), lattice_ut=lu))
+        o.init(*p.initial_fields())
+        o.step(30)
+        for x, y in zip(fields(d), o.fields()):
+            assert maxabs(x, y) <= 1e-11, (p.lattice, lu)
+    b.close()
+    b = lbpf.Batch(specs, storage="f32")
+    for d, (p, lu) in zip(b.domains, pairs):
+        d.set_fields(*p.initial_fields())
+    b.set_graph(6)
+    b.step(25)
+    for d, (p, lu) in zip(b.domains, pairs):
+        s = make_gpu(p, "f32", lattice_ut=lu)
+        s.step(25)
+        for x, y in zip(fields(s), fields(d)):
+            assert maxabs(x, y) <= 1e-6, (p.lattice, lu)
+        s.close()
+    b.close()

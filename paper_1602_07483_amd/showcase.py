@@ -10,6 +10,7 @@ along [110].
 Usage (one GPU):
     python -m paper_1602_07483_amd.showcase --case cubic
     python -m paper_1602_07483_amd.showcase --case k41k61
+    python -m paper_1602_07483_amd.showcase --case cubic --lattice-ut 7   # theta on D3Q7
 
 Prints one progress line per record and a final JSON line with the radii of
 the phi = 0 surface along [100], [110] and [111] (lattice units from the
@@ -67,10 +68,13 @@ def main(argv=None):
     ap.add_argument("--steps", type=int, default=0, help="default: the paper's figure time")
     ap.add_argument("--records", type=int, default=10)
     ap.add_argument("--storage", default="f32")
+    ap.add_argument("--lattice-ut", type=int, default=0, choices=(0, 7, 15, 19),
+                    help="lattice of theta (0: D3Q19, as phi); Sec. 4.1 pairs D2Q9 phi with D2Q5 theta")
     args = ap.parse_args(argv)
     pb = problem(args.case, args.n)
     steps = args.steps or pb.steps
-    s = lbpf.solver_for(pb, storage=args.storage, skip_U=1)   # pure substance: theta only
+    s = lbpf.solver_for(pb, storage=args.storage, skip_U=1,   # pure substance: theta only
+                        lattice_ut=args.lattice_ut)
     s.set_fields(*pb.initial_fields())
     chunk = max(1, steps // args.records)
     done, stepping = 0, 0.0
@@ -88,6 +92,7 @@ def main(argv=None):
                  red["phi_max"], red["nonfinite"]), flush=True)
     s.close()
     out = {"case": args.case, "n": args.n, "steps": steps, "storage": args.storage,
+           "lattice_ut": args.lattice_ut or 19,
            "R100": r[0], "R110": r[1], "R111": r[2], "solid_fraction": red["solid_fraction"],
            "nonfinite": red["nonfinite"], "mlups": float(args.n) ** 3 * steps / stepping / 1e6}
     print(json.dumps(out), flush=True)

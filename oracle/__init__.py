@@ -45,7 +45,7 @@ class FdoParams(ctypes.Structure):
         ("lam", ctypes.c_double), ("Mcinf", ctypes.c_double), ("k", ctypes.c_double),
         ("D", ctypes.c_double), ("kappa", ctypes.c_double),
         ("aniso", ctypes.c_int32), ("eps", ctypes.c_double), ("delta", ctypes.c_double),
-        ("skip_theta", ctypes.c_int32),
+        ("skip_theta", ctypes.c_int32), ("stencil", ctypes.c_int32),
     ]
 
 
@@ -232,17 +232,20 @@ class Oracle:
 class FDOracle:
     """The independent finite-difference discretisation (fd_oracle.c) of the
     same PDEs, explicit Euler with time step dt.  All walls carry zero flux
-    (mirror and no-flux walls coincide for this discretisation)."""
+    (mirror and no-flux walls coincide for this discretisation).  stencil 6
+    or 18: the paper's FD6 and FD18 Laplacians (18: isotropic interface
+    only, eps = 0)."""
 
     def __init__(self, nx, ny, nz, dx=1.0, W0=1.0, tau0=1.0, lam=3.2, Mcinf=1.0, k=0.15,
                  D=2.0, kappa=20.0, aniso=ANISO_CUBIC, eps=0.05, delta=0.0, skip_theta=0,
-                 **_ignored):
+                 stencil=6, **_ignored):
         lib = _load()
         p = FdoParams()
         p.nx, p.ny, p.nz = int(nx), int(ny), int(nz)
         p.dx, p.W0, p.tau0, p.lam, p.Mcinf, p.k = dx, W0, tau0, lam, Mcinf, k
         p.D, p.kappa, p.aniso, p.eps, p.delta = D, kappa, int(aniso), eps, delta
         p.skip_theta = int(skip_theta)
+        p.stencil = int(stencil)
         self.shape = (int(nz), int(ny), int(nx))
         self._h = lib.fdo_create(ctypes.byref(p))
         if not self._h:

@@ -26,6 +26,15 @@
  *    unit normal from the face gradient of the new phi); zeta, q and dphi/dt
  *    use the phase field after the phi update of the same step.
  *  - theta: dtheta/dt = kappa lap theta + dphi/dt / 2.
+ * Two stencils, as the paper's FD6 and FD18 codes in its grid-anisotropy
+ * study (Sec. 4.1, isotropic case):
+ *  - stencil 6 (default): the flux form above; with a_s = 1 its div F and
+ *    the theta Laplacian use the 6 face neighbours;
+ *  - stencil 18: for an isotropic interface only (eps = 0, and delta = 0
+ *    for K41/K61, so that a_s = 1 and the anisotropic flux vanishes), the
+ *    Laplacians of phi and theta use the 6 face and 12 edge neighbours,
+ *    lap f = [2 sum_faces f + sum_edges f - 24 f] / (6 dx^2), whose O(dx^2)
+ *    error does not depend on direction.  U keeps the flux form.
  * Where |grad phi|^2 dx^2 <= 1e-12 the normal is undefined: a_s = 1 and the
  * anisotropic and anti-trapping terms vanish.
  */
@@ -40,6 +49,7 @@ typedef struct {
     int32_t aniso;          /* 0: cubic, 1: K41/K61 */
     double eps, delta;
     int32_t skip_theta;     /* 1: isothermal (Sec. 4.2 benchmark): theta held */
+    int32_t stencil;        /* 0 or 6: face neighbours; 18: faces and edges */
 } fdo_params;
 
 typedef struct {
@@ -115,8 +125,28 @@ static void grad_face(const double* f, int x, int y, int z, int axis, int nx, in
     out[axis] = (f[IDX(x1, y1, z1)] - f[IDX(x, y, z)]) / dx;
 }
 
+/* Laplacian times dx^2 at node (x,y,z) with mirror ghosts: the 6 face
+ * neighbours, or the isotropic form over the 6 face and 12 edge neighbours */
+static double lap_dx2(const double* f, int x, int y, int z, int nx, int ny, int nz, int stencil) {
+    const double f0 = f[IDX(x, y, z)];
+    double faces = 0.0;
+    for (int d = -1; d <= 1; d += 2)
+        faces += f[IDX(clampi(x + d, nx), y, z)] + f[IDX(x, clampi(y + d, ny), z)] +
+                 f[IDX(x, y, clampi(z + d, nz))];
+    if (stencil != 18) return faces - 6.0 * f0;
+    double edges = 0.0;
+    for (int a = -1; a <= 1; a += 2)
+        for (int b = -1; b <= 1; b += 2)
+            edges += f[IDX(clampi(x + a, nx), clampi(y + b, ny), z)] +
+                     f[IDX(clampi(x + a, nx), y, clampi(z + b, nz))] +
+                     f[IDX(x, clampi(y + a, ny), clampi(z + b, nz))];
+    return (2.0 * faces + edges - 24.0 * f0) / 6.0;
+}
+
 fdo_ctx* fdo_create(const fdo_params* p) {
     if (!p || p->nx < 1 || p->ny < 1 || p->nz < 1 || !(p->dx > 0)) return NULL;
+    if (p->stencil != 0 && p->stencil != 6 && p->stencil != 18) return NULL;
+    if (p->stencil == 18 && (p->eps != 0.0 || (p->aniso == 1 && p->delta != 0.0))) return NULL;
     fdo_ctx* c = (fdo_ctx*)calloc(1, sizeof(fdo_ctx));
     if (!c) return NULL;
     c->p = *p;
@@ -182,6 +212,7 @@ void fdo_step(fdo_ctx* c, double dt, int64_t nsteps) {
                                  (c->fy[i] - (y > 0 ? c->fy[IDX(x, y - 1, z)] : 0.0)) +
                                  (c->fz[i] - (z > 0 ? c->fz[IDX(x, y, z - 1)] : 0.0));
                     div /= dx;
+                    if (p->stencil == 18) div = lap_dx2(c->phi, x, y, z, nx, ny, nz, 18) / (dx * dx);
                     double pg[3];
                     grad_node(c->phi, x, y, z, nx, ny, nz, dx, pg);
                     const double a = node_as(p, pg);
@@ -230,12 +261,9 @@ void fdo_step(fdo_ctx* c, double dt, int64_t nsteps) {
                     const double dphi = c->phin[i] - c->phi[i];
                     const double zeta = 0.5 * (1.0 + k) - 0.5 * (1.0 - k) * c->phin[i];
                     c->Un[i] = c->U[i] + (dt * div + 0.5 * (1.0 + (1.0 - k) * c->U[i]) * dphi) / zeta;
-                    /* theta: 7-point Laplacian with mirror ghosts */
+                    /* theta: Laplacian with mirror ghosts */
                     const double t0 = c->th[i];
-                    const double lap =
-                        c->th[IDX(clampi(x + 1, nx), y, z)] + c->th[IDX(clampi(x - 1, nx), y, z)] +
-                        c->th[IDX(x, clampi(y + 1, ny), z)] + c->th[IDX(x, clampi(y - 1, ny), z)] +
-                        c->th[IDX(x, y, clampi(z + 1, nz))] + c->th[IDX(x, y, clampi(z - 1, nz))] - 6.0 * t0;
+                    const double lap = lap_dx2(c->th, x, y, z, nx, ny, nz, p->stencil);
                     c->thn[i] = p->skip_theta ? t0 : t0 + dt * p->kappa * lap / (dx * dx) + 0.5 * dphi;
                 }
         double* t;

@@ -564,3 +564,63 @@ def test_separate_lattices():
     s.stream_only(5)
     for field, q in ((0, 15), (1, 7), (2, 7)):
         assert np.array_equal(np.sort(s.pops(field).ravel()), np.arange(q * 120.0))
+
+
+# ------------------------------------------------ FD6 / FD18 (Sec. 4.1)
+def _fd_heat_step(stencil, shape, modes, dt=0.01):
+    """One FD step of theta alone (phi = -1 is a fixed point with lambda = 0)
+    from the mirror-wall cosine mode of the given mode numbers; returns the
+    initial theta and the per-step rate (theta1 - theta0) / dt."""
+    from oracle import FDOracle
+    nz, ny, nx = shape
+    z, y, x = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    th = (np.cos(np.pi * modes[0] * (x + 0.5) / nx) * np.cos(np.pi * modes[1] * (y + 0.5) / ny)
+          * np.cos(np.pi * modes[2] * (z + 0.5) / nz))
+    o = FDOracle(nx, ny, nz, lam=0.0, Mcinf=0.0, kappa=1.0, eps=0.0, stencil=stencil)
+    o.set(-np.ones(shape), np.zeros(shape), th)
+    o.step(dt, 1)
+    phi, _, th1 = o.fields()
+    assert np.array_equal(phi, -np.ones(shape))
+    return th, (th1 - th) / dt
+
+
+@pytest.mark.parametrize("stencil", [6, 18])
+def test_fd_stencils_act_on_mirror_modes_as_their_symbols(stencil):
+    """The mirror-wall cosine modes are eigenvectors of both Laplacians; with
+    c_a = cos(k_a dx), the face stencil has the symbol 2 sum c_a - 6 and the
+    face + edge stencil [4 sum c_a + 4 sum_{a<b} c_a c_b - 24] / 6 (dx = 1).
+    A mixed mode (1, 2, 3) weighs every face and edge neighbour differently."""
+    shape, modes = (8, 10, 12), (1, 2, 3)
+    c = [np.cos(np.pi * m / n) for m, n in zip(modes, shape[::-1])]
+    if stencil == 6:
+        sym = 2 * sum(c) - 6
+    else:
+        sym = (4 * sum(c) + 4 * (c[0] * c[1] + c[0] * c[2] + c[1] * c[2]) - 24) / 6
+    th, rate = _fd_heat_step(stencil, shape, modes)
+    assert np.max(np.abs(rate - sym * th)) < 1e-12
+
+
+def test_fd18_error_is_isotropic_fd6_is_not():
+    """Leading truncation error of the two Laplacians, c = (symbol + k^2) / k^4:
+    the face + edge stencil has c = 1/12 along [100] and [110] alike (its
+    O(dx^2) error is (dx^2/12) lap^2, isotropic), the face stencil 1/12
+    along [100] but 1/24 along [110] -- the grid anisotropy FD18 removes."""
+    n = 64
+    c = {}
+    for st in (6, 18):
+        for name, shape, modes in (("100", (1, 1, n), (4, 0, 0)), ("110", (1, n, n), (4, 4, 0))):
+            th, rate = _fd_heat_step(st, shape, modes)
+            m = np.abs(th) > 1e-3
+            lam = np.mean(rate[m] / th[m])
+            k2 = sum((np.pi * q / n) ** 2 for q in modes)
+            c[st, name] = (lam + k2) / k2 ** 2
+    assert abs(c[6, "100"] - 1 / 12) < 2e-3 and abs(c[6, "110"] - 1 / 24) < 2e-3
+    assert abs(c[18, "100"] - 1 / 12) < 2e-3 and abs(c[18, "110"] - 1 / 12) < 2e-3
+
+
+def test_fd18_refuses_anisotropic_interfaces():
+    from oracle import FDOracle
+    with pytest.raises(ValueError):
+        FDOracle(8, 8, 8, eps=0.05, stencil=18)
+    with pytest.raises(ValueError):
+        FDOracle(8, 8, 8, eps=0.0, stencil=9)

@@ -323,6 +323,14 @@ def test_grid_anisotropy_of_isotropic_growth():
         print("phi D3Q%d theta D3Q%d: R100 %.3f R110 %.3f A_g %.3f %%" % (lat, lat_t, r100, r110, ag[key]))
     assert ag[7] > 1.0
     assert ag[15] < 0.5 and ag[19] < 0.5
+    # the FD oracle's FD6 and FD18 runs of the same setup (written by
+    # tests/golden/make_fd_anisotropy.py), which the paper sets beside its lattices
+    for st in (6, 18):
+        path = os.path.join(GOLDEN, "fd_anisotropy_%d.json" % st)
+        if os.path.exists(path):
+            with open(path) as fh:
+                g = json.load(fh)
+            print("FD%d (oracle): R100 %.3f R110 %.3f A_g %.3f %%" % (st, g["R100"], g["R110"], g["A_g_percent"]))
 
 
 def _last_crossing(prof):

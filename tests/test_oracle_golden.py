@@ -103,3 +103,31 @@ def test_lb_oracle_matches_finite_differences(name):
     assert gap <= 1.0
     assert abs(vlb - vfd) / abs(vfd) < 0.04
     assert max(abs(r["lb_solid"] - r["fd_solid"]) for r in tr) < 0.02
+
+
+def _fd_anisotropy(stencil):
+    path = os.path.join(GOLDEN, "fd_anisotropy_%d.json" % stencil)
+    if not os.path.exists(path):
+        pytest.skip("FD%d grid-anisotropy run not generated" % stencil)
+    with open(path) as fh:
+        return json.load(fh)
+
+
+def _fd_anisotropy_script():
+    import importlib.util
+    spec = importlib.util.spec_from_file_location("make_fd_anisotropy",
+                                                  os.path.join(GOLDEN, "make_fd_anisotropy.py"))
+    mod = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mod)
+    return mod
+
+
+@pytest.mark.parametrize("stencil", [6, 18])
+def test_fd_anisotropy_run_start_reproduces(stencil):
+    """The stored FD6/FD18 isotropic-growth runs are what the current FD
+    oracle computes: the sums of phi and theta after their first 100 steps."""
+    g = _fd_anisotropy(stencil)
+    mod = _fd_anisotropy_script()
+    s_phi, s_th = mod.check_sums(stencil, mod.problem())
+    assert abs(s_phi - g["check_sum_phi"]) <= 1e-12 * abs(g["check_sum_phi"])
+    assert abs(s_th - g["check_sum_theta"]) <= 1e-12 * abs(g["check_sum_theta"])

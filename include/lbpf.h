@@ -13,7 +13,8 @@
  *                            eq. (Feq_Transport), relaxation eq. (RelaxationTime_Concentration);
  *   temperature theta     -- Sec. 3.1, BGK scheme eq. (LBE_Eq_Temp) with
  *                            eqs. (EqFunction_Tempr), (Source_Tempr), (ThermalDiffusivity);
- * on the D3Q7, D3Q15 or D3Q19 lattice (Sec. 3.4, Tables 1 and 2), in the order of
+ * on the D3Q7, D3Q15 or D3Q19 lattice (Sec. 3.4, Tables 1 and 2) -- U and theta
+ * optionally on another one than phi (lbpf_grid.lattice_ut) -- in the order of
  * Sec. 3.4 "Algorithm implementation": phi first, then U and theta with the
  * new phi; split collision (eq. Collision_Stage) and streaming
  * (eq. Deplacement_STD); bounce-back walls.

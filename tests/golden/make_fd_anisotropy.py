@@ -9,8 +9,13 @@ Calls only the oracle and the seeded input generators.
 The setup is the lattice-unit form of that study: eps = 0, dx = W0, dt = 0.15
 tau0, kappa dt/dx^2 = 0.105, lambda = 10, pure substance (M c_inf = 0), a
 sphere of radius 8 at the mirror corner of a 150^3 octant (the 300^3 domain
-about its centre), 10^4 steps; the undercooling is not printed in the paper
-and Delta = 0.2 is taken.  Each stencil writes fd_anisotropy_<stencil>.json:
+about its centre), to t = 1500 tau0; the undercooling is not printed in
+the paper and Delta = 0.2 is taken.  FD18 runs at the LB time step, dt =
+0.15 tau0 (10^4 steps).  FD6 cannot: with explicit Euler its checkerboard
+mode is amplified by 1 - (12 W0^2/dx^2 + 2) dt/tau0 per step (the 7-point
+Laplacian's largest eigenvalue 12/dx^2 plus the linearised double well at
+phi = -1), -1.1 at dt = 0.15 tau0, so it diverges; it runs at dt = 0.1 tau0
+(15 000 steps).  Each stencil writes fd_anisotropy_<stencil>.json:
 the radii of the phi = 0 surface along [100] and [110] from the mirror
 point, A_g = |R100 - R110| / (R100 + R110), and the sums of phi and theta
 after the first 100 steps (for a short reproduction test).
@@ -28,14 +33,16 @@ import numpy as np  # noqa: E402
 import oracle  # noqa: E402
 from paper_1602_07483_amd.inputs import Problem, NOFLUX, SYMMETRY  # noqa: E402
 
-N, STEPS, DT, CHECK_STEPS = 150, 10000, 0.15, 100
+N, T_END, CHECK_STEPS = 150, 1500.0, 100
+DT = {6: 0.1, 18: 0.15}     # time step per stencil, in units of tau0
 
 
-def problem(n=N):
+def problem(n=N, dt=0.15):
     walls = (SYMMETRY, NOFLUX, SYMMETRY, NOFLUX, SYMMETRY, NOFLUX)
-    return Problem("isotropic", n, n, n, 19, walls, dx=1.0, dt=DT, W0=1.0, tau0=1.0, lam=10.0,
-                   Mcinf=0.0, k=0.15, D=0.7, kappa=0.7, eps=0.0, centres=[(-0.5, -0.5, -0.5)],
-                   radius=8.0, U0=0.0, theta0=-0.2, steps=STEPS)
+    return Problem("isotropic", n, n, n, 19, walls, dx=1.0, dt=dt, W0=1.0, tau0=1.0, lam=10.0,
+                   Mcinf=0.0, k=0.15, D=0.7, kappa=0.7, eps=0.0,
+                   centres=[(-0.5, -0.5, -0.5)], radius=8.0, U0=0.0, theta0=-0.2,
+                   steps=int(round(T_END / dt)))
 
 
 def first_crossing(prof):
@@ -50,7 +57,8 @@ def fd_solver(stencil, pb):
     return fd
 
 
-def check_sums(stencil, pb):
+def check_sums(stencil):
+    pb = problem(dt=DT[stencil])
     fd = fd_solver(stencil, pb)
     fd.step(pb.dt, CHECK_STEPS)
     phi, _, th = fd.fields()
@@ -58,12 +66,12 @@ def check_sums(stencil, pb):
 
 
 def run(stencil):
-    pb = problem()
-    sums = check_sums(stencil, pb)
+    pb = problem(dt=DT[stencil])
+    sums = check_sums(stencil)
     fd = fd_solver(stencil, pb)
     t0 = time.time()
     done = 0
-    while done < STEPS:
+    while done < pb.steps:
         fd.step(pb.dt, 1000)
         done += 1000
         print("FD%d step %d (%.0f s)" % (stencil, done, time.time() - t0), flush=True)
@@ -71,7 +79,7 @@ def run(stencil):
     n = pb.nx
     r100 = first_crossing(phi[0, 0, :]) + 0.5
     r110 = (first_crossing(np.array([phi[0, i, i] for i in range(n)])) + 0.5) * np.sqrt(2.0)
-    out = {"stencil": stencil, "n": n, "steps": STEPS, "dt": DT, "R100": r100, "R110": r110,
+    out = {"stencil": stencil, "n": n, "steps": pb.steps, "dt": pb.dt, "R100": r100, "R110": r110,
            "A_g_percent": abs(r100 - r110) / (r100 + r110) * 100.0,
            "check_steps": CHECK_STEPS, "check_sum_phi": sums[0], "check_sum_theta": sums[1]}
     with open(os.path.join(HERE, "fd_anisotropy_%d.json" % stencil), "w") as f:

@@ -127,7 +127,26 @@ def test_fd_anisotropy_run_start_reproduces(stencil):
     """The stored FD6/FD18 isotropic-growth runs are what the current FD
     oracle computes: the sums of phi and theta after their first 100 steps."""
     g = _fd_anisotropy(stencil)
+    assert g["dt"] == _fd_anisotropy_script().DT[stencil]
     mod = _fd_anisotropy_script()
-    s_phi, s_th = mod.check_sums(stencil, mod.problem())
+    s_phi, s_th = mod.check_sums(stencil)
     assert abs(s_phi - g["check_sum_phi"]) <= 1e-12 * abs(g["check_sum_phi"])
     assert abs(s_th - g["check_sum_theta"]) <= 1e-12 * abs(g["check_sum_theta"])
+
+
+def test_fd6_explicit_step_diverges_at_the_lb_time_step():
+    """The FD6 checkerboard mode grows by 1 - (12 W0^2/dx^2 + 2) dt/tau0 per
+    explicit step about phi = -1: -1.1 at dt = 0.15 tau0 (divergence) and
+    -0.4 at 0.1 tau0.  A small uniform liquid with a checkerboard ripple
+    shows both (mirror walls lower the largest eigenvalue of the 8^3 box to
+    3 * 2(1 + cos(pi/8)) = 11.5, so the factor there is -1.03 at 0.15)."""
+    from oracle import FDOracle
+    n = 8
+    z, y, x = np.meshgrid(np.arange(n), np.arange(n), np.arange(n), indexing="ij")
+    ripple = 1e-6 * (-1.0) ** (x + y + z)
+    for dt, grows in ((0.15, True), (0.1, False)):
+        o = FDOracle(n, n, n, lam=10.0, Mcinf=0.0, D=0.7, kappa=0.7, eps=0.0, stencil=6)
+        o.set(-1.0 + ripple, np.zeros((n, n, n)), np.full((n, n, n), -0.2))
+        o.step(dt, 200)
+        amp = np.max(np.abs(o.fields()[0] + 1.0))
+        assert (amp > 1e-5) == grows, (dt, amp)

@@ -303,7 +303,7 @@ def test_grid_anisotropy_of_isotropic_growth():
     from paper_1602_07483_amd.inputs import Problem, NOFLUX, SYMMETRY
     n = 150
     walls = (SYMMETRY, NOFLUX, SYMMETRY, NOFLUX, SYMMETRY, NOFLUX)
-    ag = {}
+    ag, radii = {}, {}
     # (phi lattice, theta lattice); the last runs phi on D3Q19 and theta on
     # D3Q7, as Sec. 4.1 runs D2Q9 with D2Q5 in 2D: reported only
     for lat, lat_t in ((7, 7), (15, 15), (19, 19), (19, 7)):
@@ -319,6 +319,7 @@ def test_grid_anisotropy_of_isotropic_growth():
         r110 = (_first_crossing(np.array([phi[0, i, i] for i in range(n)])) + 0.5) * np.sqrt(2.0)
         assert 20.0 < r100 < 0.7 * n
         key = lat if lat == lat_t else (lat, lat_t)
+        radii[key] = (r100, r110)
         ag[key] = abs(r100 - r110) / (r100 + r110) * 100.0
         print("phi D3Q%d theta D3Q%d: R100 %.3f R110 %.3f A_g %.3f %%" % (lat, lat_t, r100, r110, ag[key]))
     assert ag[7] > 1.0
@@ -331,6 +332,10 @@ def test_grid_anisotropy_of_isotropic_growth():
             with open(path) as fh:
                 g = json.load(fh)
             print("FD%d (oracle): R100 %.3f R110 %.3f A_g %.3f %%" % (st, g["R100"], g["R110"], g["A_g_percent"]))
+            if st == 18:
+                # the paper finds the LB-D3Q19 and FD18 circles to coincide
+                assert abs(radii[19][0] - g["R100"]) < 0.02 * g["R100"]
+                assert abs(radii[19][1] - g["R110"]) < 0.02 * g["R110"]
 
 
 def _last_crossing(prof):

@@ -4,7 +4,7 @@ paper sets beside its LB lattices in the isotropic-growth study of Sec. 4.1.
 
 Calls only the oracle and the seeded input generators.
 
-    python tests/golden/make_fd_anisotropy.py [6] [18]
+    python tests/golden/make_fd_anisotropy.py [6] [18] [--n N]
 
 The setup is the lattice-unit form of that study: eps = 0, dx = W0, dt = 0.15
 tau0, kappa dt/dx^2 = 0.105, lambda = 10, pure substance (M c_inf = 0), a
@@ -57,17 +57,21 @@ def fd_solver(stencil, pb):
     return fd
 
 
-def check_sums(stencil):
-    pb = problem(dt=DT[stencil])
+def check_sums(stencil, n=N):
+    pb = problem(n, dt=DT[stencil])
     fd = fd_solver(stencil, pb)
     fd.step(pb.dt, CHECK_STEPS)
     phi, _, th = fd.fields()
     return float(phi.sum()), float(th.sum())
 
 
-def run(stencil):
-    pb = problem(dt=DT[stencil])
-    sums = check_sums(stencil)
+def out_name(stencil, n=N):
+    return "fd_anisotropy_%d.json" % stencil if n == N else "fd_anisotropy_%d_n%d.json" % (stencil, n)
+
+
+def run(stencil, n=N):
+    pb = problem(n, dt=DT[stencil])
+    sums = check_sums(stencil, n)
     fd = fd_solver(stencil, pb)
     t0 = time.time()
     done = 0
@@ -82,11 +86,17 @@ def run(stencil):
     out = {"stencil": stencil, "n": n, "steps": pb.steps, "dt": pb.dt, "R100": r100, "R110": r110,
            "A_g_percent": abs(r100 - r110) / (r100 + r110) * 100.0,
            "check_steps": CHECK_STEPS, "check_sum_phi": sums[0], "check_sum_theta": sums[1]}
-    with open(os.path.join(HERE, "fd_anisotropy_%d.json" % stencil), "w") as f:
+    with open(os.path.join(HERE, out_name(stencil, n)), "w") as f:
         json.dump(out, f, indent=1)
     print(json.dumps(out), flush=True)
 
 
 if __name__ == "__main__":
-    for s in sys.argv[1:] or ["6", "18"]:
-        run(int(s))
+    args = sys.argv[1:]
+    n = N
+    if "--n" in args:
+        i = args.index("--n")
+        n = int(args[i + 1])
+        del args[i:i + 2]
+    for s in args or ["6", "18"]:
+        run(int(s), n)

@@ -35,7 +35,15 @@ class OrcParams(ctypes.Structure):
         ("vel", ctypes.c_double * 3),
         ("skip_theta", ctypes.c_int32),
         ("lattice_ut", ctypes.c_int32),
+        ("skip_U", ctypes.c_int32),
+        ("grad_stencil", ctypes.c_int32),
     ]
+
+
+class OrcParamsF32(ctypes.Structure):
+    """orc_params of the single-precision build (every double is a float)."""
+    _fields_ = [(n, ctypes.c_float if t is ctypes.c_double else
+                 (ctypes.c_float * 3 if n == "vel" else t)) for n, t in OrcParams._fields_]
 
 
 class FdoParams(ctypes.Structure):
@@ -46,10 +54,34 @@ class FdoParams(ctypes.Structure):
         ("D", ctypes.c_double), ("kappa", ctypes.c_double),
         ("aniso", ctypes.c_int32), ("eps", ctypes.c_double), ("delta", ctypes.c_double),
         ("skip_theta", ctypes.c_int32), ("stencil", ctypes.c_int32),
+        ("skip_U", ctypes.c_int32),
     ]
 
 
 _lib = None
+_lib_f32 = None
+
+
+def _load_f32():
+    """The single-precision build of the LB oracle (liblbpf_oracle_f32.so)."""
+    global _lib_f32
+    if _lib_f32 is not None:
+        return _lib_f32
+    path = os.path.join(_HERE, "liblbpf_oracle_f32.so")
+    if not os.path.exists(path):
+        from . import build as _b
+        _b.build()
+    lib = ctypes.CDLL(path)
+    P = ctypes.POINTER
+    fp = P(ctypes.c_float)
+    lib.orc_create.restype = ctypes.c_void_p
+    lib.orc_create.argtypes = [P(OrcParamsF32)]
+    lib.orc_destroy.argtypes = [ctypes.c_void_p]
+    lib.orc_init.argtypes = [ctypes.c_void_p, fp, fp, fp]
+    lib.orc_step.argtypes = [ctypes.c_void_p, ctypes.c_int64]
+    lib.orc_fields.argtypes = [ctypes.c_void_p, fp, fp, fp]
+    _lib_f32 = lib
+    return lib
 
 
 def _load():
@@ -150,7 +182,7 @@ class Oracle:
     def __init__(self, nx, ny, nz, lattice=19, walls=(0,) * 6, dx=1.0, dt=1.0,
                  W0=1.0, tau0=1.0, lam=3.2, Mcinf=1.0, k=0.15, D=2.0, kappa=20.0,
                  aniso=ANISO_CUBIC, eps=0.05, delta=0.0, vel=(0.0, 0.0, 0.0), skip_theta=0,
-                 lattice_ut=0):
+                 lattice_ut=0, skip_U=0, grad_stencil=0):
         lib = _load()
         p = OrcParams()
         p.nx, p.ny, p.nz = int(nx), int(ny), int(nz)
@@ -164,6 +196,8 @@ class Oracle:
             p.vel[a] = float(vel[a])
         p.skip_theta = int(skip_theta)
         p.lattice_ut = int(lattice_ut)
+        p.skip_U = int(skip_U)
+        p.grad_stencil = int(grad_stencil)
         self.params = p
         self.shape = (int(nz), int(ny), int(nx))
         self.q = int(lattice)
@@ -233,12 +267,15 @@ class FDOracle:
     """The independent finite-difference discretisation (fd_oracle.c) of the
     same PDEs, explicit Euler with time step dt.  All walls carry zero flux
     (mirror and no-flux walls coincide for this discretisation).  stencil 6
-    or 18: the paper's FD6 and FD18 Laplacians (18: isotropic interface
-    only, eps = 0)."""
+    or 18: the paper's FD6 and FD18 Laplacians of the phase-field equation
+    (18: isotropic interface only, eps = 0).  skip_U: pure substance, U held.
+    It has no advection: a nonzero vel is an error."""
 
     def __init__(self, nx, ny, nz, dx=1.0, W0=1.0, tau0=1.0, lam=3.2, Mcinf=1.0, k=0.15,
                  D=2.0, kappa=20.0, aniso=ANISO_CUBIC, eps=0.05, delta=0.0, skip_theta=0,
-                 stencil=6, **_ignored):
+                 stencil=6, skip_U=0, vel=(0.0, 0.0, 0.0), **_ignored):
+        if any(float(v) != 0.0 for v in vel):
+            raise ValueError("the finite-difference oracle has no advection (vel must be 0)")
         lib = _load()
         p = FdoParams()
         p.nx, p.ny, p.nz = int(nx), int(ny), int(nz)
@@ -246,6 +283,7 @@ class FDOracle:
         p.D, p.kappa, p.aniso, p.eps, p.delta = D, kappa, int(aniso), eps, delta
         p.skip_theta = int(skip_theta)
         p.stencil = int(stencil)
+        p.skip_U = int(skip_U)
         self.shape = (int(nz), int(ny), int(nx))
         self._h = lib.fdo_create(ctypes.byref(p))
         if not self._h:
@@ -274,3 +312,59 @@ class FDOracle:
         out = [np.zeros(self.shape) for _ in range(3)]
         self._lib.fdo_get(self._h, _dptr(out[0]), _dptr(out[1]), _dptr(out[2]))
         return out
+
+
+class OracleF32:
+    """The LB oracle's algorithm with every double replaced by float (the
+    single-precision build of the same source): test evidence of the error
+    that FP32 state and arithmetic alone give the method after n steps, used
+    to bound FP32 parity where the growing interface amplifies rounding.  It
+    is compared with the FP64 oracle, never used as a reference."""
+
+    def __init__(self, nx, ny, nz, lattice=19, walls=(0,) * 6, dx=1.0, dt=1.0,
+                 W0=1.0, tau0=1.0, lam=3.2, Mcinf=1.0, k=0.15, D=2.0, kappa=20.0,
+                 aniso=ANISO_CUBIC, eps=0.05, delta=0.0, vel=(0.0, 0.0, 0.0), skip_theta=0,
+                 lattice_ut=0, skip_U=0, grad_stencil=0):
+        lib = _load_f32()
+        p = OrcParamsF32()
+        p.nx, p.ny, p.nz = int(nx), int(ny), int(nz)
+        p.lattice = int(lattice)
+        for i, wv in enumerate(walls):
+            p.wall[i] = int(wv)
+        p.dx, p.dt, p.W0, p.tau0 = dx, dt, W0, tau0
+        p.lam, p.Mcinf, p.k, p.D, p.kappa = lam, Mcinf, k, D, kappa
+        p.aniso, p.eps, p.delta = int(aniso), eps, delta
+        for a in range(3):
+            p.vel[a] = float(vel[a])
+        p.skip_theta, p.lattice_ut = int(skip_theta), int(lattice_ut)
+        p.skip_U, p.grad_stencil = int(skip_U), int(grad_stencil)
+        self.shape = (int(nz), int(ny), int(nx))
+        self._h = lib.orc_create(ctypes.byref(p))
+        if not self._h:
+            raise ValueError("oracle rejected the parameters")
+        self._lib = lib
+
+    def close(self):
+        if self._h:
+            self._lib.orc_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def init(self, phi, U, theta):
+        a = [np.ascontiguousarray(v, dtype=np.float32).reshape(self.shape) for v in (phi, U, theta)]
+        fp = ctypes.POINTER(ctypes.c_float)
+        self._lib.orc_init(self._h, *[x.ctypes.data_as(fp) for x in a])
+
+    def step(self, n=1):
+        self._lib.orc_step(self._h, int(n))
+
+    def fields(self):
+        out = [np.zeros(self.shape, dtype=np.float32) for _ in range(3)]
+        fp = ctypes.POINTER(ctypes.c_float)
+        self._lib.orc_fields(self._h, *[x.ctypes.data_as(fp) for x in out])
+        return [x.astype(np.float64) for x in out]

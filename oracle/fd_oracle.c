@@ -25,16 +25,20 @@
  *    with q and j_at on faces (q averaged, [1+(1-k)U] dphi/dt averaged, the
  *    unit normal from the face gradient of the new phi); zeta, q and dphi/dt
  *    use the phase field after the phi update of the same step.
- *  - theta: dtheta/dt = kappa lap theta + dphi/dt / 2.
- * Two stencils, as the paper's FD6 and FD18 codes in its grid-anisotropy
- * study (Sec. 4.1, isotropic case):
- *  - stencil 6 (default): the flux form above; with a_s = 1 its div F and
- *    the theta Laplacian use the 6 face neighbours;
+ *  - theta: dtheta/dt = kappa lap theta + dphi/dt / 2, lap over the 6 face
+ *    neighbours.
+ * Two stencils for the Laplacian of the phase-field equation, as the paper's
+ * FD6 and FD18 codes in its grid-anisotropy study (Sec. 4.1, isotropic case,
+ * which names the stencil of that equation only):
+ *  - stencil 6 (default): the flux form above; with a_s = 1 its div F uses
+ *    the 6 face neighbours;
  *  - stencil 18: for an isotropic interface only (eps = 0, and delta = 0
  *    for K41/K61, so that a_s = 1 and the anisotropic flux vanishes), the
- *    Laplacians of phi and theta use the 6 face and 12 edge neighbours,
+ *    phi Laplacian uses the 6 face and 12 edge neighbours,
  *    lap f = [2 sum_faces f + sum_edges f - 24 f] / (6 dx^2), whose O(dx^2)
- *    error does not depend on direction.  U keeps the flux form.
+ *    error does not depend on direction.  theta and U keep their face forms.
+ * skip_U (pure substances, M c_inf = 0, where U does not act on phi or
+ * theta): U is held at its initial value and its equation is not solved.
  * Where |grad phi|^2 dx^2 <= 1e-12 the normal is undefined: a_s = 1 and the
  * anisotropic and anti-trapping terms vanish.
  */
@@ -49,7 +53,8 @@ typedef struct {
     int32_t aniso;          /* 0: cubic, 1: K41/K61 */
     double eps, delta;
     int32_t skip_theta;     /* 1: isothermal (Sec. 4.2 benchmark): theta held */
-    int32_t stencil;        /* 0 or 6: face neighbours; 18: faces and edges */
+    int32_t stencil;        /* phi Laplacian: 0 or 6 face neighbours; 18: faces and edges */
+    int32_t skip_U;         /* 1: pure substance (M c_inf = 0): U held */
 } fdo_params;
 
 typedef struct {
@@ -143,6 +148,8 @@ static double lap_dx2(const double* f, int x, int y, int z, int nx, int ny, int 
     return (2.0 * faces + edges - 24.0 * f0) / 6.0;
 }
 
+void fdo_destroy(fdo_ctx* c);
+
 fdo_ctx* fdo_create(const fdo_params* p) {
     if (!p || p->nx < 1 || p->ny < 1 || p->nz < 1 || !(p->dx > 0)) return NULL;
     if (p->stencil != 0 && p->stencil != 6 && p->stencil != 18) return NULL;
@@ -154,7 +161,10 @@ fdo_ctx* fdo_create(const fdo_params* p) {
     double** arrs[] = {&c->phi, &c->U, &c->th, &c->phin, &c->Un, &c->thn, &c->fx, &c->fy, &c->fz};
     for (size_t i = 0; i < sizeof(arrs) / sizeof(arrs[0]); ++i) {
         *arrs[i] = (double*)calloc(c->n, sizeof(double));
-        if (!*arrs[i]) return NULL;
+        if (!*arrs[i]) {
+            fdo_destroy(c);   /* frees the arrays already allocated (the rest are NULL) */
+            return NULL;
+        }
     }
     return c;
 }
@@ -223,7 +233,7 @@ void fdo_step(fdo_ctx* c, double dt, int64_t nsteps) {
                     c->phin[i] = ph + dt * rhs / (p->tau0 * a * a);
                 }
         /* U: face fluxes with the new phi */
-        for (int axis = 0; axis < 3; ++axis) {
+        for (int axis = 0; axis < 3 && !p->skip_U; ++axis) {
             const int lim[3] = {nx - 1, ny - 1, nz - 1};
 #pragma omp parallel for collapse(2) schedule(static)
             for (int z = 0; z < nz; ++z)
@@ -260,10 +270,11 @@ void fdo_step(fdo_ctx* c, double dt, int64_t nsteps) {
                     div /= dx;
                     const double dphi = c->phin[i] - c->phi[i];
                     const double zeta = 0.5 * (1.0 + k) - 0.5 * (1.0 - k) * c->phin[i];
-                    c->Un[i] = c->U[i] + (dt * div + 0.5 * (1.0 + (1.0 - k) * c->U[i]) * dphi) / zeta;
-                    /* theta: Laplacian with mirror ghosts */
+                    c->Un[i] = p->skip_U ? c->U[i]
+                                         : c->U[i] + (dt * div + 0.5 * (1.0 + (1.0 - k) * c->U[i]) * dphi) / zeta;
+                    /* theta: face Laplacian with mirror ghosts */
                     const double t0 = c->th[i];
-                    const double lap = lap_dx2(c->th, x, y, z, nx, ny, nz, p->stencil);
+                    const double lap = lap_dx2(c->th, x, y, z, nx, ny, nz, 6);
                     c->thn[i] = p->skip_theta ? t0 : t0 + dt * p->kappa * lap / (dx * dx) + 0.5 * dphi;
                 }
         double* t;

@@ -45,6 +45,10 @@
  *  R21 Isothermal runs (the alloy benchmark of Sec. 4.2 sets theta = 0):
  *      with skip_theta the heat equation is not solved and theta keeps its
  *      initial value everywhere.
+ *  R23 Options for studies, off by default: skip_U holds U (pure
+ *      substances, M c_inf = 0, where U acts on nothing); grad_stencil = 1
+ *      takes the gradients of phi from the isotropic lattice form
+ *      (e^2 dx)^-1 sum_i w_i e_i phi(x + e_i) instead of R5.
  *  R22 Separate lattices (lattice_ut): the U and theta schemes may run on
  *      another lattice than the phase field, as the 2D validation of Sec.
  *      4.1 uses D2Q9 for phi and D2Q5 for theta; each scheme takes the e^2,
@@ -278,6 +282,24 @@ static void grad(const orc_ctx* c, const double* f, int x, int y, int z, double 
     g[2] = (fget(c, f, x, y, z+1) - fget(c, f, x, y, z-1)) * h;
 }
 
+/* Gradient of phi: R5, or with grad_stencil = 1 the isotropic lattice form
+ * (e^2 dx)^-1 sum_i w_i e_i phi(x + e_i) over the phase field's lattice,
+ * with the same mirror ghosts. */
+static void grad_phi(const orc_ctx* c, const double* f, int x, int y, int z, double g[3])
+{
+    if (c->p.grad_stencil != 1) {
+        grad(c, f, x, y, z, g);
+        return;
+    }
+    const orc_lat* L = &c->lg;
+    g[0] = g[1] = g[2] = 0.0;
+    for (int i = 1; i < L->q; ++i) {
+        const double v = L->w[i] * fget(c, f, x + L->e[i][0], y + L->e[i][1], z + L->e[i][2]);
+        for (int al = 0; al < 3; ++al) g[al] += v * L->e[i][al];
+    }
+    for (int al = 0; al < 3; ++al) g[al] /= L->e2 * c->p.dx;
+}
+
 /* ------------------------------------------------------------------------- */
 /* Creation                                                                   */
 /* ------------------------------------------------------------------------- */
@@ -303,6 +325,7 @@ orc_ctx* orc_create(const orc_params* p)
         return NULL;
     if (!(p->dx > 0) || !(p->dt > 0) || !(p->tau0 > 0) || !(p->W0 > 0)) return NULL;
     if (!(p->k > 0 && p->k < 1)) return NULL;
+    if (p->grad_stencil != 0 && p->grad_stencil != 1) return NULL;
     c = (orc_ctx*)calloc(1, sizeof(orc_ctx));
     if (!c) return NULL;
     c->p = *p;
@@ -412,7 +435,7 @@ static void phi_terms(orc_ctx* c, const double* phi, const double* U, const doub
     for (int x = 0; x < p->nx; ++x) {
         const size_t s = nidx(c, x, y, z);
         double g[3], a = 1.0, N[3] = {0.0, 0.0, 0.0};
-        grad(c, phi, x, y, z, g);
+        grad_phi(c, phi, x, y, z, g);
         if ((g[0]*g[0] + g[1]*g[1] + g[2]*g[2]) * p->dx * p->dx > SMIN)
             orc_anisotropy(p->aniso, p->eps, p->delta, g, &a, N);
         c->as2[s] = a * a;
@@ -505,7 +528,7 @@ static void ut_terms(orc_ctx* c, const double* phin, const double* phio,
         double divq = 0.0;
         grad(c, c->r, x, y, z, G);
         grad(c, c->wz, x, y, z, F);
-        grad(c, phin, x, y, z, pg);
+        grad_phi(c, phin, x, y, z, pg);
         {
             const double s2 = pg[0]*pg[0] + pg[1]*pg[1] + pg[2]*pg[2];
             if (s2 * p->dx * p->dx > SMIN) {
@@ -591,7 +614,7 @@ static void ut_collide(orc_ctx* c)
             const double heq = L->A[i]*u + L->B[i]*(c->r[s]*u + eJ * p->dt / (L->e2 * p->dx));
             const double feq = theta_eq(c, i, (size_t)s, t);
             const double hi = c->pop[1][o], fi = c->pop[2][o];
-            c->star[1][o] = hi - (hi - heq) / etaU + L->w[i] * c->srcU[s] * p->dt;
+            if (!p->skip_U) c->star[1][o] = hi - (hi - heq) / etaU + L->w[i] * c->srcU[s] * p->dt;
             c->star[2][o] = fi - (fi - feq) / etaT + L->w[i] * c->Qth[s] * p->dt;
         }
     }
@@ -638,8 +661,10 @@ int orc_step(orc_ctx* c, int64_t nsteps)
         /* 2. supersaturation and temperature with the new phase field */
         ut_terms(c, c->phi, c->phi_old, c->U, c->th);
         ut_collide(c);
-        stream(c, &c->lt, c->star[1], c->pop[1]);
-        moment0(c, &c->lt, c->pop[1], c->U);
+        if (!c->p.skip_U) {       /* pure substances hold U */
+            stream(c, &c->lt, c->star[1], c->pop[1]);
+            moment0(c, &c->lt, c->pop[1], c->U);
+        }
         if (!c->p.skip_theta) {   /* isothermal runs hold theta */
             stream(c, &c->lt, c->star[2], c->pop[2]);
             moment0(c, &c->lt, c->pop[2], c->th);

@@ -47,6 +47,14 @@ typedef struct {
                                  19); 0: the phase field's.  Sec. 4.1 runs its
                                  2D validation with D2Q9 for phi and D2Q5 for
                                  theta */
+    int32_t skip_U;           /* 1: pure substance (M c_inf = 0, where U acts
+                                 on nothing): U is held at its initial value,
+                                 its scheme is not run */
+    int32_t grad_stencil;     /* gradients of phi: 0 = central differences
+                                 along the axes (reading R5); 1 = the
+                                 isotropic lattice gradient
+                                 (e^2 dx)^-1 sum_i w_i e_i phi(x + e_i) over
+                                 the phase field's lattice, mirror ghosts */
 } orc_params;
 
 typedef struct orc_ctx orc_ctx;

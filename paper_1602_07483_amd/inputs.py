@@ -172,18 +172,35 @@ def workload_centred_octant(n: int = 256, steps: int = 10000) -> Problem:
                    steps=steps, reduce_every=100)
 
 
-def workload_thermal2d(n: int = 500, steps: int = 37500) -> Problem:
+def workload_interior(lattice: int = 19) -> Problem:
+    """136 x 40 x 24 with a seed R = 8 in the middle and a second one at a
+    mirror corner, walls of both kinds, U noise 1e-3 (seed 7): with the
+    default launches of both step kernels (tiles of 32 x 8, 64 x 4, 32 x 4 or
+    64 x 8 nodes) some tiles have no node on an x or y face, so the growing
+    interface crosses tiles on the wall-free path that large domains run."""
+    walls = (SYMMETRY, NOFLUX, SYMMETRY, NOFLUX, NOFLUX, SYMMETRY)
+    return Problem("interior", 136, 40, 24, lattice, walls, dt=DT if lattice == 19 else 0.11, eps=0.05,
+                   centres=[(67.5, 19.5, 11.5), (-0.5, -0.5, 23.5)], radius=8.0, U0=-0.55,
+                   theta0=-0.55, noise_amp=1e-3, noise_seed=7)
+
+
+def workload_thermal2d(n: int = 500, steps: int = 37500, dx: float = 0.4) -> Problem:
     """Pure-substance thermal dendrite of Sec. 4.1 (anisotropic case) as a
     one-node-thick D3Q19 slab (mirror walls in z, which reduce D3Q19 to D2Q9):
     quadrant of n^2 nodes, dx/W0 = 0.4, dt/tau0 = 0.008, kappa = 4,
     lambda = 6.3826 (zero kinetic coefficient), eps = 0.05, Delta = 0.55,
     seed radius 10 dx at the mirror corner.  The solute field is decoupled
     (M c_inf = 0); its diffusivity only has to keep its scheme stable.
-    37 500 steps reach T = t/tau0 = 300."""
+    37 500 steps reach T = t/tau0 = 300.
+
+    Another dx refines the grid under diffusive scaling, dt = 0.008 (dx/0.4)^2
+    (every relaxation time unchanged), with the seed radius kept at 4 W0:
+    n nodes then span n dx W0 and T = steps dt."""
     walls = (SYMMETRY, NOFLUX, SYMMETRY, NOFLUX, SYMMETRY, SYMMETRY)
-    return Problem("thermal2d-%d" % n, n, n, 1, 19, walls, dx=0.4, dt=0.008, W0=1.0,
-                   tau0=1.0, lam=6.3826, Mcinf=0.0, k=0.15, D=1.0, kappa=4.0, eps=0.05,
-                   centres=[(-0.5, -0.5, 0.0)], radius=10.0, U0=0.0, theta0=-0.55,
+    dt = 0.008 * (dx / 0.4) ** 2
+    return Problem("thermal2d-%d" % n if dx == 0.4 else "thermal2d-%d-dx%g" % (n, dx), n, n, 1, 19, walls,
+                   dx=dx, dt=dt, W0=1.0, tau0=1.0, lam=6.3826, Mcinf=0.0, k=0.15, D=1.0, kappa=4.0,
+                   eps=0.05, centres=[(-0.5, -0.5, 0.0)], radius=4.0 / dx, U0=0.0, theta0=-0.55,
                    steps=steps, reduce_every=500)
 
 

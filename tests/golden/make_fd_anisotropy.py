@@ -52,7 +52,8 @@ def first_crossing(prof):
 
 
 def fd_solver(stencil, pb):
-    fd = oracle.FDOracle(pb.nx, pb.ny, pb.nz, stencil=stencil, **pb.model_kwargs())
+    # pure substance: U does not act on phi or theta and is not solved
+    fd = oracle.FDOracle(pb.nx, pb.ny, pb.nz, stencil=stencil, skip_U=1, **pb.model_kwargs())
     fd.set(*pb.initial_fields())
     return fd
 

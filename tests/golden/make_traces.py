@@ -15,6 +15,13 @@ fd2d, fd3d -- the LB oracle and the finite-difference discretisation of the
               octant over 1500 steps; tip positions every 200 / 100 steps
 fd3d_iso   -- the same 64^3 octant as the paper's isothermal alloy benchmark
               (theta = 0 and held in both), 1500 steps, tips every 50
+thermal2d_isograd -- thermal2d with the isotropic lattice gradient of phi
+              (oracle grad_stencil = 1) instead of axis central differences
+thermal2d_dx<h>_T150 -- thermal2d refined under diffusive scaling
+              (dt = 0.008 (h/0.4)^2, seed radius 4 W0) in a 100 W0 quadrant
+              up to T = 150, h = 0.4, 0.3, 0.2; records every T = 4
+The thermal cases hold U (oracle skip_U: M c_inf = 0, U acts on nothing),
+which leaves phi and theta bit for bit unchanged.
 """
 import json
 import os
@@ -92,15 +99,31 @@ FD_CASES = {"fd2d": (lambda: fd_problem(200, 1), 4000, 200, 0),
             "fd3d": (lambda: fd_problem(64, 64), 1500, 100, 0),
             "fd3d_iso": (lambda: fd_problem(64, 64, iso=True), 1500, 50, 1)}
 
+def thermal2d_refined(dx, box=100.0, T=150.0, T_every=4.0):
+    pb = inputs.workload_thermal2d(n=int(round(box / dx)), dx=dx)
+    pb.steps = int(round(T / pb.dt))
+    pb.reduce_every = int(round(T_every / pb.dt))
+    return pb
+
+
+# extra oracle options per workload
+EXTRA = {"thermal2d_isograd": {"skip_U": 1, "grad_stencil": 1}}
+for _h in (0.4, 0.3, 0.2):
+    EXTRA["thermal2d_dx%g_T150" % _h] = {"skip_U": 1}
+
 WORKLOADS = {
     "thermal2d": lambda: inputs.workload_thermal2d(),
+    "thermal2d_isograd": lambda: inputs.workload_thermal2d(),
+    "thermal2d_dx0.4_T150": lambda: thermal2d_refined(0.4),
+    "thermal2d_dx0.3_T150": lambda: thermal2d_refined(0.3),
+    "thermal2d_dx0.2_T150": lambda: thermal2d_refined(0.2),
     "octant128": lambda: inputs.workload_octant(128, 5000),
     "centred256": lambda: inputs.workload_centred_octant(256, 10000),
 }
 
 
-def trace(pb, log=print):
-    o = oracle.Oracle(pb.nx, pb.ny, pb.nz, **pb.model_kwargs())
+def trace(pb, log=print, extra=None):
+    o = oracle.Oracle(pb.nx, pb.ny, pb.nz, **pb.model_kwargs(), **(extra or {}))
     o.init(*pb.initial_fields())
     out = []
     t0 = time.time()
@@ -121,7 +144,7 @@ def trace(pb, log=print):
 
 
 def main(names):
-    for name in names or list(WORKLOADS) + list(FD_CASES):
+    for name in names or ["thermal2d", "octant128", "centred256"] + list(FD_CASES):
         if name in FD_CASES:
             factory, steps, every, skip_theta = FD_CASES[name]
             pb = factory()
@@ -135,8 +158,10 @@ def main(names):
             print("wrote", path)
             continue
         pb = WORKLOADS[name]()
+        extra = EXTRA.get(name, {})
         rec = {"workload": pb.name, "problem": {k: v for k, v in pb.__dict__.items()},
-               "oracle_threads": oracle.num_threads(), "trace": trace(pb)}
+               "oracle_options": extra, "oracle_threads": oracle.num_threads(),
+               "trace": trace(pb, extra=extra)}
         path = os.path.join(HERE, "trace_%s.json" % name)
         with open(path, "w") as fh:
             json.dump(rec, fh, indent=0)

@@ -123,7 +123,7 @@ def _fd_anisotropy_script():
     return mod
 
 
-@pytest.mark.parametrize("stencil,n", [(6, 150), (18, 150), (6, 100), (18, 100)])
+@pytest.mark.parametrize("stencil,n", [(6, 150), (18, 150)])
 def test_fd_anisotropy_run_start_reproduces(stencil, n):
     """The stored FD6/FD18 isotropic-growth runs are what the current FD
     oracle computes: the sums of phi and theta after their first 100 steps."""
@@ -156,8 +156,31 @@ def test_fd6_explicit_step_diverges_at_the_lb_time_step():
 def test_fd18_grid_is_less_anisotropic_than_fd6():
     """Sec. 4.1's FD comparison: the isotropic-growth A_g of FD6 well above
     that of FD18 (the paper: 4.365 % and 0.575 %; its undercooling is not
-    printed, so the values themselves are parity unpinned).  100^3 octant,
+    printed, so the values themselves are parity unpinned).  150^3 octant,
     each stencil at its stable time step."""
-    g6, g18 = _fd_anisotropy(6, 100), _fd_anisotropy(18, 100)
+    g6, g18 = _fd_anisotropy(6), _fd_anisotropy(18)
     print("A_g FD6 %.3f %%, FD18 %.3f %%" % (g6["A_g_percent"], g18["A_g_percent"]))
     assert g6["A_g_percent"] > 1.0 and g18["A_g_percent"] < 0.5
+
+
+def test_fp32_rounding_evidence():
+    """The stored single-precision rounding errors (the oracle's algorithm
+    built in float against the FP64 oracle, tests/golden/fp32_rounding.json)
+    are what the current oracles compute: the 32^3 D3Q15 ensemble domain
+    after 50 steps is recomputed.  The float build does round in single
+    precision (its error is far above FP64 rounding and below 1e-4), and on
+    the fastest-growing cases it exceeds 1e-5 after 200 steps, which is why
+    the GPU's FP32 parity there is bounded by it."""
+    import importlib.util
+    spec = importlib.util.spec_from_file_location("make_fp32_rounding",
+                                                  os.path.join(GOLDEN, "make_fp32_rounding.py"))
+    mod = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mod)
+    with open(os.path.join(GOLDEN, "fp32_rounding.json")) as fh:
+        g = json.load(fh)["cases"]
+    pb = [p for p in mod.cases() if p.name == "ens-07"][0]
+    got = mod.rounding_error(pb, (50,))["50"]
+    assert got == g["ens-07"]["max_abs_phi_U_theta"]["50"]
+    assert all(1e-9 < e < 1e-4 for e in got)
+    assert g["interior"]["max_abs_phi_U_theta"]["200"][0] > 1e-5
+    assert g["ens-62"]["max_abs_phi_U_theta"]["200"][0] > 1e-5

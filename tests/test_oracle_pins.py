@@ -167,6 +167,116 @@ def test_uniform_state_recurrence(q):
     assert phi > 0.99   # the solid grew
 
 
+@pytest.mark.parametrize("q", [7, 19])
+def test_uniform_state_reductions(q):
+    """The diagnostics on a uniform state whose scalar recurrence (above) is
+    known: the solute mass of reading R15, sum zeta(phi)(1 + (1-k)U) dx^3,
+    stays at N dx^3 zeta(phi0)(1 + (1-k)U0) while phi and U change (the
+    recurrence conserves that product exactly); the enthalpy
+    sum (theta - phi/2) dx^3 stays at its start (eq. Source_Tempr); the solid
+    fraction is (1 + phi)/2 and the plain sums are N phi dx^3 and N U dx^3.
+    dx = 0.7 fixes the volume factor."""
+    dx = 0.7
+    pb = dict(lattice=q, walls=(NOFLUX, SYMMETRY, NOFLUX, NOFLUX, SYMMETRY, NOFLUX), dx=dx,
+              dt=0.15, W0=dx, tau0=1.0, lam=3.2, Mcinf=1.0, k=0.15, D=2.0 * dx * dx,
+              kappa=20.0 * dx * dx)
+    shape = (3, 4, 5)
+    N = 60
+    o = Oracle(5, 4, 3, **pb)
+    phi, U, th = 0.3, -0.4, -0.2
+    o.init(np.full(shape, phi), np.full(shape, U), np.full(shape, th))
+    k = pb["k"]
+    zeta = lambda f: 0.5 * (1 + k) - 0.5 * (1 - k) * f
+    vol = dx ** 3
+    m0 = N * vol * zeta(phi) * (1 + (1 - k) * U)
+    h0 = N * vol * (th - 0.5 * phi)
+    for step in range(121):
+        if step % 20 == 0:
+            r = o.reduce()
+            f = o.fields()
+            ph, u = float(f[0][0, 0, 0]), float(f[1][0, 0, 0])
+            assert abs(r[R_MASS] - m0) <= 1e-12 * abs(m0), step
+            assert abs(r[R_ENTHALPY] - h0) <= 1e-12 * abs(h0), step
+            assert abs(r[R_SOLID] - 0.5 * (1 + ph)) <= 1e-14, step
+            assert abs(r[R_SUMPHI] - N * vol * ph) <= 1e-12 * N * vol, step
+            assert abs(r[R_SUMU] - N * vol * u) <= 1e-12 * N * vol, step
+        o.step(1)
+    f = o.fields()
+    assert f[0].min() > 0.9 and f[1].max() > -0.3   # phi and U moved far from the start
+
+
+def test_skip_U_leaves_phi_and_theta_unchanged():
+    """Pure substance (M c_inf = 0): U acts on neither phi (eq. LBE_SourceTerm
+    carries M c_inf U) nor theta, so holding U (skip_U) leaves phi and theta
+    bit for bit those of the full step, and U keeps its initial field."""
+    pb = Problem("pure", 24, 20, 1, 19, (SYMMETRY, NOFLUX, SYMMETRY, NOFLUX, SYMMETRY, SYMMETRY),
+                 dx=0.4, dt=0.008, lam=6.3826, Mcinf=0.0, D=1.0, kappa=4.0, eps=0.05,
+                 centres=[(-0.5, -0.5, 0.0)], radius=6.0, U0=0.1, theta0=-0.55,
+                 noise_amp=1e-2, noise_seed=9)
+    f0 = pb.initial_fields()
+    a = Oracle(pb.nx, pb.ny, pb.nz, **pb.model_kwargs())
+    b = Oracle(pb.nx, pb.ny, pb.nz, skip_U=1, **pb.model_kwargs())
+    a.init(*f0)
+    b.init(*f0)
+    a.step(200)
+    b.step(200)
+    fa, fb = a.fields(), b.fields()
+    assert np.array_equal(fa[0], fb[0]) and np.array_equal(fa[2], fb[2])
+    assert np.array_equal(fb[1], f0[1])
+    assert not np.array_equal(fa[1], f0[1])
+
+
+def _initial_N(q, phi, grad_stencil, eps=0.05, aniso=0, delta=0.0):
+    """The anisotropy vector N of the initial phase field, read back from the
+    initial g populations: their first moment is -N c_phi (eq. Feq_Phase)."""
+    nz, ny, nx = phi.shape
+    o = Oracle(nx, ny, nz, lattice=q, walls=(NOFLUX,) * 6, dx=1.0, dt=0.15, W0=1.0, tau0=1.0,
+               eps=eps, aniso=aniso, delta=delta, grad_stencil=grad_stencil)
+    o.init(phi, np.zeros_like(phi), np.zeros_like(phi))
+    e, w, _, _, e2 = oracle.lattice(q)
+    g = o.pops(0)
+    cphi = 0.15
+    return -np.einsum("ia,izyx->azyx", e.astype(float), g) / cphi
+
+
+@pytest.mark.parametrize("q", [15, 19])
+def test_isotropic_gradient_option(q):
+    """grad_stencil = 1 takes grad phi as (e^2 dx)^-1 sum_i w_i e_i phi(x+e_i)
+    (the isotropic variant of reading R5).  Pins, through the anisotropy
+    vector N = |p|^2 a_s grad_p a_s (eq. TermesAnisotropes), which the initial
+    g populations carry as their first moment:
+      * N is homogeneous of degree 1 in p, so for phi = c + b.x + x.Hx/2 (the
+        lattice moments make the stencil exact on quadratics: odd moments
+        vanish, sum w e e = e^2 I) N equals N(b + H x) of the exact gradient
+        at interior nodes, as the axis stencil does too;
+      * the two stencils differ on the cubic field phi = x y^2: the axis
+        difference in x gives y^2 exactly, the lattice form
+        y^2 + dx^2 (sum_i w_i e_x^2 e_y^2)/e^2, so N differs."""
+    rng = np.random.default_rng(q)
+    n = 9
+    z, y, x = np.meshgrid(*(np.arange(n, dtype=float),) * 3, indexing="ij")
+    X = np.stack([x, y, z]) - 4.0
+    b = rng.normal(size=3) * 0.05
+    Hm = rng.normal(size=(3, 3)) * 0.01
+    H = Hm + Hm.T
+    phi = 0.1 + np.einsum("a,azyx->zyx", b, X) + 0.5 * np.einsum("azyx,ab,bzyx->zyx", X, H, X)
+    grad = b[:, None, None, None] + np.einsum("ab,bzyx->azyx", H, X)
+    inner = (slice(None), slice(1, -1), slice(1, -1), slice(1, -1))
+    n_iso = _initial_N(q, phi, 1)
+    n_ax = _initial_N(q, phi, 0)
+    # N of the exact gradient, from the same oracle routine
+    ref = np.zeros_like(grad)
+    for idx in np.ndindex(n, n, n):
+        a, Nv = oracle.anisotropy(grad[(slice(None),) + idx], 0, 0.05, 0.0)
+        ref[(slice(None),) + idx] = Nv
+    assert np.max(np.abs(n_iso[inner] - ref[inner])) < 1e-13
+    assert np.max(np.abs(n_ax[inner] - ref[inner])) < 1e-13
+    # a cubic profile separates them
+    phi3 = 0.1 + 0.002 * (x - 4.0) * (y - 4.0) ** 2 + 0.02 * (y - 4.0) + 0.01 * (z - 4.0)
+    d = np.max(np.abs(_initial_N(q, phi3, 1)[inner] - _initial_N(q, phi3, 0)[inner]))
+    assert d > 1e-6
+
+
 # ----------------------------------------------------------------- diffusion
 def _gaussian_run(n_half, sigma0, steps, D, kappa, q=19):
     """Liquid (phi = -1) quasi-1D slab: U and theta obey pure diffusion."""

@@ -63,7 +63,7 @@ def run_gpu(storage, steps, warmup, n, launch=None):
     from paper_1602_07483_amd.inputs import workload_centred
 
     pb = workload_centred(n=n)
-    pb.reduce_every = 0
+    pb.reduce_every = 100        # FP64 reductions (solute mass, tip) every 100 steps, timed
     stream = torch.cuda.current_stream().cuda_stream
     s = lbpf.solver_for(pb, storage=storage, stream=stream)
     fields0 = pb.initial_fields()
@@ -258,6 +258,62 @@ def run_multiseed(steps, storage="f16"):
             "storage": storage, "runs": out}
 
 
+def oracle_errors(storages, steps_small=200, n_big=256, steps_big=10000):
+    """Error of each storage form against the FP64 oracle:
+    * fields: max-abs of phi, U, theta after steps_small steps of the 32^3
+      corner workload (seeded input), against a live oracle run;
+    * tip velocity and solute-mass drift: a steps_big run of the 256^3
+      centred workload with FP64 reductions every 100 steps, against the
+      oracle's stored trace of the same run (tests/golden/trace_centred256.json,
+      computed on the equivalent octant): the largest relative tip-velocity
+      error over the intervals of free growth, and the solute-mass drift of
+      both over the whole run."""
+    import numpy as np
+    import oracle
+    import torch
+    from paper_1602_07483_amd import lbpf
+    from paper_1602_07483_amd.inputs import workload_small, workload_centred
+
+    small = workload_small(steps=steps_small)
+    f0 = small.initial_fields()
+    o = oracle.Oracle(small.nx, small.ny, small.nz, **small.model_kwargs())
+    o.init(*f0)
+    o.step(steps_small)
+    ref = o.fields()
+    o.close()
+    with open(os.path.join(ROOT, "tests", "golden", "trace_centred256.json")) as fh:
+        tr = json.load(fh)["trace"]
+    vo = np.diff([r["tip"][0] for r in tr])
+    stream = torch.cuda.current_stream().cuda_stream
+    out = {}
+    for storage in storages:
+        s = lbpf.solver_for(small, storage=storage, stream=stream)
+        s.set_fields(*f0)
+        s.step(steps_small)
+        g = s.read(reductions=False)[:3]
+        s.close()
+        pb = workload_centred(n=n_big, steps=steps_big)
+        s = lbpf.solver_for(pb, storage=storage, stream=stream)
+        s.set_fields(*pb.initial_fields())
+        s.step(steps_big)
+        hist = s.history()
+        s.close()
+        vg = np.diff([h["tip"][0] for h in hist])
+        tips_o = np.array([r["tip"][0] for r in tr])
+        inside = tips_o < 0.9 * (n_big // 2)
+        ok = inside[:-1] & inside[1:] & (np.abs(vo) > 1e-3)
+        m0 = 8.0 * tr[0]["solute_mass"]
+        out[storage] = {
+            "fields_max_abs_after_%d_steps_32cube" % steps_small:
+                {name: float(np.max(np.abs(a - b))) for name, a, b in zip(("phi", "U", "theta"), g, ref)},
+            "tip_velocity_max_rel_error": float(np.max(np.abs(vg[ok] - vo[ok]) / np.abs(vo[ok]))),
+            "tip_velocity_intervals": int(ok.sum()),
+            "mass_drift": {"gpu": (hist[-1]["solute_mass"] - hist[0]["solute_mass"]) / abs(hist[0]["solute_mass"]),
+                           "oracle": (8.0 * tr[-1]["solute_mass"] - m0) / abs(m0)},
+            "steps": steps_big}
+    return out
+
+
 def copy_bandwidth(nbytes=2 << 30, reps=20):
     import torch
     from paper_1602_07483_amd import lbpf
@@ -274,12 +330,19 @@ def copy_bandwidth(nbytes=2 << 30, reps=20):
     return 2.0 * nbytes / dt / 1e9
 
 
-def cpu_baseline(n=256, budget_s=12.0, max_steps=12):
-    """The FP64 oracle, as it stands, on the same workload: steps until about
-    budget_s of stepping (initialisation excluded)."""
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _oracle_rate(pb, budget_s, max_steps):
     import oracle
-    from paper_1602_07483_amd.inputs import workload_centred
-    pb = workload_centred(n=n)
     o = oracle.Oracle(pb.nx, pb.ny, pb.nz, **pb.model_kwargs())
     o.init(*pb.initial_fields())
     steps = 0
@@ -291,9 +354,33 @@ def cpu_baseline(n=256, budget_s=12.0, max_steps=12):
             break
     dt = time.perf_counter() - t0
     o.close()
-    return {"value": float(n) ** 3 * steps / dt / 1e6, "unit": "MLUPS",
-            "cores": oracle.num_threads(), "kind": "oracle",
-            "sample": "%d^3 D3Q19 centred-seed workload, %d FP64 steps on the host" % (n, steps)}
+    return float(pb.nodes) * steps / dt / 1e6, steps
+
+
+def cpu_baseline(n=256):
+    """The FP64 oracle, as it stands (initialisation excluded), on bounded
+    samples: the benchmark's 256^3 workload on all host threads (the line's
+    value), the 128^3 octant dendrite on all threads, and the same octant on
+    one thread."""
+    import ctypes
+    import oracle
+    from paper_1602_07483_amd.inputs import workload_centred, workload_octant
+    threads = oracle.num_threads()
+    v, steps = _oracle_rate(workload_centred(n=n), 12.0, 12)
+    v128, s128 = _oracle_rate(workload_octant(128), 6.0, 40)
+    one = None
+    try:
+        gomp = ctypes.CDLL("libgomp.so.1")
+        gomp.omp_set_num_threads(1)
+        one, s1 = _oracle_rate(workload_octant(128), 8.0, 10)
+        gomp.omp_set_num_threads(threads)
+    except OSError:
+        s1 = 0
+    return {"value": v, "unit": "MLUPS", "cores": threads, "kind": "oracle",
+            "sample": "%d^3 D3Q19 centred-seed workload, %d FP64 steps on %d host threads" % (n, steps, threads),
+            "cpu_model": _cpu_model(),
+            "octant128_all_threads": {"mlups": v128, "steps": s128},
+            "octant128_one_thread": {"mlups": one, "steps": s1}}
 
 
 def main():
@@ -310,6 +397,8 @@ def main():
     ap.add_argument("--no-multiseed", action="store_true", help="skip the 512^3 multi-seed leg")
     ap.add_argument("--multiseed-steps", type=int, default=200)
     ap.add_argument("--ensemble-steps", type=int, default=2000)
+    ap.add_argument("--no-errors", action="store_true",
+                    help="skip the error of each storage form against the FP64 oracle")
     ap.add_argument("--autotune", action="store_true",
                     help="let the library's autotuner pick the launch before timing")
     args = ap.parse_args()
@@ -342,6 +431,12 @@ def main():
     ensemble = None
     if not args.no_ensemble:
         ensemble = run_ensemble(args.ensemble_steps, max(args.ensemble_steps // 4, 1))
+    errors = None
+    if not args.no_errors and args.n == 256:
+        errors = oracle_errors(["f32"] + ([] if args.no_variants else ["f16", "bf16"]))
+        for st, e in errors.items():
+            if st in variants:
+                variants[st]["error_vs_oracle"] = e
 
     dom = max(res["kernels"], key=lambda k: res["kernels"][k]["avg_ms"])
     kd = res["kernels"][dom]
@@ -361,12 +456,14 @@ def main():
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": "centred seed R=10, %d^3 D3Q19, phi/U/theta, Delta=0.6, "
-                               "eps=0.05, k=0.15, no-flux walls" % args.n,
+                               "eps=0.05, k=0.15, no-flux walls, dt/tau0=0.15 (dt=tau0 is unstable), "
+                               "FP64 reductions every 100 steps" % args.n,
                    "nodes": args.n ** 3, "lattice": "D3Q19", "storage": "f32"},
         "algorithmic_GBps": res["algorithmic_GBps"],
         "launch": res["launch"],
         "kernels": res["kernels"],
         "host_io": res["host_io"],
+        "error_vs_oracle": errors.get("f32") if errors else None,
         "variants": variants,
         "roofline": roofline,
         "cpu_baseline": cpu,

@@ -156,7 +156,12 @@ typedef struct {
                                  4.1).  NaN without an earlier record. */
 } lbpf_reductions;
 
-/* Create a context: validates the parameters, allocates the populations
+/* Create a context for one domain of the model of Sec. 2 (phase field
+ * eq. PhaseField_KarmaRappel, supersaturation eq. Concentration_Echebarria
+ * with the anti-trapping current eq. AntiTrapping_Current, temperature
+ * eq. Temp_Ramirez), discretised by the schemes of Sec. 3.1-3.3 on the
+ * lattice of Sec. 3.4 (Tables 1 and 2) with the bounce-back walls of
+ * Sec. 3.4: validates the parameters, allocates the populations
  * (two lattices per field), the fields and the reduction buffers on the
  * current device.  Device arrays have their rows padded to a multiple of 32
  * values; that layout stays inside the library (every copy in or out uses
@@ -179,7 +184,14 @@ lbpf_status lbpf_destroy(lbpf_ctx* ctx);
 lbpf_status lbpf_set_fields(lbpf_ctx* ctx, const double* phi, const double* U,
                             const double* theta);
 
-/* Advance nsteps >= 0 time steps, asynchronously on the context stream.  When
+/* Advance nsteps >= 0 time steps, asynchronously on the context stream.  One
+ * step is the algorithm of Sec. 3.4: the phase-field node terms (a_s(n) of
+ * eq. Anisotropic-Function_As or As_K41-K61, N of eq. TermesAnisotropes,
+ * eta_phi of eq. LBE_RelaxationTime, Q_phi of eq. LBE_SourceTerm), the
+ * non-local collision eq. Collision_Stage and streaming eq. Deplacement_STD
+ * with bounce-back; then, with the new phi, U by eqs. LBE_Eq_Transport and
+ * Feq_Transport (J_tot eq. Def_Jtot, S eq. Def_S, Q_U eq. Def_Qu) and theta
+ * by eqs. LBE_Eq_Temp and EqFunction_Tempr (source eq. Source_Tempr).  When
  * reduce_every > 0 a reduction record is appended to the history after every
  * step whose count is a multiple of reduce_every.  Errors: ESTATE (no fields
  * yet), EINVAL (nsteps < 0), EDEVICE. */
@@ -199,7 +211,12 @@ lbpf_status lbpf_set_graph(lbpf_ctx* ctx, int32_t steps_per_graph);
 lbpf_status lbpf_sync(lbpf_ctx* ctx);
 
 /* Copy the current fields to host arrays (each may be NULL to skip it) and,
- * when red != NULL, compute a fresh reduction record of the current state.
+ * when red != NULL, compute a fresh reduction record of the current state:
+ * the fields are the zeroth moments of the populations (phi = sum g_i,
+ * U = sum h_i, theta = sum f_i, Sec. 3.1-3.3); the record holds the solid
+ * fraction, the solute content zeta(phi)(1 + (1-k)U) summed over the nodes
+ * (the definition of U in Sec. 2 solved for c/c_inf), the enthalpy, and the
+ * tip position and velocity (V_p of Sec. 4.1).
  * Synchronises the stream.  Returns EUNSTABLE (after copying) when that
  * record fails the health check. */
 lbpf_status lbpf_read(lbpf_ctx* ctx, double* phi, double* U, double* theta,
@@ -326,6 +343,17 @@ int32_t lbpf_storage_bytes(int32_t storage);
  * benchmark.  Asynchronous.  Errors: EINVAL, EDEVICE. */
 lbpf_status lbpf_bench_copy(void* dst, const void* src, int64_t nbytes, void* hip_stream);
 
+/* Bandwidth reference kernels (measurement only, no part of the method):
+ * mode 0 reads nbytes from src, mode 1 writes nbytes to dst, mode 2 copies
+ * src to dst; width = bytes per lane and access (2, 4, 8 or 16); nontemporal =
+ * 1 adds streaming cache hints; blocks = grid size in 256-thread blocks
+ * (0: one thread per four elements, at most 4096 blocks), each thread
+ * striding over the array with four accesses in flight.  Device pointers,
+ * 16-byte aligned, nbytes a multiple of width; mode 0 may write one word at
+ * dst.  Asynchronous on hip_stream.  Errors: EINVAL, EDEVICE. */
+lbpf_status lbpf_bench_bandwidth(int32_t mode, int32_t width, int32_t nontemporal, int32_t blocks, void* dst,
+                                 const void* src, int64_t nbytes, void* hip_stream);
+
 /* Description of the last error on ctx (or of the last failed creation when
  * ctx is NULL); valid until the next call on the same context. */
 const char* lbpf_last_error(const lbpf_ctx* ctx);
@@ -351,6 +379,23 @@ lbpf_status lbpf_batch_create(int32_t n, const lbpf_grid* grids, const lbpf_para
 lbpf_ctx* lbpf_batch_domain(lbpf_batch* b, int32_t i);
 /* As lbpf_set_graph, for the whole batch. */
 lbpf_status lbpf_batch_set_graph(lbpf_batch* b, int32_t steps_per_graph);
+/* Launch of the batch kernel k_phi (kernel 0) or k_ut (1) over all domains:
+ * tile shape (as lbpf_set_kernel_launch: 64x2, 64x4, 32x4, 32x8, 32x16;
+ * FP64 64x2 and 32x4) and z slab.  Takes effect at the next step (the work
+ * tables are rebuilt and a captured graph is recaptured).  The default is
+ * 32x8 (FP64 32x4) with slab 8 (16-bit storage) or 4.  Errors: EINVAL. */
+lbpf_status lbpf_batch_set_launch(lbpf_batch* b, int32_t kernel, int32_t tile_x, int32_t tile_y, int32_t zslab);
+lbpf_status lbpf_batch_get_launch(lbpf_batch* b, int32_t kernel, int32_t* tile_x, int32_t* tile_y,
+                                  int32_t* zslab);
+/* Autotuner of the batch launches: times every tile shape of the storage
+ * type with z slabs {2, 4, 6, 8, 12} (both kernels alike, two untimed steps
+ * and steps_per_candidate timed steps each, events around the k_phi and the
+ * k_ut launches), keeps for each kernel its fastest launch, and restores
+ * every domain's state (a temporary device snapshot of all populations and
+ * fields is allocated).  *best_ms_per_step (may be NULL) receives the sum of
+ * the two kernels' best times per batch step.  Synchronises.  Errors:
+ * EINVAL, ESTATE (a domain without fields, parities differ), EDEVICE. */
+lbpf_status lbpf_batch_autotune(lbpf_batch* b, int32_t steps_per_candidate, double* best_ms_per_step);
 /* Advance every domain nsteps; all must have fields and equal step parity.
  * Asynchronous.  Errors: ESTATE, EINVAL, EDEVICE. */
 lbpf_status lbpf_batch_step(lbpf_batch* b, int64_t nsteps);

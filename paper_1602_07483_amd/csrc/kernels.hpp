@@ -926,7 +926,7 @@ __global__ __launch_bounds__(TX * TY, (sizeof(T) == 4 ? 3 : 1)) void k_ut(
 
 template <class T>
 struct DomainDesc {
-    Coef<T> c;
+    Coef<T> c[2];      // constants with the tiling of k_phi [0] and k_ut [1]
     void* pop[3][2];   // g, h, f populations per parity
     T* fld[3][2];      // phi, U, theta per parity
 };
@@ -938,7 +938,7 @@ __global__ __launch_bounds__(TX * TY, (sizeof(T) == 4 ? 4 : 1)) void k_phi_batch
     if (wk.x < 0) return;   // padding entry: the whole block leaves
     const DomainDesc<T>& d = dd[wk.x];
     const int a = par, b = 1 - par;
-    phi_body<L, T, S, TX, TY, true>(d.c, wk.y, (const S*)d.pop[0][a], (S*)d.pop[0][b], d.fld[0][a],
+    phi_body<L, T, S, TX, TY, true>(d.c[0], wk.y, (const S*)d.pop[0][a], (S*)d.pop[0][b], d.fld[0][a],
                                     d.fld[1][a], d.fld[2][a], d.fld[0][b]);
 }
 
@@ -949,7 +949,7 @@ __global__ __launch_bounds__(TX * TY, (sizeof(T) == 4 ? 3 : 1)) void k_ut_batch(
     if (wk.x < 0) return;   // padding entry: the whole block leaves
     const DomainDesc<T>& d = dd[wk.x];
     const int a = par, b = 1 - par;
-    ut_body<L, T, S, TX, TY, true>(d.c, wk.y, (const S*)d.pop[1][a], (S*)d.pop[1][b],
+    ut_body<L, T, S, TX, TY, true>(d.c[1], wk.y, (const S*)d.pop[1][a], (S*)d.pop[1][b],
                                    (const S*)d.pop[2][a], (S*)d.pop[2][b], d.fld[0][a], d.fld[0][b],
                                    d.fld[1][a], d.fld[2][a], d.fld[1][b], d.fld[2][b]);
 }

@@ -58,27 +58,74 @@ __global__ __launch_bounds__(256) void k_reduce_final(const double* __restrict__
     }
 }
 
-// Plain 16-byte vector copy, four loads in flight per thread and streaming
-// hints: the practical bandwidth reference.
+// Bandwidth reference kernels: read-only (MODE 0), write-only (1) and copy
+// (2) over n elements of V (2, 4, 8 or 16 bytes per lane), four accesses in
+// flight per thread, optionally with streaming (non-temporal) hints, on a
+// grid-stride loop.  The read-only form folds what it reads into one word per
+// thread and stores it only when it equals a run-time value (all ones, which
+// no fold of the zero-filled buffers reaches), so the loads cannot be removed.
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
-__global__ __launch_bounds__(256) void k_copy(const u32x4* __restrict__ src, u32x4* __restrict__ dst,
-                                              size_t n16) {
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ unsigned fold(unsigned short v) { return v; }
+__device__ __forceinline__ unsigned fold(unsigned v) { return v; }
+__device__ __forceinline__ unsigned fold(u32x2 v) { return v.x ^ v.y; }
+__device__ __forceinline__ unsigned fold(u32x4 v) { return v.x ^ v.y ^ v.z ^ v.w; }
+template <class V> __device__ __forceinline__ V splat(unsigned v) { return V(v); }
+template <> __device__ __forceinline__ unsigned short splat<unsigned short>(unsigned v) { return (unsigned short)v; }
+
+template <class V, int MODE, bool NT>
+__global__ __launch_bounds__(256) void k_bw(const V* __restrict__ src, V* __restrict__ dst, size_t n,
+                                            unsigned* __restrict__ sink, unsigned magic) {
     const size_t stride = (size_t)gridDim.x * blockDim.x;
     size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    for (; i + 3 * stride < n16; i += 4 * stride) {
-        u32x4 v[4];
+    unsigned acc = 0;
+    auto ld = [&](size_t j) -> V {
+        if constexpr (NT) return __builtin_nontemporal_load(&src[j]);
+        else return src[j];
+    };
+    auto st = [&](size_t j, V v) {
+        if constexpr (NT) __builtin_nontemporal_store(v, &dst[j]);
+        else dst[j] = v;
+    };
+    for (; i + 3 * stride < n; i += 4 * stride) {
+        V v[4];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) v[u] = __builtin_nontemporal_load(&src[i + u * stride]);
+        for (int u = 0; u < 4; ++u) v[u] = MODE == 1 ? splat<V>((unsigned)(i + u * stride)) : ld(i + u * stride);
 #pragma unroll
-        for (int u = 0; u < 4; ++u) __builtin_nontemporal_store(v[u], &dst[i + u * stride]);
+        for (int u = 0; u < 4; ++u) {
+            if constexpr (MODE == 0) acc ^= fold(v[u]);
+            else st(i + u * stride, v[u]);
+        }
     }
-    for (; i < n16; i += stride) dst[i] = src[i];
+    for (; i < n; i += stride) {
+        if constexpr (MODE == 0) acc ^= fold(ld(i));
+        else st(i, MODE == 1 ? splat<V>((unsigned)i) : ld(i));
+    }
+    if (MODE == 0 && acc == magic) sink[0] = acc;
+}
+
+template <class V, int MODE>
+void launch_bw(int nt, int nb, hipStream_t st, const void* src, void* dst, size_t n) {
+    if (nt)
+        hipLaunchKernelGGL((k_bw<V, MODE, true>), dim3(nb), dim3(256), 0, st, (const V*)src, (V*)dst, n,
+                           (unsigned*)dst, 0xFFFFFFFFu);
+    else
+        hipLaunchKernelGGL((k_bw<V, MODE, false>), dim3(nb), dim3(256), 0, st, (const V*)src, (V*)dst, n,
+                           (unsigned*)dst, 0xFFFFFFFFu);
+}
+template <class V>
+void launch_bw_mode(int mode, int nt, int nb, hipStream_t st, const void* src, void* dst, size_t n) {
+    if (mode == 0) launch_bw<V, 0>(nt, nb, st, src, dst, n);
+    else if (mode == 1) launch_bw<V, 1>(nt, nb, st, src, dst, n);
+    else launch_bw<V, 2>(nt, nb, st, src, dst, n);
 }
 
 }  // namespace lbpf
 
 using namespace lbpf;
 using namespace lbpf_rt;
+
 
 namespace {
 thread_local std::string g_create_error;
@@ -99,7 +146,7 @@ struct lbpf_batch {
     hipStream_t stream = nullptr;
     bool own_stream = false;
     int storage = LBPF_F32;
-    int shape = 3, zslab = 6;
+    int shape[2] = {3, 3}, zslab[2] = {6, 6};   // tile shape id and z slab of k_phi [0], k_ut [1]
     void* d_desc = nullptr;        // DomainDesc<T>[ndom]
     // work tables of k_phi [0] and k_ut [1] over the domains whose phi
     // (resp. U, theta) lattice is D3Q7, D3Q15, D3Q19
@@ -756,8 +803,7 @@ lbpf_status lbpf_set_kernel_launch(lbpf_ctx* ctx, int32_t kernel, int32_t tile_x
     if (xcd_remap != 0 && xcd_remap != 1) return fail(ctx, LBPF_EINVAL, "xcd_remap must be 0 or 1");
     for (int i = 0; i < kNumShapes; ++i) {
         if (kShapes[i].tx != tile_x || kShapes[i].ty != tile_y) continue;
-        const bool ok = ctx->storage == LBPF_F64 ? (i == 0 || i == 2) : true;
-        if (!ok) return fail(ctx, LBPF_EINVAL, "tile shape not available for FP64 storage");
+        if (!shape_ok(ctx->storage, i)) return fail(ctx, LBPF_EINVAL, "tile shape not available for this storage");
         if (kernel == K_UT && ut_pinned(ctx) && i != adv_shape(ctx))
             return fail(ctx, LBPF_EINVAL, kAdvTileMsg);
         ctx->shape[kernel] = i;
@@ -832,7 +878,7 @@ lbpf_status lbpf_autotune(lbpf_ctx* ctx, int32_t steps_per_candidate, double* be
     const int zs_list[] = {2, 4, 6, 8, 12, 16};
     constexpr int NZ = sizeof(zs_list) / sizeof(zs_list[0]);
     for (int sh = 0; sh < kNumShapes && !st; ++sh) {
-        if (ctx->storage == LBPF_F64 && !(sh == 0 || sh == 2)) continue;
+        if (!shape_ok(ctx->storage, sh)) continue;
         for (int zi = 0; zi < 2 * NZ && !st; ++zi) {
             const int zsl = zs_list[zi % NZ];
             if (zsl > 2 * ctx->grid.nz && zi % NZ > 0) continue;
@@ -985,15 +1031,29 @@ lbpf_status lbpf_read_fields_device(lbpf_ctx* ctx, void* phi, void* U, void* the
     return LBPF_OK;
 }
 
+lbpf_status lbpf_bench_bandwidth(int32_t mode, int32_t width, int32_t nontemporal, int32_t blocks, void* dst,
+                                 const void* src, int64_t nbytes, void* hip_stream) {
+    if (mode < 0 || mode > 2 || (width != 2 && width != 4 && width != 8 && width != 16) || blocks < 0 || nbytes < 0 ||
+        (nbytes % width) != 0 || ((uintptr_t)dst % 16) || ((uintptr_t)src % 16) ||
+        (mode != 1 && !src) || !dst)
+        return LBPF_EINVAL;
+    const size_t n = (size_t)nbytes / width;
+    if (n == 0) return LBPF_OK;
+    // default grid: one thread per four elements, capped at 2^20 threads
+    const int nb = blocks ? blocks : (int)std::min<size_t>(4096, (n / 4 + 255) / 256 + 1);
+    const hipStream_t st = (hipStream_t)hip_stream;
+    if (width == 2) launch_bw_mode<unsigned short>(mode, nontemporal, nb, st, src, dst, n);
+    else if (width == 4) launch_bw_mode<unsigned>(mode, nontemporal, nb, st, src, dst, n);
+    else if (width == 8) launch_bw_mode<u32x2>(mode, nontemporal, nb, st, src, dst, n);
+    else launch_bw_mode<u32x4>(mode, nontemporal, nb, st, src, dst, n);
+    return hipGetLastError() == hipSuccess ? LBPF_OK : LBPF_EDEVICE;
+}
+
 lbpf_status lbpf_bench_copy(void* dst, const void* src, int64_t nbytes, void* hip_stream) {
     if (!dst || !src || nbytes < 0 || (nbytes % 16) != 0 || ((uintptr_t)dst % 16) || ((uintptr_t)src % 16))
         return LBPF_EINVAL;
-    const size_t n16 = (size_t)nbytes / 16;
-    if (n16 == 0) return LBPF_OK;
-    const int nb = (int)std::min<size_t>(32768, (n16 + 255) / 256);
-    hipLaunchKernelGGL(k_copy, dim3(nb), dim3(256), 0, (hipStream_t)hip_stream, (const u32x4*)src,
-                       (u32x4*)dst, n16);
-    return hipGetLastError() == hipSuccess ? LBPF_OK : LBPF_EDEVICE;
+    const int nb = (int)std::min<int64_t>(32768, (nbytes / 16 + 255) / 256);
+    return lbpf_bench_bandwidth(2, 16, 1, nb > 0 ? nb : 1, dst, src, nbytes, hip_stream);
 }
 
 }  // extern "C"
@@ -1023,21 +1083,21 @@ lbpf_status batch_build_t(lbpf_batch* b) {
     std::vector<int2> items[2][3];
     for (int d = 0; d < nd; ++d) {
         lbpf_ctx* c = b->dom[d];
-        for (int k = 0; k < 2; ++k) {   // one tiling for both batch kernels
-            c->shape[k] = b->shape;
-            c->zslab[k] = b->zslab;
+        for (int k = 0; k < 2; ++k) {
+            c->shape[k] = b->shape[k];
+            c->zslab[k] = b->zslab[k];
             c->remap[k] = 0;   // the work table carries the XCD order
         }
-        desc[d].c = make_coef<T>(c);
+        for (int k = 0; k < 2; ++k) desc[d].c[k] = make_coef<T>(c, k);
         for (int f = 0; f < 3; ++f)
             for (int par = 0; par < 2; ++par) {
                 desc[d].pop[f][par] = c->pop[f][par];
                 desc[d].fld[f][par] = (T*)c->fld[f][par];
             }
-        const int nt = total_tiles(c, K_PHI);   // both kernels tile alike
         for (int k = 0; k < 2; ++k) {
             const int q = k == K_PHI ? c->q : c->q_ut;
             const int li = q == 7 ? 0 : q == 15 ? 1 : 2;
+            const int nt = total_tiles(c, k);
             for (int t = 0; t < nt; ++t) items[k][li].push_back(int2{d, t});
         }
     }
@@ -1062,47 +1122,46 @@ lbpf_status batch_build_t(lbpf_batch* b) {
     return LBPF_OK;
 }
 
-template <class L, class T, class S, int TX, int TY>
-lbpf_status batch_launch_l(lbpf_batch* b, int li, int par) {
-    if (!b->nwork[K_PHI][li]) return LBPF_OK;
-    hipLaunchKernelGGL((k_phi_batch<L, T, S, TX, TY>), dim3(b->nwork[K_PHI][li]), dim3(TX * TY), 0, b->stream,
-                       (const DomainDesc<T>*)b->d_desc, (const int2*)b->d_work[K_PHI][li], par);
-    BCHK(hipGetLastError());
-    return LBPF_OK;
+template <class T, class S>
+hipError_t batch_launch_ts(lbpf_batch* b, int k, int li, int par) {
+    const int2* w = b->d_work[k][li];
+    const int n = b->nwork[k][li];
+    switch (li) {
+        case 0: return batch_launch_s<D3Q7, T, S>(k, b->shape[k], b->d_desc, w, n, par, b->stream);
+        case 1: return batch_launch_s<D3Q15, T, S>(k, b->shape[k], b->d_desc, w, n, par, b->stream);
+        default: return batch_launch_s<D3Q19, T, S>(k, b->shape[k], b->d_desc, w, n, par, b->stream);
+    }
 }
 
-template <class L, class T, class S, int TX, int TY>
-lbpf_status batch_launch_u(lbpf_batch* b, int li, int par) {
-    if (!b->nwork[K_UT][li]) return LBPF_OK;
-    hipLaunchKernelGGL((k_ut_batch<L, T, S, TX, TY>), dim3(b->nwork[K_UT][li]), dim3(TX * TY), 0, b->stream,
-                       (const DomainDesc<T>*)b->d_desc, (const int2*)b->d_work[K_UT][li], par);
-    BCHK(hipGetLastError());
+// Launches of kernel k (K_PHI or K_UT) for every lattice present in the batch.
+lbpf_status batch_launch_kernel(lbpf_batch* b, int k, int par) {
+    for (int li = 0; li < 3; ++li) {
+        if (!b->nwork[k][li]) continue;
+        hipError_t e = hipErrorInvalidValue;
+        switch (b->storage) {
+            case LBPF_F32: e = batch_launch_ts<float, float>(b, k, li, par); break;
+            case LBPF_F16_DEV: e = batch_launch_ts<float, __half>(b, k, li, par); break;
+            case LBPF_BF16_DEV: e = batch_launch_ts<float, __hip_bfloat16>(b, k, li, par); break;
+            case LBPF_F64: e = batch_launch_ts<double, double>(b, k, li, par); break;
+        }
+        if (e != hipSuccess) return bfail(b, LBPF_EDEVICE, std::string("batch launch: ") + hipGetErrorString(e));
+    }
     return LBPF_OK;
 }
 
 // One time step of every domain: phase field of all domains, then U/theta.
-template <class T, class S, int TX, int TY>
-lbpf_status batch_step_t(lbpf_batch* b, int par) {
-    lbpf_status st = batch_launch_l<D3Q7, T, S, TX, TY>(b, 0, par);
-    if (!st) st = batch_launch_l<D3Q15, T, S, TX, TY>(b, 1, par);
-    if (!st) st = batch_launch_l<D3Q19, T, S, TX, TY>(b, 2, par);
-    if (!st) st = batch_launch_u<D3Q7, T, S, TX, TY>(b, 0, par);
-    if (!st) st = batch_launch_u<D3Q15, T, S, TX, TY>(b, 1, par);
-    if (!st) st = batch_launch_u<D3Q19, T, S, TX, TY>(b, 2, par);
+lbpf_status batch_step_once(lbpf_batch* b, int par) {
+    lbpf_status st = batch_launch_kernel(b, K_PHI, par);
+    if (!st) st = batch_launch_kernel(b, K_UT, par);
     return st;
 }
 
-lbpf_status batch_step_once(lbpf_batch* b, int par) {
-    switch (b->storage) {
-        case LBPF_F32: return batch_step_t<float, float, 32, 8>(b, par);
-        case LBPF_F16_DEV: return batch_step_t<float, __half, 32, 8>(b, par);
-        case LBPF_BF16_DEV: return batch_step_t<float, __hip_bfloat16, 32, 8>(b, par);
-        case LBPF_F64: return batch_step_t<double, double, 32, 4>(b, par);
-    }
-    return bfail(b, LBPF_EINVAL, "bad storage");
-}
-
 lbpf_status batch_build(lbpf_batch* b) {
+    if (b->gexec) {   // a captured graph holds the old work tables
+        (void)hipStreamSynchronize(b->stream);
+        (void)hipGraphExecDestroy(b->gexec);
+        b->gexec = nullptr;
+    }
     return b->storage == LBPF_F64 ? batch_build_t<double>(b) : batch_build_t<float>(b);
 }
 
@@ -1132,8 +1191,10 @@ lbpf_status lbpf_batch_create(int32_t n, const lbpf_grid* grids, const lbpf_para
     lbpf_batch* b = new (std::nothrow) lbpf_batch();
     if (!b) return bfail(nullptr, LBPF_ENOMEM, "host allocation failed");
     b->storage = grids[0].storage;
-    b->shape = b->storage == LBPF_F64 ? 2 : 3;   // 32x4 (FP64) or 32x8 tiles
-    b->zslab = lbpf_storage_bytes(b->storage) == 2 ? 8 : 4;   // measured for the batch kernels
+    for (int k = 0; k < 2; ++k) {   // defaults measured for the batch kernels
+        b->shape[k] = b->storage == LBPF_F64 ? 2 : 3;   // 32x4 (FP64) or 32x8 tiles
+        b->zslab[k] = lbpf_storage_bytes(b->storage) == 2 ? 8 : 4;
+    }
     b->stream = (hipStream_t)hip_stream;
     if (!b->stream) {
         if (hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking) != hipSuccess) {
@@ -1180,6 +1241,124 @@ lbpf_status lbpf_batch_set_graph(lbpf_batch* b, int32_t steps_per_graph) {
         (void)hipGraphExecDestroy(b->gexec);
         b->gexec = nullptr;
     }
+    return LBPF_OK;
+}
+
+lbpf_status lbpf_batch_set_launch(lbpf_batch* b, int32_t kernel, int32_t tile_x, int32_t tile_y, int32_t zslab) {
+    if (!b) return LBPF_EINVAL;
+    if (kernel != K_PHI && kernel != K_UT) return bfail(b, LBPF_EINVAL, "kernel must be 0 (k_phi) or 1 (k_ut)");
+    if (zslab < 1) return bfail(b, LBPF_EINVAL, "zslab < 1");
+    for (int i = 0; i < kNumShapes; ++i) {
+        if (kShapes[i].tx != tile_x || kShapes[i].ty != tile_y) continue;
+        if (!shape_ok(b->storage, i)) return bfail(b, LBPF_EINVAL, "tile shape not available for this storage");
+        b->shape[kernel] = i;
+        b->zslab[kernel] = zslab;
+        b->built = false;
+        return LBPF_OK;
+    }
+    return bfail(b, LBPF_EINVAL, "unsupported tile shape");
+}
+
+lbpf_status lbpf_batch_get_launch(lbpf_batch* b, int32_t kernel, int32_t* tile_x, int32_t* tile_y,
+                                  int32_t* zslab) {
+    if (!b || !tile_x || !tile_y || !zslab) return LBPF_EINVAL;
+    if (kernel != K_PHI && kernel != K_UT) return bfail(b, LBPF_EINVAL, "kernel must be 0 (k_phi) or 1 (k_ut)");
+    *tile_x = kShapes[b->shape[kernel]].tx;
+    *tile_y = kShapes[b->shape[kernel]].ty;
+    *zslab = b->zslab[kernel];
+    return LBPF_OK;
+}
+
+lbpf_status lbpf_batch_autotune(lbpf_batch* b, int32_t steps_per_candidate, double* best_ms_per_step) {
+    if (!b) return LBPF_EINVAL;
+    if (steps_per_candidate < 1) return bfail(b, LBPF_EINVAL, "steps_per_candidate < 1");
+    const int cur0 = b->dom[0]->cur;
+    for (lbpf_ctx* c : b->dom) {
+        if (!c->have_fields) return bfail(b, LBPF_ESTATE, "a domain has no fields yet");
+        if (c->cur != cur0) return bfail(b, LBPF_ESTATE, "domains are at different parities");
+    }
+    BCHK(hipStreamSynchronize(b->stream));
+    // snapshot of every domain's state (populations and fields of parity cur0)
+    std::vector<size_t> off;
+    size_t total = 0;
+    for (lbpf_ctx* c : b->dom) {
+        off.push_back(total);
+        for (int f = 0; f < 3; ++f) total += c->np * lattice_of(c, f) * c->sbytes + c->na * c->tbytes;
+    }
+    char* snap = nullptr;
+    BCHK(hipMalloc((void**)&snap, total));
+    auto copy_state = [&](bool save) -> hipError_t {
+        for (size_t d = 0; d < b->dom.size(); ++d) {
+            lbpf_ctx* c = b->dom[d];
+            size_t o = off[d];
+            for (int f = 0; f < 3; ++f) {
+                const size_t pb = c->np * lattice_of(c, f) * c->sbytes, fb = c->na * c->tbytes;
+                hipError_t e = save ? hipMemcpyAsync(snap + o, c->pop[f][cur0], pb, hipMemcpyDeviceToDevice, b->stream)
+                                    : hipMemcpyAsync(c->pop[f][cur0], snap + o, pb, hipMemcpyDeviceToDevice, b->stream);
+                if (e != hipSuccess) return e;
+                o += pb;
+                e = save ? hipMemcpyAsync(snap + o, c->fld[f][cur0], fb, hipMemcpyDeviceToDevice, b->stream)
+                         : hipMemcpyAsync(c->fld[f][cur0], snap + o, fb, hipMemcpyDeviceToDevice, b->stream);
+                if (e != hipSuccess) return e;
+                o += fb;
+            }
+        }
+        return hipSuccess;
+    };
+    hipError_t e = copy_state(true);
+    hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
+    for (int i = 0; i < 3 && e == hipSuccess; ++i) e = hipEventCreate(&ev[i]);
+    const int s0[2] = {b->shape[0], b->shape[1]}, z0[2] = {b->zslab[0], b->zslab[1]};
+    int bs[2] = {s0[0], s0[1]}, bz[2] = {z0[0], z0[1]};
+    double best[2] = {1e300, 1e300};
+    lbpf_status st = e == hipSuccess ? LBPF_OK : bfail(b, LBPF_EDEVICE, hipGetErrorString(e));
+    const int zs_list[] = {2, 4, 6, 8, 12};
+    for (int sh = 0; sh < kNumShapes && !st; ++sh) {
+        if (!shape_ok(b->storage, sh)) continue;
+        for (int zsl : zs_list) {
+            for (int k = 0; k < 2; ++k) { b->shape[k] = sh; b->zslab[k] = zsl; }
+            st = batch_build(b);
+            int par = cur0;
+            for (int w = 0; w < 2 && !st; ++w) { st = batch_step_once(b, par); par = 1 - par; }
+            double ms[2] = {0, 0};
+            for (int it = 0; it < steps_per_candidate && !st; ++it) {
+                if (hipEventRecord(ev[0], b->stream) != hipSuccess) { st = bfail(b, LBPF_EDEVICE, "event"); break; }
+                st = batch_launch_kernel(b, K_PHI, par);
+                if (!st && hipEventRecord(ev[1], b->stream) != hipSuccess) st = bfail(b, LBPF_EDEVICE, "event");
+                if (!st) st = batch_launch_kernel(b, K_UT, par);
+                if (!st && hipEventRecord(ev[2], b->stream) != hipSuccess) st = bfail(b, LBPF_EDEVICE, "event");
+                if (!st && hipEventSynchronize(ev[2]) != hipSuccess) st = bfail(b, LBPF_EDEVICE, "event sync");
+                float a = 0.f, c2 = 0.f;
+                if (!st && (hipEventElapsedTime(&a, ev[0], ev[1]) != hipSuccess ||
+                            hipEventElapsedTime(&c2, ev[1], ev[2]) != hipSuccess))
+                    st = bfail(b, LBPF_EDEVICE, "event time");
+                ms[0] += a;
+                ms[1] += c2;
+                par = 1 - par;
+            }
+            if (st) break;
+            for (int k = 0; k < 2; ++k) {
+                const double per = ms[k] / steps_per_candidate;
+                if (per < best[k]) { best[k] = per; bs[k] = sh; bz[k] = zsl; }
+            }
+        }
+    }
+    // keep the best launch of each kernel and restore the state
+    for (int k = 0; k < 2; ++k) {
+        b->shape[k] = st ? s0[k] : bs[k];
+        b->zslab[k] = st ? z0[k] : bz[k];
+    }
+    b->built = false;
+    (void)hipStreamSynchronize(b->stream);
+    const hipError_t er = copy_state(false);
+    for (lbpf_ctx* c : b->dom) c->cur = cur0;
+    (void)hipStreamSynchronize(b->stream);
+    for (hipEvent_t x : ev)
+        if (x) (void)hipEventDestroy(x);
+    (void)hipFree(snap);
+    if (st) return st;
+    if (er != hipSuccess) return bfail(b, LBPF_EDEVICE, std::string("restore: ") + hipGetErrorString(er));
+    if (best_ms_per_step) *best_ms_per_step = best[0] + best[1];
     return LBPF_OK;
 }
 

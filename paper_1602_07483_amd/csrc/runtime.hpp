@@ -29,12 +29,19 @@ struct TimedLaunch {
     hipEvent_t a, b;
 };
 
-// Tile shapes (TX x TY threads; a wavefront covers 64/TX rows).
+// Tile shapes (TX x TY threads, one node per thread; a wavefront covers
+// 64/TX rows).
 struct Shape {
     int tx, ty;
 };
 constexpr Shape kShapes[] = {{64, 2}, {64, 4}, {32, 4}, {32, 8}, {32, 16}};
 constexpr int kNumShapes = 5;
+
+// Is tile shape i available for a storage type?  FP64: 64 x 2 and 32 x 4.
+inline bool shape_ok(int storage, int i) {
+    if (storage == LBPF_F64) return i == 0 || i == 2;
+    return i >= 0 && i < kNumShapes;
+}
 
 // The two step kernels, each with a launch of its own.
 enum { K_PHI = 0, K_UT = 1 };
@@ -228,5 +235,12 @@ template <class L, class T, class S>
 lbpf_status launch_phi_s(lbpf_ctx* ctx);
 template <class L, class T, class S>
 lbpf_status launch_ut_s(lbpf_ctx* ctx);
+// One batch launch of k_phi (kernel K_PHI) or k_ut (K_UT) with tile shape id
+// `shape` over nwork (domain, tile) work items, reading the populations and
+// fields of parity par from the DomainDesc<T> array desc; defined in
+// step.hip.  Returns a HIP error code.
+template <class L, class T, class S>
+hipError_t batch_launch_s(int kernel, int shape, const void* desc, const int2* work, int nwork, int par,
+                          hipStream_t stream);
 
 }  // namespace lbpf_rt

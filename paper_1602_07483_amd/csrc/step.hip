@@ -99,6 +99,39 @@ lbpf_status launch_step_s(lbpf_ctx* ctx) {
 template <class L, class T, class S>
 lbpf_status launch_phi_s(lbpf_ctx* ctx) { return launch_k<L, T, S, K_PHI>(ctx); }
 
+namespace {
+template <class L, class T, class S, int TX, int TY>
+hipError_t batch_launch_t(int kernel, const void* desc, const int2* work, int nwork, int par, hipStream_t st) {
+    if (kernel == K_PHI)
+        hipLaunchKernelGGL((k_phi_batch<L, T, S, TX, TY>), dim3(nwork), dim3(TX * TY), 0, st,
+                           (const DomainDesc<T>*)desc, work, par);
+    else
+        hipLaunchKernelGGL((k_ut_batch<L, T, S, TX, TY>), dim3(nwork), dim3(TX * TY), 0, st,
+                           (const DomainDesc<T>*)desc, work, par);
+    return hipGetLastError();
+}
+}  // namespace
+
+template <class L, class T, class S>
+hipError_t batch_launch_s(int kernel, int shape, const void* desc, const int2* work, int nwork, int par,
+                          hipStream_t st) {
+    if constexpr (sizeof(T) == 8) {
+        switch (shape) {
+            case 0: return batch_launch_t<L, T, S, 64, 2>(kernel, desc, work, nwork, par, st);
+            case 2: return batch_launch_t<L, T, S, 32, 4>(kernel, desc, work, nwork, par, st);
+        }
+    } else {
+        switch (shape) {
+            case 0: return batch_launch_t<L, T, S, 64, 2>(kernel, desc, work, nwork, par, st);
+            case 1: return batch_launch_t<L, T, S, 64, 4>(kernel, desc, work, nwork, par, st);
+            case 2: return batch_launch_t<L, T, S, 32, 4>(kernel, desc, work, nwork, par, st);
+            case 3: return batch_launch_t<L, T, S, 32, 8>(kernel, desc, work, nwork, par, st);
+            case 4: return batch_launch_t<L, T, S, 32, 16>(kernel, desc, work, nwork, par, st);
+        }
+    }
+    return hipErrorInvalidValue;
+}
+
 template <class L, class T, class S>
 lbpf_status launch_ut_s(lbpf_ctx* ctx) { return launch_k<L, T, S, K_UT>(ctx); }
 
@@ -126,5 +159,7 @@ using StepL = D3Q19;
 template lbpf_status launch_step_s<StepL, LBPF_STEP_TYPES>(lbpf_ctx*);
 template lbpf_status launch_phi_s<StepL, LBPF_STEP_TYPES>(lbpf_ctx*);
 template lbpf_status launch_ut_s<StepL, LBPF_STEP_TYPES>(lbpf_ctx*);
+template hipError_t batch_launch_s<StepL, LBPF_STEP_TYPES>(int, int, const void*, const int2*, int, int,
+                                                            hipStream_t);
 
 }  // namespace lbpf_rt

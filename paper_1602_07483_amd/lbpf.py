@@ -66,8 +66,10 @@ SYMBOLS = ["lbpf_create", "lbpf_destroy", "lbpf_set_fields", "lbpf_step", "lbpf_
            "lbpf_kernel_times",
            "lbpf_set_launch", "lbpf_get_launch", "lbpf_set_kernel_launch",
            "lbpf_get_kernel_launch", "lbpf_autotune",
-           "lbpf_storage_bytes", "lbpf_bench_copy", "lbpf_last_error", "lbpf_set_graph",
+           "lbpf_storage_bytes", "lbpf_bench_copy", "lbpf_bench_bandwidth",
+           "lbpf_last_error", "lbpf_set_graph",
            "lbpf_batch_create", "lbpf_batch_domain", "lbpf_batch_set_graph", "lbpf_batch_step",
+           "lbpf_batch_set_launch", "lbpf_batch_get_launch", "lbpf_batch_autotune",
            "lbpf_batch_sync", "lbpf_batch_destroy", "lbpf_batch_last_error",
            "lbpf_set_fields_device", "lbpf_read_fields_device"]
 
@@ -112,12 +114,19 @@ def load():
         "lbpf_autotune": ([vp, ctypes.c_int32, dp], ctypes.c_int),
         "lbpf_storage_bytes": ([ctypes.c_int32], ctypes.c_int32),
         "lbpf_bench_copy": ([vp, vp, ctypes.c_int64, vp], ctypes.c_int),
+        "lbpf_bench_bandwidth": ([ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, vp, vp,
+                                  ctypes.c_int64, vp], ctypes.c_int),
         "lbpf_last_error": ([vp], ctypes.c_char_p),
         "lbpf_set_graph": ([vp, ctypes.c_int32], ctypes.c_int),
         "lbpf_batch_create": ([ctypes.c_int32, P(lbpf_grid), P(lbpf_params), vp, P(vp)], ctypes.c_int),
         "lbpf_batch_domain": ([vp, ctypes.c_int32], vp),
         "lbpf_batch_set_graph": ([vp, ctypes.c_int32], ctypes.c_int),
         "lbpf_batch_step": ([vp, ctypes.c_int64], ctypes.c_int),
+        "lbpf_batch_set_launch": ([vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32],
+                                  ctypes.c_int),
+        "lbpf_batch_get_launch": ([vp, ctypes.c_int32, P(ctypes.c_int32), P(ctypes.c_int32), P(ctypes.c_int32)],
+                                  ctypes.c_int),
+        "lbpf_batch_autotune": ([vp, ctypes.c_int32, dp], ctypes.c_int),
         "lbpf_batch_sync": ([vp], ctypes.c_int),
         "lbpf_batch_destroy": ([vp], ctypes.c_int),
         "lbpf_batch_last_error": ([vp], ctypes.c_char_p),
@@ -150,6 +159,12 @@ def lbpf_storage_bytes(storage):
 def lbpf_bench_copy(dst_ptr, src_ptr, nbytes, stream_ptr=0):
     return lib().lbpf_bench_copy(ctypes.c_void_p(dst_ptr), ctypes.c_void_p(src_ptr),
                                  int(nbytes), ctypes.c_void_p(stream_ptr))
+
+
+def lbpf_bench_bandwidth(mode, width, nontemporal, blocks, dst_ptr, src_ptr, nbytes, stream_ptr=0):
+    return lib().lbpf_bench_bandwidth(int(mode), int(width), int(nontemporal), int(blocks),
+                                      ctypes.c_void_p(dst_ptr), ctypes.c_void_p(src_ptr or 0),
+                                      int(nbytes), ctypes.c_void_p(stream_ptr))
 
 
 def make_structs(nx, ny, nz, lattice=19, walls=(0,) * 6, storage="f32", dx=1.0, dt=1.0,
@@ -389,6 +404,22 @@ class Batch:
 
     def set_graph(self, steps_per_graph):
         self._check(self._lib.lbpf_batch_set_graph(self._h, int(steps_per_graph)))
+
+    def set_launch(self, kernel, tile_x, tile_y, zslab):
+        """kernel 0: k_phi, 1: k_ut (all domains)."""
+        self._check(self._lib.lbpf_batch_set_launch(self._h, int(kernel), int(tile_x), int(tile_y), int(zslab)))
+
+    def get_launch(self, kernel):
+        a, b, c = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        self._check(self._lib.lbpf_batch_get_launch(self._h, int(kernel), ctypes.byref(a), ctypes.byref(b),
+                                                    ctypes.byref(c)))
+        return a.value, b.value, c.value
+
+    def autotune(self, steps_per_candidate=4):
+        """Returns ({"k_phi": (tx, ty, zslab), "k_ut": ...}, best ms per batch step)."""
+        best = ctypes.c_double()
+        self._check(self._lib.lbpf_batch_autotune(self._h, int(steps_per_candidate), ctypes.byref(best)))
+        return {"k_phi": self.get_launch(0), "k_ut": self.get_launch(1)}, best.value
 
     def close(self):
         if getattr(self, "_h", None):

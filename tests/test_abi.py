@@ -54,6 +54,9 @@ def test_storage_bytes_and_invalid_arguments_without_gpu():
     assert L.lbpf_create(ctypes.byref(g), ctypes.byref(p), None, ctypes.byref(h)) == lbpf.LBPF_EINVAL
     assert not h.value
     assert L.lbpf_bench_copy(None, None, 16, None) == lbpf.LBPF_EINVAL
+    for bad in ((3, 16, 0, 0, 16), (0, 3, 0, 0, 16), (2, 16, 0, -1, 16), (2, 16, 0, 0, 12)):
+        assert L.lbpf_bench_bandwidth(bad[0], bad[1], bad[2], bad[3], None, None, bad[4],
+                                      None) == lbpf.LBPF_EINVAL
     assert L.lbpf_destroy(None) == lbpf.LBPF_OK
     # batched domains take the single-domain lattices; checked before any device call
     g.nx, g.lattice = 8, 17

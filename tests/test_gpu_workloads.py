@@ -15,7 +15,7 @@ import pytest
 from paper_1602_07483_amd import lbpf
 from paper_1602_07483_amd.inputs import (workload_thermal2d, workload_octant, workload_centred,
                                          workload_ensemble, workload_multiseed)
-from tests.pairs import make_oracle, make_gpu, maxabs
+from tests.pairs import make_oracle, make_gpu, maxabs, fp32_bound
 
 pytestmark = pytest.mark.gpu
 
@@ -54,7 +54,7 @@ def free_growth(tips, reach):
     return inside[:-1] & inside[1:]
 
 
-@pytest.mark.parametrize("storage,tol", [("f64", 1e-11), ("f32", 1e-5)])
+@pytest.mark.parametrize("storage,tol", [("f64", 1e-12), ("f32", 1e-5)])
 def test_quasi2d_slab_matches_oracle(storage, tol):
     """nz = 1 with mirror z-walls (the D2Q9 reduction of D3Q19): fields after
     300 steps of the 2D thermal dendrite parameters."""
@@ -69,11 +69,11 @@ def test_quasi2d_slab_matches_oracle(storage, tol):
         assert maxabs(a, b) <= tol
 
 
-def test_thermal2d_tip_velocity_matches_oracle_and_paper():
+def test_thermal2d_tip_velocity_matches_oracle():
     """Sec. 4.1, anisotropic thermal dendrite, Delta = 0.55: FP32 GPU run of
-    37 500 steps (T = 300) against the oracle's trace; the dimensionless
-    velocity V_p = V d0 / kappa at T = 300 within the paper's 4 % spread of
-    the sharp-interface Green's-function value 0.0170 it quotes."""
+    37 500 steps (T = 300) against the oracle's trace: tip positions within
+    0.05 node and the tip velocity within 1 % past the initial transient.
+    The paper's values at this resolution are printed beside it."""
     g = golden("thermal2d")
     pb = workload_thermal2d()
     hist = run_trace(pb, "f32")
@@ -90,17 +90,56 @@ def test_thermal2d_tip_velocity_matches_oracle_and_paper():
     assert rel.max() < 0.01
     d0 = 0.8839 / pb.lam                       # a1 W0 / lambda
     vp = vg[-1] * pb.dx / pb.dt * d0 / pb.kappa
-    print("thermal2d V_p(T=300): GPU %.5f" % vp)
-    assert abs(vp - 0.0170) / 0.0170 < 0.04
+    print("thermal2d V_p(T=300): GPU %.5f (paper: LB 0.01735, FD/MC 0.01667, GF 0.0170)" % vp)
+
+
+def _thermal2d_vp(dx, box=200.0, T=300.0, **over):
+    """V_p at time T of the Sec. 4.1 thermal dendrite refined to dx/W0
+    (dt proportional to dx^2, seed radius 4 W0) in a box of `box` W0,
+    FP32, theta alone."""
+    pb = workload_thermal2d(n=int(round(box / dx)), dx=dx)
+    pb.steps = int(round(T / pb.dt))
+    pb.reduce_every = int(round(4.0 / pb.dt))
+    s = make_gpu(pb, "f32", skip_U=1, **over)
+    s.step(pb.steps)
+    hist = s.history()
+    st, red = s.read_status()
+    s.close()
+    assert st == lbpf.LBPF_OK, red
+    tips = np.array([h["tip"][0] for h in hist])
+    steps = np.array([h["step"] for h in hist], dtype=float)
+    v = np.diff(tips)[-1] / np.diff(steps)[-1] * pb.dx / pb.dt
+    return v * (0.8839 / pb.lam) / pb.kappa
+
+
+def test_thermal2d_refinement_converges_to_the_green_function_value():
+    """The same dendrite at dx/W0 = 0.4, 0.3, 0.2 (dt proportional to dx^2,
+    T = 300, the 200 W0 quadrant of the paper): V_p rises by equal steps for
+    equal steps of dx, i.e. the scheme converges at first order, and the
+    first-order extrapolation to dx = 0 lies within 1 % of the
+    Green's-function value 0.0170 that Sec. 4.1 quotes.  At dx/W0 = 0.4 it
+    equals the oracle's stored value (tests/golden/trace_thermal2d.json)
+    within 0.1 %."""
+    v = {h: _thermal2d_vp(h) for h in (0.4, 0.3, 0.2)}
+    d1, d2 = v[0.3] - v[0.4], v[0.2] - v[0.3]
+    v0 = 2.0 * v[0.2] - v[0.4]
+    print("V_p(T=300) at dx/W0 = 0.4, 0.3, 0.2: %.5f %.5f %.5f; extrapolated %.5f (%+.2f %% from 0.0170)"
+          % (v[0.4], v[0.3], v[0.2], v0, 100 * (v0 / 0.0170 - 1)))
+    assert d1 > 0 and d2 > 0 and 0.6 < d1 / d2 < 1.6
+    assert abs(v0 - 0.0170) / 0.0170 < 0.01
+    g = golden("thermal2d")
+    pb = workload_thermal2d()
+    to = [r["tip"][0] for r in g["trace"]]
+    vo = (to[-1] - to[-2]) / pb.reduce_every * pb.dx / pb.dt * (0.8839 / pb.lam) / pb.kappa
+    assert abs(v[0.4] - vo) / vo < 1e-3
 
 
 def test_thermal2d_tip_velocity_paper_lattices():
     """Sec. 4.1's own lattice pair: the phase field on D2Q9 and theta on
     D2Q5, here a one-node slab with phi on D3Q19 (D2Q9 after the mirror
     reduction) and theta on D3Q7 (a D2Q5), pure substance (theta alone),
-    FP32, T = 300.  V_p within the paper's 4 % spread of the Green's-function
-    value 0.0170; its distance to the paper's LB value 0.01735 is printed
-    (the all-D2Q9 slab lies 5.6 % below it)."""
+    FP32, T = 300: V_p within 0.5 % of the all-D2Q9 value of the oracle's
+    stored run, so the theta lattice does not move the tip velocity."""
     pb = workload_thermal2d()
     s = make_gpu(pb, "f32", skip_U=1, lattice_ut=7)
     s.step(pb.steps)
@@ -112,9 +151,10 @@ def test_thermal2d_tip_velocity_paper_lattices():
     v = velocities(None, tips, pb.reduce_every)
     d0 = 0.8839 / pb.lam
     vp = v[-1] * pb.dx / pb.dt * d0 / pb.kappa
-    print("thermal2d D2Q9 phi + D2Q5 theta: V_p(T=300) %.5f (%.2f %% from 0.01735, %.2f %% from 0.0170)"
-          % (vp, 100 * (vp / 0.01735 - 1), 100 * (vp / 0.0170 - 1)))
-    assert abs(vp - 0.0170) / 0.0170 < 0.04
+    to = [r["tip"][0] for r in golden("thermal2d")["trace"]]
+    vo = (to[-1] - to[-2]) / pb.reduce_every * pb.dx / pb.dt * d0 / pb.kappa
+    print("thermal2d D2Q9 phi + D2Q5 theta: V_p(T=300) %.5f, all-D2Q9 oracle %.5f" % (vp, vo))
+    assert abs(vp - vo) / vo < 0.005
 
 
 def test_octant128_tip_velocity_matches_oracle():
@@ -137,12 +177,12 @@ def test_octant128_tip_velocity_matches_oracle():
     assert ok.sum() >= 5 and rel.max() < 0.01
 
 
-@pytest.mark.parametrize("storage,bound", [("f32", 0.01), ("f16", 0.02), ("bf16", 0.05)])
+@pytest.mark.parametrize("storage,bound", [("f32", 0.01), ("f16", 0.01), ("bf16", 0.01)])
 def test_centred256_tip_velocity_matches_oracle(storage, bound):
     """256^3 centred seed, 10 000 steps, FP64 reductions every 100 steps,
     against the oracle's trace of the equivalent octant (mirror walls through
-    the seed centre): tip velocity (FP32 within 1 %; mixed storage reported
-    with a loose bound), solid fraction, and solute-mass drift."""
+    the seed centre): tip velocity within 1 % (FP32 and mixed storage),
+    solid fraction, and solute-mass drift."""
     g = golden("centred256")
     pb = workload_centred(256, 10000)
     hist = run_trace(pb, storage)
@@ -169,13 +209,14 @@ def test_ensemble_health_and_sampled_parity():
     largest domain of each lattice against the oracle after 200 steps
     (FP32 batch, element by element).
 
-    Tolerance 2e-5: the largest D3Q19 domain (95^3, Delta = 0.52,
-    eps = 0.061) grows fastest, and there the rounding of the FP32 state
-    (one rounding of phi, U, theta per node and step) is amplified by the
-    growing tips about 1.5x every 25 steps after step 75, to about 1.2e-5
-    at step 200; the same algorithm with every double of the oracle
-    replaced by float reaches 2.0e-5.  The 1e-5 bar is checked on the
-    small workload and the ragged cases."""
+    Tolerance per domain and field: 1e-5, or what the oracle's own
+    algorithm rounded to float reaches on that domain after 200 steps where
+    that is larger (tests/golden/fp32_rounding.json, written by
+    tests/golden/make_fp32_rounding.py).  The largest D3Q19 domain (95^3,
+    Delta = 0.52, eps = 0.061) grows fastest; the growing tips amplify the
+    rounding of any FP32 state (one rounding of phi, U, theta per node and
+    step) about 1.5x every 25 steps after step 75, and the float algorithm
+    reaches 1.9e-5 on phi there, the GPU about 1.2e-5."""
     probs = workload_ensemble()
     b = lbpf.Batch([lbpf.problem_kwargs(p) for p in probs], storage="f16")
     for d, p in zip(b.domains, probs):
@@ -209,7 +250,8 @@ def test_ensemble_health_and_sampled_parity():
         ophi, oU, oth = o.fields()
         print("%s (Q%d, %d^3): max|dphi| %.2e max|dU| %.2e" % (p.name, p.lattice, p.nx,
                                                               maxabs(phi, ophi), maxabs(U, oU)))
-        assert maxabs(phi, ophi) <= 2e-5 and maxabs(U, oU) <= 2e-5 and maxabs(th, oth) <= 2e-5
+        for f, (got, want) in enumerate(((phi, ophi), (U, oU), (th, oth))):
+            assert maxabs(got, want) <= fp32_bound(p.name, f), (p.name, f, maxabs(got, want))
     b.close()
 
 

@@ -26,32 +26,86 @@ def load(name):
         return json.load(fh)
 
 
-def test_thermal2d_tip_velocity_against_paper():
-    """Sec. 4.1, anisotropic thermal dendrite at Delta = 0.55, T = 300: the
-    paper's LB code gives V_p = 0.01735, its finite-difference/Monte-Carlo
-    code 0.01667 (4 % apart), and it quotes the sharp-interface
-    Green's-function value 0.0170 and Karma & Rappel's 0.0174.  The oracle,
-    run as a one-node D3Q19 slab (D2Q9 after the mirror reduction), must lie
-    within the paper's own 4 % spread of the Green's-function value and of
-    the FD/MC value.  (It lies 5.6 % below the paper's LB value.)"""
+def _vp(trace, pb):
+    """V_p = V d0 / kappa of each record interval (Sec. 4.1), with the
+    record times T = step dt / tau0."""
+    steps = np.array([r["step"] for r in trace], dtype=float)
+    tips = np.array([r["tip"][0] for r in trace])
+    d0 = 0.8839 * pb.W0 / pb.lam                           # a1 W0 / lambda
+    v = np.diff(tips) / np.diff(steps) * pb.dx / pb.dt     # W0 / tau0 units
+    return steps[1:] * pb.dt / pb.tau0, v * d0 / pb.kappa
+
+
+def test_thermal2d_tip_velocity_at_the_paper_resolution():
+    """Sec. 4.1, anisotropic thermal dendrite at Delta = 0.55, delta x/W0 =
+    0.4, T = 300, as a one-node D3Q19 slab (D2Q9 after the mirror
+    reduction): the oracle's V_p is steady (the last third changes by under
+    1 %) and symmetric in x and y.  The paper prints V_p = 0.01735 for its
+    LB code at this resolution, 0.01667 for its FD/MC code, and quotes the
+    sharp-interface Green's-function value 0.0170 and Karma & Rappel's
+    0.0174.  The oracle gives 0.01638: 5.6 % below the paper's LB value,
+    3.6 % below the Green's-function value.  That gap is discretisation
+    error of the scheme at this resolution: under refinement the oracle's
+    V_p converges, at first order in delta x, to the Green's-function value
+    (test_thermal2d_refinement_converges_to_the_green_function_value)."""
     g = load("thermal2d")
     pb = inputs.workload_thermal2d()
     tr = g["trace"]
     assert tr[-1]["step"] == 37500 and tr[-1]["nonfinite"] == 0
-    tips = np.array([r["tip"][0] for r in tr])
-    v = np.diff(tips) / pb.reduce_every                  # lattice units per step
-    d0 = 0.8839 * pb.W0 / pb.lam                           # a1 W0 / lambda
-    vp = v * pb.dx / pb.dt * d0 / pb.kappa
-    print("V_p(T=300) = %.5f; vs 0.0170 %+.1f %%, vs 0.01667 %+.1f %%, vs 0.01735 %+.1f %%"
-          % (vp[-1], 100 * (vp[-1] / 0.0170 - 1), 100 * (vp[-1] / 0.01667 - 1),
-             100 * (vp[-1] / 0.01735 - 1)))
-    assert abs(vp[-1] - 0.0170) / 0.0170 < 0.04
-    assert abs(vp[-1] - 0.01667) / 0.01667 < 0.04
-    # steady state reached: the last third changes by under 1 %
+    T, vp = _vp(tr, pb)
+    print("V_p(T=300) = %.5f; vs the paper's LB 0.01735 %+.1f %%, FD/MC 0.01667 %+.1f %%, GF 0.0170 %+.1f %%"
+          % (vp[-1], 100 * (vp[-1] / 0.01735 - 1), 100 * (vp[-1] / 0.01667 - 1), 100 * (vp[-1] / 0.0170 - 1)))
     late = vp[2 * len(vp) // 3:]
     assert (late.max() - late.min()) / late.mean() < 0.01
-    # the tip stays on the x axis and the quadrant is symmetric in x and y
     assert abs(tr[-1]["tip"][0] - tr[-1]["tip"][1]) < 1e-9
+
+
+def test_thermal2d_gradient_stencil_is_not_the_gap():
+    """The one discretisation choice left open for the 2D runs, the
+    gradient stencil of phi (reading R5, axis central differences), against
+    its isotropic lattice variant (oracle grad_stencil = 1): V_p(T = 300)
+    agrees within 0.5 %, so the stencil does not explain the 5.6 % gap to the
+    paper's LB value."""
+    pb = inputs.workload_thermal2d()
+    _, va = _vp(load("thermal2d")["trace"], pb)
+    g = load("thermal2d_isograd")
+    assert g["oracle_options"] == {"skip_U": 1, "grad_stencil": 1}
+    _, vi = _vp(g["trace"], pb)
+    print("V_p(T=300): axis stencil %.5f, isotropic %.5f" % (va[-1], vi[-1]))
+    assert abs(vi[-1] - va[-1]) / va[-1] < 0.005
+
+
+def test_thermal2d_refinement_converges_to_the_green_function_value():
+    """The oracle's V_p under refinement, delta x/W0 = 0.4, 0.3, 0.2 with
+    dt proportional to delta x^2 (all relaxation times fixed), seed radius
+    4 W0, in a 100 W0 quadrant up to T = 150 (tests/golden/make_traces.py):
+    V_p(T = 150) rises monotonically, by about equal steps for equal steps
+    of delta x (first-order convergence).  Extrapolating the T = 300 value
+    at delta x/W0 = 0.4 to delta x = 0 with that first-order slope gives the
+    converged V_p, which must lie within 1 % of the sharp-interface
+    Green's-function value 0.0170 the paper quotes (Sec. 4.1): the scheme
+    converges to the right answer and its 3.6 % deficit at delta x/W0 = 0.4
+    is discretisation error."""
+    v150 = {}
+    for h in (0.4, 0.3, 0.2):
+        g = load("thermal2d_dx%g_T150" % h)
+        assert g["oracle_options"] == {"skip_U": 1}
+        p = g["problem"]
+        pb = inputs.workload_thermal2d(n=p["nx"], dx=h)
+        assert abs(p["dt"] - pb.dt) < 1e-15 and p["radius"] == pb.radius
+        T, vp = _vp(g["trace"], pb)
+        assert abs(T[-1] - 150.0) < 1e-9
+        v150[h] = vp[-1]
+    d1, d2 = v150[0.3] - v150[0.4], v150[0.2] - v150[0.3]
+    slope = (v150[0.2] - v150[0.4]) / 0.2
+    _, v300 = _vp(load("thermal2d")["trace"], inputs.workload_thermal2d())
+    v0 = v300[-1] + slope * 0.4
+    print("V_p(T=150) at dx/W0 = 0.4, 0.3, 0.2: %.5f %.5f %.5f; first-order slope %.5f per W0; "
+          "converged V_p(T=300) %.5f (%+.2f %% from 0.0170)" % (v150[0.4], v150[0.3], v150[0.2], slope, v0,
+                                                                100 * (v0 / 0.0170 - 1)))
+    assert d1 > 0 and d2 > 0
+    assert 0.6 < d1 / d2 < 1.6
+    assert abs(v0 - 0.0170) / 0.0170 < 0.01
 
 
 @pytest.mark.parametrize("name,factory,steps", [

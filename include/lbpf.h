@@ -354,6 +354,29 @@ lbpf_status lbpf_bench_copy(void* dst, const void* src, int64_t nbytes, void* hi
 lbpf_status lbpf_bench_bandwidth(int32_t mode, int32_t width, int32_t nontemporal, int32_t blocks, void* dst,
                                  const void* src, int64_t nbytes, void* hip_stream);
 
+/* Reductions of caller-held device fields, allocating nothing -- for callers
+ * that cannot allocate device memory: code under HIP graph capture, serving
+ * loops, harnesses that forbid hipMalloc.  A variant of the reduction record
+ * of lbpf_read (same kernels, same grid, so the same values bit for bit) that
+ * needs no context: phi, U, theta are device arrays of the current device,
+ * [nz][ny][nx] with x fastest and no padding, element type dtype
+ * (LBPF_FIELD_F32 or _F64); k and dx as in lbpf_params; centre is a host
+ * array of 3 doubles (node units).  rec receives, in device memory, 12
+ * doubles: step (always 0), solid fraction, solute mass, enthalpy, tip x, y,
+ * z (minus centre; NaN when no crossing), phi min, phi max, non-finite
+ * count, sum U, sum phi -- the fields of lbpf_reductions in that order.
+ * Asynchronous on hip_stream.  The per-block partial sums live in a fixed
+ * scratch array of 1024 x 16 doubles (128 KiB) in the library's device
+ * image, one per device, kept until the process ends: calls that overlap on
+ * one device race on it and must be serialised (one stream, or events).
+ * Every call rewrites the whole part of the scratch it reads, so nothing
+ * must be cleared between calls.  At most 2^31 nodes.  No hipMalloc, no
+ * hipFree, no memset.  Errors (lbpf_last_error(NULL)): EINVAL (NULL
+ * pointer, bad dtype, n < 1 or > 2^31, k outside (0,1), dx <= 0), EDEVICE. */
+lbpf_status lbpf_reduce_fields_noalloc(const void* phi, const void* U, const void* theta, int32_t dtype,
+                                       int32_t nx, int32_t ny, int32_t nz, double k, double dx,
+                                       const double* centre, double* rec, void* hip_stream);
+
 /* Description of the last error on ctx (or of the last failed creation when
  * ctx is NULL); valid until the next call on the same context. */
 const char* lbpf_last_error(const lbpf_ctx* ctx);

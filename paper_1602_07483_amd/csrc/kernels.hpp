@@ -1065,6 +1065,7 @@ __global__ __launch_bounds__(256) void k_stream_only(int nx, int ny, int nz, int
 enum { RV_SOLID = 0, RV_MASS, RV_ENTH, RV_SUMU, RV_SUMPHI, RV_BAD, RV_NSUM,   // sums
        RV_TIPX = RV_NSUM, RV_TIPY, RV_TIPZ, RV_PMAX, RV_NEG_PMIN, RV_COUNT };   // maxima
 constexpr int RED_STRIDE = 16;   // doubles per partial / record slot
+constexpr int RED_BLOCKS_NOALLOC = 1024;   // partial records of the allocation-free reduction
 
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll

@@ -7,6 +7,8 @@
 // buffers; the parity `cur` names the current state.
 #include "runtime.hpp"
 
+#include <mutex>
+
 // The library's two non-template kernels, defined in this translation unit
 // only (the step translation units include kernels.hpp too).
 namespace lbpf {
@@ -123,9 +125,40 @@ void launch_bw_mode(int mode, int nt, int nb, hipStream_t st, const void* src, v
 
 }  // namespace lbpf
 
+// Scratch of the reduction entry point that allocates nothing
+// (lbpf_reduce_fields_noalloc): the per-block partial records of
+// k_reduce_part, RED_BLOCKS x RED_STRIDE doubles (128 KiB) on every device
+// the library runs on, held until the process ends.  Host code never uses
+// this name as an address: the device address comes from
+// hipGetSymbolAddress, once per device (scratch_on_device).
+static __device__ __align__(256) double scratch[lbpf::RED_BLOCKS_NOALLOC * lbpf::RED_STRIDE];
+
 using namespace lbpf;
 using namespace lbpf_rt;
 
+namespace {
+// Device address of `scratch` on each device, taken once per device with that
+// device current (each device holds its own copy of the array).
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+hipError_t scratch_on_device(void** out) {
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return hipSuccess;
+}
+}  // namespace
 
 namespace {
 thread_local std::string g_create_error;
@@ -1047,6 +1080,45 @@ lbpf_status lbpf_bench_bandwidth(int32_t mode, int32_t width, int32_t nontempora
     else if (width == 8) launch_bw_mode<u32x2>(mode, nontemporal, nb, st, src, dst, n);
     else launch_bw_mode<u32x4>(mode, nontemporal, nb, st, src, dst, n);
     return hipGetLastError() == hipSuccess ? LBPF_OK : LBPF_EDEVICE;
+}
+
+lbpf_status lbpf_reduce_fields_noalloc(const void* phi, const void* U, const void* theta, int32_t dtype,
+                                       int32_t nx, int32_t ny, int32_t nz, double k, double dx,
+                                       const double* centre, double* rec, void* hip_stream) {
+    if (!phi || !U || !theta || !centre || !rec)
+        return fail(nullptr, LBPF_EINVAL, "lbpf_reduce_fields_noalloc: NULL argument");
+    if (dtype != LBPF_FIELD_F32 && dtype != LBPF_FIELD_F64)
+        return fail(nullptr, LBPF_EINVAL, "lbpf_reduce_fields_noalloc: dtype must be 0 (FP32) or 1 (FP64)");
+    if (nx < 1 || ny < 1 || nz < 1)
+        return fail(nullptr, LBPF_EINVAL, "lbpf_reduce_fields_noalloc: nx, ny, nz must be >= 1");
+    const size_t n = (size_t)nx * (size_t)ny * (size_t)nz;
+    if (n > kNoallocMaxNodes)
+        return fail(nullptr, LBPF_EINVAL,
+                    "lbpf_reduce_fields_noalloc: more than 2^31 nodes (the limit of this entry point)");
+    if (!(k > 0.0 && k < 1.0) || !(dx > 0.0))
+        return fail(nullptr, LBPF_EINVAL, "lbpf_reduce_fields_noalloc: k must lie in (0,1) and dx be > 0");
+    void* part = nullptr;
+    hipError_t e = scratch_on_device(&part);
+    if (e != hipSuccess)
+        return fail(nullptr, LBPF_EDEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    const hipStream_t st = (hipStream_t)hip_stream;
+    // same grid as the context reductions: results equal theirs bit for bit
+    const int nb = (int)std::min<size_t>(RED_BLOCKS_NOALLOC, (n + 255) / 256);
+    if (dtype == LBPF_FIELD_F64)
+        hipLaunchKernelGGL((k_reduce_part<double>), dim3(nb), dim3(256), 0, st, nx, ny, nz, nx, k, dx * dx * dx,
+                           (const double*)phi, (const double*)U, (const double*)theta, (double*)part);
+    else
+        hipLaunchKernelGGL((k_reduce_part<float>), dim3(nb), dim3(256), 0, st, nx, ny, nz, nx, k, dx * dx * dx,
+                           (const float*)phi, (const float*)U, (const float*)theta, (double*)part);
+    e = hipGetLastError();
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(256), 0, st, (const double*)part, nb, 1.0 / (double)n,
+                           centre[0], centre[1], centre[2], 0LL, rec);
+        e = hipGetLastError();
+    }
+    if (e != hipSuccess)
+        return fail(nullptr, LBPF_EDEVICE, std::string("lbpf_reduce_fields_noalloc: ") + hipGetErrorString(e));
+    return LBPF_OK;
 }
 
 lbpf_status lbpf_bench_copy(void* dst, const void* src, int64_t nbytes, void* hip_stream) {

@@ -23,6 +23,7 @@ using namespace lbpf;
 
 constexpr int HIST_CAP = 8192;
 constexpr int RED_BLOCKS = 1024;
+constexpr size_t kNoallocMaxNodes = (size_t)1 << 31;   // lbpf_reduce_fields_noalloc
 
 struct TimedLaunch {
     int kind;

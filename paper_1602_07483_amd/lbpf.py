@@ -66,7 +66,7 @@ SYMBOLS = ["lbpf_create", "lbpf_destroy", "lbpf_set_fields", "lbpf_step", "lbpf_
            "lbpf_kernel_times",
            "lbpf_set_launch", "lbpf_get_launch", "lbpf_set_kernel_launch",
            "lbpf_get_kernel_launch", "lbpf_autotune",
-           "lbpf_storage_bytes", "lbpf_bench_copy", "lbpf_bench_bandwidth",
+           "lbpf_storage_bytes", "lbpf_bench_copy", "lbpf_bench_bandwidth", "lbpf_reduce_fields_noalloc",
            "lbpf_last_error", "lbpf_set_graph",
            "lbpf_batch_create", "lbpf_batch_domain", "lbpf_batch_set_graph", "lbpf_batch_step",
            "lbpf_batch_set_launch", "lbpf_batch_get_launch", "lbpf_batch_autotune",
@@ -114,6 +114,9 @@ def load():
         "lbpf_autotune": ([vp, ctypes.c_int32, dp], ctypes.c_int),
         "lbpf_storage_bytes": ([ctypes.c_int32], ctypes.c_int32),
         "lbpf_bench_copy": ([vp, vp, ctypes.c_int64, vp], ctypes.c_int),
+        "lbpf_reduce_fields_noalloc": ([vp, vp, vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                        ctypes.c_int32, ctypes.c_double, ctypes.c_double,
+                                        P(ctypes.c_double), vp, vp], ctypes.c_int),
         "lbpf_bench_bandwidth": ([ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, vp, vp,
                                   ctypes.c_int64, vp], ctypes.c_int),
         "lbpf_last_error": ([vp], ctypes.c_char_p),
@@ -165,6 +168,17 @@ def lbpf_bench_bandwidth(mode, width, nontemporal, blocks, dst_ptr, src_ptr, nby
     return lib().lbpf_bench_bandwidth(int(mode), int(width), int(nontemporal), int(blocks),
                                       ctypes.c_void_p(dst_ptr), ctypes.c_void_p(src_ptr or 0),
                                       int(nbytes), ctypes.c_void_p(stream_ptr))
+
+
+def lbpf_reduce_fields_noalloc(phi_ptr, U_ptr, theta_ptr, dtype, nx, ny, nz, k, dx, centre, rec_ptr,
+                               stream_ptr=0):
+    """Reduction record of device fields into 12 device doubles at rec_ptr,
+    with no allocation (see include/lbpf.h)."""
+    c = (ctypes.c_double * 3)(*[float(v) for v in centre])
+    return lib().lbpf_reduce_fields_noalloc(ctypes.c_void_p(phi_ptr), ctypes.c_void_p(U_ptr),
+                                            ctypes.c_void_p(theta_ptr), int(dtype), int(nx), int(ny), int(nz),
+                                            float(k), float(dx), c, ctypes.c_void_p(rec_ptr),
+                                            ctypes.c_void_p(stream_ptr))
 
 
 def make_structs(nx, ny, nz, lattice=19, walls=(0,) * 6, storage="f32", dx=1.0, dt=1.0,

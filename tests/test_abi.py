@@ -54,6 +54,14 @@ def test_storage_bytes_and_invalid_arguments_without_gpu():
     assert L.lbpf_create(ctypes.byref(g), ctypes.byref(p), None, ctypes.byref(h)) == lbpf.LBPF_EINVAL
     assert not h.value
     assert L.lbpf_bench_copy(None, None, 16, None) == lbpf.LBPF_EINVAL
+    # the allocation-free reduction validates before any device call
+    c3 = (ctypes.c_double * 3)(0.0, 0.0, 0.0)
+    okp = ctypes.c_void_p(16)
+    for args in ((None, okp, okp, 0, 4, 4, 4, 0.15, 1.0), (okp, okp, okp, 2, 4, 4, 4, 0.15, 1.0),
+                 (okp, okp, okp, 0, 0, 4, 4, 0.15, 1.0), (okp, okp, okp, 0, 4096, 4096, 4096, 0.15, 1.0),
+                 (okp, okp, okp, 0, 4, 4, 4, 1.5, 1.0), (okp, okp, okp, 0, 4, 4, 4, 0.15, 0.0)):
+        assert L.lbpf_reduce_fields_noalloc(*args, c3, okp, None) == lbpf.LBPF_EINVAL
+    assert b"noalloc" in L.lbpf_last_error(None)
     for bad in ((3, 16, 0, 0, 16), (0, 3, 0, 0, 16), (2, 16, 0, -1, 16), (2, 16, 0, 0, 12)):
         assert L.lbpf_bench_bandwidth(bad[0], bad[1], bad[2], bad[3], None, None, bad[4],
                                       None) == lbpf.LBPF_EINVAL

@@ -395,7 +395,9 @@ const char* lbpf_last_error(const lbpf_ctx* ctx);
  * when it is stepped alone; the batch kernels are compiled separately and
  * may contract floating-point operations differently, so FP32 results agree
  * with the single-domain ones to a few units in the last place, not bit for
- * bit.  Launch shape and step chunking do not change the batch's results. */
+ * bit.  Step chunking and graph replay do not change the batch's results;
+ * another tile shape (lbpf_batch_set_launch) is another instantiation of the
+ * batch kernels and may round a few ulp differently. */
 lbpf_status lbpf_batch_create(int32_t n, const lbpf_grid* grids, const lbpf_params* params,
                               void* hip_stream, lbpf_batch** out);
 /* Domain i (borrowed pointer, valid until lbpf_batch_destroy); NULL if out of range. */

@@ -8,7 +8,7 @@ import pytest
 
 from oracle import Oracle, R_SOLID, R_MASS, R_ENTHALPY, R_TIPX, R_TIPY, R_TIPZ
 from paper_1602_07483_amd import lbpf
-from paper_1602_07483_amd.inputs import Problem, workload_small, workload_octant, NOFLUX, SYMMETRY, DT
+from paper_1602_07483_amd.inputs import workload_interior, Problem, workload_small, workload_octant, NOFLUX, SYMMETRY, DT
 from tests.pairs import make_oracle, make_gpu, maxabs
 
 pytestmark = pytest.mark.gpu
@@ -27,9 +27,13 @@ def fields(s):
     return phi, U, th
 
 
-def test_launch_shape_does_not_change_results():
-    """Tile shape, slab height and XCD order change speed only: bit-identical fields."""
-    pb = ragged()
+@pytest.mark.parametrize("case", ["ragged", "interior"])
+def test_launch_shape_does_not_change_results(case):
+    """Tile shape, slab height and XCD order change speed only: bit-identical
+    fields, on the ragged case (every tile touches a wall) and on the
+    136x40x24 interior case (some tiles of every shape take the wall-free
+    path, others the wall path)."""
+    pb = ragged() if case == "ragged" else workload_interior()
     ref = None
     for launch in [(32, 8, 6, 1), (64, 2, 8, 1), (32, 4, 2, 0), (64, 4, 16, 1), (32, 16, 4, 1), (32, 8, 1, 0)]:
         s = make_gpu(pb, "f32")
@@ -125,6 +129,63 @@ def test_batch_graph_and_chunking_are_bit_exact():
         for a, b in zip(outs[0], other):
             for x, y in zip(a, b):
                 assert np.array_equal(x, y)
+
+
+@pytest.mark.parametrize("storage", ["f32", "f16"])
+def test_batch_launch_and_autotune(storage):
+    """Batch launches per kernel (tile shape and z slab for k_phi and k_ut
+    apart) and the batch autotuner.  Another tile shape is another
+    instantiation of the batch kernels, whose constants come from a
+    descriptor, so the compiler may contract multiply-adds differently:
+    after 20 steps the fields agree with the default launch to a few ulp.
+    The tuner restores every domain's state: a batch tuned after 6 steps and
+    stepped 14 more equals, bit for bit, one set to the tuned launches by
+    hand at the same point (graph replay captured again after each change)."""
+    probs = _batch_problems()
+
+    def run(setup):
+        b = lbpf.Batch([lbpf.problem_kwargs(p) for p in probs], storage=storage)
+        for d, p in zip(b.domains, probs):
+            d.set_fields(*p.initial_fields())
+        b.set_graph(4)
+        b.step(6)
+        setup(b)
+        b.step(14)
+        out = [fields(d) for d in b.domains]
+        launches = (b.get_launch(0), b.get_launch(1))
+        b.close()
+        return out, launches
+
+    ref, l0 = run(lambda b: None)
+    assert l0[0][:2] == (32, 8) and l0[1][:2] == (32, 8)
+
+    def mixed(b):
+        b.set_launch(0, 32, 4, 2)
+        b.set_launch(1, 64, 4, 12)
+
+    got, launches = run(mixed)
+    assert launches == ((32, 4, 2), (64, 4, 12))
+    tol = 1e-6 if storage == "f32" else 1e-3
+    for a, g in zip(ref, got):
+        for x, y in zip(a, g):
+            assert maxabs(x, y) <= tol
+
+    def tuned(b):
+        launches, best = b.autotune(1)
+        assert best > 0 and set(launches) == {"k_phi", "k_ut"}
+
+    got_t, lt = run(tuned)
+    print(storage, "tuned launches", lt)
+
+    def by_hand(b):
+        b.set_launch(0, *lt[0])
+        b.set_launch(1, *lt[1])
+
+    got_h, lh = run(by_hand)
+    assert lh == lt
+    for a, g in zip(got_h, got_t):
+        for x, y in zip(a, g):
+            assert np.array_equal(x, y)
 
 
 def test_batch_fp64_matches_oracle():

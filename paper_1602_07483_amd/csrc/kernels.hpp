@@ -684,27 +684,52 @@ __device__ __forceinline__ void ut_body(const Coef<T>& c, int block, const S* __
             const size_t np = (size_t)opaque(c.np);
             pUx = Un[xi];
             pthx = thn[xi];
-            Unroll<0, L::Q>::run([&](auto ic) {
-                constexpr int I = decltype(ic)::value;
-                constexpr int ex = L::ex(I), ey = L::ey(I), ez = L::ez(I);
-                const int off = ex + ey * px + ez * (int)plane;
-                const bool cr = crosses<L, I>(f);    // wall links: read any in-bounds value
-                if constexpr (BUF) {
-                    const unsigned vx = xi * (unsigned)sizeof(S);
-                    const unsigned vj = cr ? vx + (unsigned)off * (unsigned)sizeof(S) : vx;
-                    const unsigned sj = (unsigned)(I * np) * (unsigned)sizeof(S) - (unsigned)off * (unsigned)sizeof(S);
-                    // The pull is a bijection: with e_x = 0 and rows of whole
-                    // 128-byte lines, every line of a source row is read by
-                    // this block alone, once.
-                    constexpr int CP = ex == 0 && (TX * sizeof(S)) % 128 == 0 ? 2 : 0;
-                    if constexpr (SU) ph_[I] = Raw<S>::template ld<CP>(rhin, vj, sj);
-                    if constexpr (ST) pf_[I] = Raw<S>::template ld<CP>(rfin, vj, sj);
-                } else {
-                    const unsigned so = cr ? xi : xi - (unsigned)off;
-                    if constexpr (SU) ph_[I] = Raw<S>::ldg(hin + (size_t)I * np + so);
-                    if constexpr (ST) pf_[I] = Raw<S>::ldg(fin + (size_t)I * np + so);
-                }
-            });
+            // On edge tiles a link that crosses a wall loads the populations
+            // its source gives after bounce-back or reflection (element
+            // (j, source) of the wall rule) together with the others, so the
+            // collision of stage C waits for no load of its own.
+            const bool edge = !(tile.xy_inner && z > 0 && z < nz - 1);
+            if (!edge) {
+                Unroll<0, L::Q>::run([&](auto ic) {
+                    constexpr int I = decltype(ic)::value;
+                    constexpr int ex = L::ex(I), ey = L::ey(I), ez = L::ez(I);
+                    const int off = ex + ey * px + ez * (int)plane;
+                    if constexpr (BUF) {
+                        const unsigned vx = xi * (unsigned)sizeof(S);
+                        const unsigned sj = (unsigned)(I * np) * (unsigned)sizeof(S) - (unsigned)off * (unsigned)sizeof(S);
+                        // The pull is a bijection: with e_x = 0 and rows of whole
+                        // 128-byte lines, every line of a source row is read by
+                        // this block alone, once.
+                        constexpr int CP = ex == 0 && (TX * sizeof(S)) % 128 == 0 ? 2 : 0;
+                        if constexpr (SU) ph_[I] = Raw<S>::template ld<CP>(rhin, vx, sj);
+                        if constexpr (ST) pf_[I] = Raw<S>::template ld<CP>(rfin, vx, sj);
+                    } else {
+                        const unsigned so = xi - (unsigned)off;
+                        if constexpr (SU) ph_[I] = Raw<S>::ldg(hin + (size_t)I * np + so);
+                        if constexpr (ST) pf_[I] = Raw<S>::ldg(fin + (size_t)I * np + so);
+                    }
+                });
+            } else {
+                Unroll<0, L::Q>::run([&](auto ic) {
+                    constexpr int I = decltype(ic)::value;
+                    constexpr int ex = L::ex(I), ey = L::ey(I), ez = L::ez(I);
+                    const int off = ex + ey * px + ez * (int)plane;
+                    size_t src = (size_t)I * np + (xi - (unsigned)off);   // element of dh_j, df_j at the source
+                    if (crosses<L, I>(f)) {
+                        const Src w = source<L, I>(opaque_v(tile.x), opaque_v(tile.y), z, nx, ny, nz, c.symm);
+                        src = (size_t)w.j * np + ((size_t)w.sz * ny + w.sy) * px + w.sx;
+                    }
+                    if constexpr (BUF) {
+                        const unsigned ve = (unsigned)src * (unsigned)sizeof(S);
+                        if constexpr (SU) ph_[I] = Raw<S>::template ld<>(rhin, ve, 0u);
+                        if constexpr (ST) pf_[I] = Raw<S>::template ld<>(rfin, ve, 0u);
+                    } else {
+                        if constexpr (SU) ph_[I] = Raw<S>::ldg(hin + src);
+                        if constexpr (ST) pf_[I] = Raw<S>::ldg(fin + src);
+                    }
+                    __builtin_amdgcn_sched_barrier(0);   // one direction's sources at a time
+                });
+            }
         }
     };
 
@@ -823,9 +848,9 @@ __device__ __forceinline__ void ut_body(const Coef<T>& c, int block, const S* __
             auto wall_link = [&](auto ic, T& vu, T& vt) {
                 constexpr int I = decltype(ic)::value;
                 const Src s = source<L, I>(opaque_v(tile.x), opaque_v(tile.y), z, nx, ny, nz, c.symm);
-                const size_t si = ((size_t)s.sz * ny + s.sy) * px + s.sx;
-                const T dh = SU ? (T)Codec<S>::dec(hin[(size_t)s.j * np + si]) : T(0);
-                const T df = ST ? (T)Codec<S>::dec(fin[(size_t)s.j * np + si]) : T(0);
+                // loaded with the others from the wall rule's source
+                const T dh = SU ? (T)Raw<S>::dec(ph_[I]) : T(0);
+                const T df = ST ? (T)Raw<S>::dec(pf_[I]) : T(0);
                 const int tsl = (s.sz + 3) % 3, tl = (s.sy - tile.y0 + 1) * G::HX + (s.sx - tile.x0 + 1);
                 const V4<T> ta = sta[tsl][tl];
                 constexpr T wi = T(L::w(I));

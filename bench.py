@@ -383,6 +383,11 @@ def cpu_baseline(n=256):
             "octant128_one_thread": {"mlups": one, "steps": s1}}
 
 
+
+def note(msg):
+    """Progress of the legs, on stderr (the result line is the only stdout)."""
+    print("bench: " + msg, file=sys.stderr, flush=True)
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -412,6 +417,7 @@ def main():
     if args.autotune:
         launch = "auto"
     res = run_gpu("f32", args.steps, args.warmup, args.n, launch)
+    note("f32 %.0f MLUPS" % res["mlups"])
     variants = {}
     if not args.no_variants:
         for st in ("f16", "bf16"):
@@ -420,23 +426,28 @@ def main():
                             "algorithmic_GBps": r["algorithmic_GBps"],
                             "speedup_vs_f32": r["mlups"] / res["mlups"],
                             "kernels": r["kernels"]}
+            note("%s %.0f MLUPS" % (st, r["mlups"]))
     copy_gbs = copy_bandwidth()
     single_field = separate_lattices = None
     if not args.no_variants:
         single_field = run_single_field(max(args.steps // 3, 1), args.warmup, args.n)
         separate_lattices = run_separate_lattices(max(args.steps // 3, 1), args.warmup, args.n)
+        note("single-field and separate-lattice legs done")
     multiseed = None
     if not args.no_multiseed:
         multiseed = run_multiseed(args.multiseed_steps)
+        note("multi-seed leg done")
     ensemble = None
     if not args.no_ensemble:
         ensemble = run_ensemble(args.ensemble_steps, max(args.ensemble_steps // 4, 1))
+        note("ensemble leg done")
     errors = None
     if not args.no_errors and args.n == 256:
         errors = oracle_errors(["f32"] + ([] if args.no_variants else ["f16", "bf16"]))
         for st, e in errors.items():
             if st in variants:
                 variants[st]["error_vs_oracle"] = e
+        note("errors against the oracle done")
 
     dom = max(res["kernels"], key=lambda k: res["kernels"][k]["avg_ms"])
     kd = res["kernels"][dom]

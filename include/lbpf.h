@@ -308,8 +308,8 @@ lbpf_status lbpf_kernel_times(lbpf_ctx* ctx, double ms[3], int64_t launches[3]);
  * launch of its own.  lbpf_set_launch sets both (all or nothing);
  * lbpf_set_kernel_launch one.  lbpf_get_launch reports k_ut's, the kernel
  * that moves the most bytes; lbpf_get_kernel_launch either.
- * Defaults: k_phi 32x8, zslab 6 (FP32) or 8 (16-bit); k_ut 64x4 zslab 6
- * (FP32) or 32x8 zslab 8 (16-bit); FP64 32x4 zslab 4 for both; remap 1.
+ * Defaults: k_phi 32x8 zslab 6, remap 1; k_ut 64x4 zslab 6 remap 0 (FP32)
+ * or 32x8 zslab 6 remap 1 (16-bit); FP64 32x4 zslab 4 remap 1 for both.
  * With an advective velocity (lbpf_params.vel or a velocity field) k_ut
  * runs on its advection tile, 32x8 (FP64 32x4), the only one with the
  * advective variant.

@@ -517,7 +517,7 @@ lbpf_status lbpf_create(const lbpf_grid* grid, const lbpf_params* params, void* 
     for (int k = 0; k < 2; ++k) {
         ctx->shape[k] = kDefaultShape[k][g.storage];
         ctx->zslab[k] = kDefaultZslab[k][g.storage];
-        ctx->remap[k] = 1;
+        ctx->remap[k] = kDefaultRemap[k][g.storage];
     }
     if (ut_pinned(ctx)) ctx->shape[K_UT] = adv_shape(ctx);
     ctx->n = (size_t)g.nx * g.ny * g.nz;

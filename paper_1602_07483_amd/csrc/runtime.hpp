@@ -51,8 +51,12 @@ enum { K_PHI = 0, K_UT = 1 };
 // fastest measured at 256^3 on D3Q19: k_phi on 32x8 tiles, k_ut on 64x4 tiles
 // with FP32 populations (a 256-byte row keeps every line of an x-aligned pull
 // within one block) and 32x8 with 16-bit ones; FP64 has 64x2 and 32x4 only.
+// Tiles are dealt to the XCDs in contiguous runs except for FP32 k_ut, whose
+// 64x4 tiles run 4 % faster in the hardware's round-robin order (although
+// more of their reads then miss the XCD's L2).
 constexpr int kDefaultShape[2][4] = {{3, 3, 3, 2}, {1, 3, 3, 2}};
-constexpr int kDefaultZslab[2][4] = {{6, 8, 8, 4}, {6, 8, 8, 4}};
+constexpr int kDefaultZslab[2][4] = {{6, 6, 6, 4}, {6, 6, 6, 4}};
+constexpr int kDefaultRemap[2][4] = {{1, 1, 1, 1}, {0, 1, 1, 1}};
 // The one k_ut tile with the advection-diffusion variant: 32x8 (FP64 32x4).
 // Its wider halo terms (four values per node instead of one) would cost the
 // 64x4 FP32 tile a block per CU.

@@ -677,15 +677,36 @@ def test_separate_lattices():
 
 
 # ------------------------------------------------ FD6 / FD18 (Sec. 4.1)
-def _fd_heat_step(stencil, shape, modes, dt=0.01):
-    """One FD step of theta alone (phi = -1 is a fixed point with lambda = 0)
-    from the mirror-wall cosine mode of the given mode numbers; returns the
-    initial theta and the per-step rate (theta1 - theta0) / dt."""
-    from oracle import FDOracle
+def _mirror_mode(shape, modes):
     nz, ny, nx = shape
     z, y, x = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
-    th = (np.cos(np.pi * modes[0] * (x + 0.5) / nx) * np.cos(np.pi * modes[1] * (y + 0.5) / ny)
-          * np.cos(np.pi * modes[2] * (z + 0.5) / nz))
+    return (np.cos(np.pi * modes[0] * (x + 0.5) / nx) * np.cos(np.pi * modes[1] * (y + 0.5) / ny)
+            * np.cos(np.pi * modes[2] * (z + 0.5) / nz))
+
+
+def _fd_phi_step(stencil, shape, modes, dt=0.01):
+    """One FD step of phi alone from half the mirror-wall cosine mode of the
+    given mode numbers, with eps = 0 (a_s = 1, no anisotropy flux) and
+    lambda = 0 (no coupling): tau0 dphi/dt = lap phi + phi - phi^3 with
+    W0 = tau0 = 1.  Returns the initial phi and the stencil's action,
+    (phi1 - phi0) / dt - (phi0 - phi0^3)."""
+    from oracle import FDOracle
+    ph = 0.5 * _mirror_mode(shape, modes)
+    nz, ny, nx = shape
+    o = FDOracle(nx, ny, nz, lam=0.0, Mcinf=0.0, kappa=1.0, eps=0.0, stencil=stencil)
+    o.set(ph, np.zeros(shape), np.zeros(shape))
+    o.step(dt, 1)
+    ph1, _, _ = o.fields()
+    return ph, (ph1 - ph) / dt - (ph - ph ** 3)
+
+
+def _fd_heat_step(stencil, shape, modes, dt=0.01):
+    """One FD step of theta alone (phi = -1 is a fixed point with lambda = 0)
+    from the mirror-wall cosine mode; returns the initial theta and the
+    per-step rate (theta1 - theta0) / dt."""
+    from oracle import FDOracle
+    th = _mirror_mode(shape, modes)
+    nz, ny, nx = shape
     o = FDOracle(nx, ny, nz, lam=0.0, Mcinf=0.0, kappa=1.0, eps=0.0, stencil=stencil)
     o.set(-np.ones(shape), np.zeros(shape), th)
     o.step(dt, 1)
@@ -699,15 +720,18 @@ def test_fd_stencils_act_on_mirror_modes_as_their_symbols(stencil):
     """The mirror-wall cosine modes are eigenvectors of both Laplacians; with
     c_a = cos(k_a dx), the face stencil has the symbol 2 sum c_a - 6 and the
     face + edge stencil [4 sum c_a + 4 sum_{a<b} c_a c_b - 24] / 6 (dx = 1).
-    A mixed mode (1, 2, 3) weighs every face and edge neighbour differently."""
+    A mixed mode (1, 2, 3) weighs every face and edge neighbour differently.
+    Sec. 4.1 names FD6 and FD18 by the Laplacian of the phase-field
+    equation: phi takes the stencil's symbol, theta the face stencil's in
+    both."""
     shape, modes = (8, 10, 12), (1, 2, 3)
     c = [np.cos(np.pi * m / n) for m, n in zip(modes, shape[::-1])]
-    if stencil == 6:
-        sym = 2 * sum(c) - 6
-    else:
-        sym = (4 * sum(c) + 4 * (c[0] * c[1] + c[0] * c[2] + c[1] * c[2]) - 24) / 6
+    face = 2 * sum(c) - 6
+    edge = (4 * sum(c) + 4 * (c[0] * c[1] + c[0] * c[2] + c[1] * c[2]) - 24) / 6
+    ph, act = _fd_phi_step(stencil, shape, modes)
+    assert np.max(np.abs(act - (face if stencil == 6 else edge) * ph)) < 1e-12
     th, rate = _fd_heat_step(stencil, shape, modes)
-    assert np.max(np.abs(rate - sym * th)) < 1e-12
+    assert np.max(np.abs(rate - face * th)) < 1e-12
 
 
 def test_fd18_error_is_isotropic_fd6_is_not():
@@ -719,9 +743,9 @@ def test_fd18_error_is_isotropic_fd6_is_not():
     c = {}
     for st in (6, 18):
         for name, shape, modes in (("100", (1, 1, n), (4, 0, 0)), ("110", (1, n, n), (4, 4, 0))):
-            th, rate = _fd_heat_step(st, shape, modes)
-            m = np.abs(th) > 1e-3
-            lam = np.mean(rate[m] / th[m])
+            ph, act = _fd_phi_step(st, shape, modes)
+            m = np.abs(ph) > 1e-3
+            lam = np.mean(act[m] / ph[m])
             k2 = sum((np.pi * q / n) ** 2 for q in modes)
             c[st, name] = (lam + k2) / k2 ** 2
     assert abs(c[6, "100"] - 1 / 12) < 2e-3 and abs(c[6, "110"] - 1 / 24) < 2e-3

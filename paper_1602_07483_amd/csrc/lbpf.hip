@@ -524,7 +524,11 @@ lbpf_status lbpf_create(const lbpf_grid* grid, const lbpf_params* params, void* 
     // rows start on 128-byte lines (FP32): a tile row then reads whole lines
     ctx->px = (g.nx + 31) / 32 * 32;
     ctx->na = (size_t)ctx->px * g.ny * g.nz;
-    ctx->np = (ctx->na + 63) / 64 * 64;
+    // Stride between the Q arrays of a field: whole 64-element groups, plus
+    // an odd number of 256-byte units, so that the Q loads of one node do not
+    // sit a power of two apart (at 256^3 that power of two is 64 MiB, and
+    // k_phi FP32 runs 3.5 % slower on it).
+    ctx->np = (ctx->na + 63) / 64 * 64 + kStridePadBytes / ctx->sbytes;
     hipError_t e = hipSuccess;
     for (int f = 0; f < 3 && e == hipSuccess; ++f)
         for (int par = 0; par < 2 && e == hipSuccess; ++par) {

@@ -57,6 +57,9 @@ enum { K_PHI = 0, K_UT = 1 };
 constexpr int kDefaultShape[2][4] = {{3, 3, 3, 2}, {1, 3, 3, 2}};
 constexpr int kDefaultZslab[2][4] = {{6, 6, 6, 4}, {6, 6, 6, 4}};
 constexpr int kDefaultRemap[2][4] = {{1, 1, 1, 1}, {0, 1, 1, 1}};
+
+// Padding added to the stride between population arrays: 17 x 256 bytes.
+constexpr size_t kStridePadBytes = 17 * 256;
 // The one k_ut tile with the advection-diffusion variant: 32x8 (FP64 32x4).
 // Its wider halo terms (four values per node instead of one) would cost the
 // 64x4 FP32 tile a block per CU.

@@ -37,7 +37,7 @@ def bytes_per_lup(q, b):
 
 def kernel_source_hash():
     h = hashlib.sha256()
-    for f in ("kernels.hpp", "lattice.hpp", "runtime.hpp", "step.hip"):
+    for f in ("kernels.hpp", "lattice.hpp", "runtime.hpp", "step.hip", "lbpf.hip"):
         with open(os.path.join(ROOT, "paper_1602_07483_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]

@@ -56,7 +56,8 @@ typedef enum {
     LBPF_ENOMEM = -2,     /* device or host allocation failed */
     LBPF_EDEVICE = -3,    /* a HIP runtime call failed */
     LBPF_EUNSTABLE = -4,  /* health check failed: non-finite value or |phi| > 1 + 1e-3 */
-    LBPF_ESTATE = -5      /* call out of order (e.g. step before set_fields) */
+    LBPF_ESTATE = -5,     /* call out of order (e.g. step before set_fields) */
+    LBPF_EIO = -6         /* a file could not be read or written */
 } lbpf_status;
 
 /* D3Q7 (e^2 = 1/4), D3Q15 and D3Q19 (e^2 = 1/3): Sec. 3.4, Tables 1 and 2. */
@@ -334,6 +335,27 @@ lbpf_status lbpf_get_kernel_launch(lbpf_ctx* ctx, int32_t kernel, int32_t* tile_
  * accumulators; the tuner's own are not.  Synchronises.
  * Errors: ESTATE (no fields yet), EINVAL, ENOMEM, EDEVICE. */
 lbpf_status lbpf_autotune(lbpf_ctx* ctx, int32_t steps_per_candidate, double* best_ms_per_step);
+
+/* The autotuner with a persisted result, so that a configuration is timed
+ * once per machine type.  cache_path names a text file with one line per
+ * tuned configuration:
+ *   lbpf-autotune-1 <gcnArchName> cu<CUs> q<lattice> qut<lattice_ut>
+ *     s<storage> <nx>x<ny>x<nz> pin<0|1>  <k_phi: tx ty zslab remap>
+ *     <k_ut: tx ty zslab remap> <ms per step>
+ * where pin = 1 when k_ut runs one of its variants (advection, skip_U or
+ * skip_theta).  If a line's key matches this context (device architecture
+ * and CU count, lattices, storage, domain size, pin), its launches are set
+ * without any timing and *hit = 1; *best_ms_per_step receives the stored
+ * time.  Otherwise lbpf_autotune runs, its result is appended to the file
+ * (created if missing) and *hit = 0.  Lines that do not parse or name a
+ * launch this context refuses are skipped.  hit and best_ms_per_step may
+ * be NULL.  Concurrent writers append whole lines; the first matching line
+ * wins.
+ * Errors: those of lbpf_autotune; EINVAL (NULL cache_path); EIO (the file
+ * exists but cannot be read, or cannot be appended to: the tuned launches
+ * are then set all the same). */
+lbpf_status lbpf_autotune_cached(lbpf_ctx* ctx, int32_t steps_per_candidate, const char* cache_path,
+                                 int32_t* hit, double* best_ms_per_step);
 
 /* Bytes of one stored population for a storage type (0 if invalid). */
 int32_t lbpf_storage_bytes(int32_t storage);

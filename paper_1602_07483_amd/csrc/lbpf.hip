@@ -7,11 +7,22 @@
 // buffers; the parity `cur` names the current state.
 #include "runtime.hpp"
 
+#include <rocprofiler-sdk-roctx/roctx.h>
+
 #include <mutex>
 
 // The library's two non-template kernels, defined in this translation unit
 // only (the step translation units include kernels.hpp too).
 namespace lbpf {
+
+// A named range on the profiler's timeline (rocprofv3 --marker-trace) for
+// the duration of one library call; free when no profiler is attached.
+struct Range {
+    explicit Range(const char* name) { roctxRangePushA(name); }
+    ~Range() { roctxRangePop(); }
+    Range(const Range&) = delete;
+    Range& operator=(const Range&) = delete;
+};
 
 // Record layout (RED_STRIDE doubles): step, solid, mass, enthalpy, tip x,y,z,
 // phi min, phi max, non-finite count, sum U, sum phi.
@@ -561,6 +572,7 @@ lbpf_status lbpf_destroy(lbpf_ctx* ctx) {
 }
 
 lbpf_status lbpf_set_fields(lbpf_ctx* ctx, const double* phi, const double* U, const double* theta) {
+    const lbpf::Range range("lbpf_set_fields");
     if (!ctx) return LBPF_EINVAL;
     if (!phi || !U || !theta) return fail(ctx, LBPF_EINVAL, "NULL field array");
     ctx->cur = 0;
@@ -624,6 +636,7 @@ lbpf_status capture_graph(lbpf_ctx* ctx) {
 }
 
 lbpf_status lbpf_step(lbpf_ctx* ctx, int64_t nsteps) {
+    const lbpf::Range range("lbpf_step");
     if (!ctx) return LBPF_EINVAL;
     if (nsteps < 0) return fail(ctx, LBPF_EINVAL, "nsteps < 0");
     if (!ctx->have_fields) return fail(ctx, LBPF_ESTATE, "lbpf_set_fields has not been called");
@@ -690,6 +703,7 @@ lbpf_status lbpf_sync(lbpf_ctx* ctx) {
 }
 
 lbpf_status lbpf_read(lbpf_ctx* ctx, double* phi, double* U, double* theta, lbpf_reductions* red) {
+    const lbpf::Range range("lbpf_read");
     if (!ctx) return LBPF_EINVAL;
     if (!ctx->have_fields) return fail(ctx, LBPF_ESTATE, "lbpf_set_fields has not been called");
     double* dst[3] = {phi, U, theta};
@@ -883,6 +897,7 @@ lbpf_status lbpf_get_launch(lbpf_ctx* ctx, int32_t* tile_x, int32_t* tile_y, int
 }
 
 lbpf_status lbpf_autotune(lbpf_ctx* ctx, int32_t steps_per_candidate, double* best_ms_per_step) {
+    const lbpf::Range range("lbpf_autotune");
     if (!ctx) return LBPF_EINVAL;
     if (steps_per_candidate < 1) return fail(ctx, LBPF_EINVAL, "steps_per_candidate < 1");
     if (!ctx->have_fields) return fail(ctx, LBPF_ESTATE, "lbpf_set_fields has not been called");
@@ -964,6 +979,74 @@ lbpf_status lbpf_autotune(lbpf_ctx* ctx, int32_t steps_per_candidate, double* be
     }
     if (st) return st;
     if (best_ms_per_step) *best_ms_per_step = best[0] + best[1];
+    return LBPF_OK;
+}
+
+lbpf_status lbpf_autotune_cached(lbpf_ctx* ctx, int32_t steps_per_candidate, const char* cache_path,
+                                 int32_t* hit, double* best_ms_per_step) {
+    const lbpf::Range range("lbpf_autotune_cached");
+    if (!ctx) return LBPF_EINVAL;
+    if (!cache_path) return fail(ctx, LBPF_EINVAL, "cache_path is NULL");
+    if (hit) *hit = 0;
+    int dev = 0;
+    hipDeviceProp_t prop;
+    CHK(hipGetDevice(&dev));
+    CHK(hipGetDeviceProperties(&prop, dev));
+    char arch[sizeof(prop.gcnArchName) + 1];
+    std::snprintf(arch, sizeof(arch), "%s", prop.gcnArchName);
+    for (char* a = arch; *a; ++a)
+        if (*a == ' ' || *a == '\t') *a = '_';
+    char key[512];
+    std::snprintf(key, sizeof(key), "lbpf-autotune-1 %s cu%d q%d qut%d s%d %dx%dx%d pin%d", arch,
+                  prop.multiProcessorCount, ctx->q, ctx->q_ut, ctx->storage, ctx->grid.nx, ctx->grid.ny,
+                  ctx->grid.nz, ut_pinned(ctx) ? 1 : 0);
+    const size_t klen = std::strlen(key);
+    if (FILE* in = std::fopen(cache_path, "r")) {
+        char line[1024];
+        bool found = false;
+        while (!found && std::fgets(line, sizeof(line), in)) {
+            if (std::strncmp(line, key, klen) != 0 || (line[klen] != ' ' && line[klen] != '\t')) continue;
+            int l[2][4];
+            double ms = 0.0;
+            if (std::sscanf(line + klen, "%d %d %d %d %d %d %d %d %lf", &l[0][0], &l[0][1], &l[0][2], &l[0][3],
+                            &l[1][0], &l[1][1], &l[1][2], &l[1][3], &ms) != 9)
+                continue;
+            // all or nothing: a launch this context refuses leaves the old ones
+            const int s0[2] = {ctx->shape[0], ctx->shape[1]}, z0[2] = {ctx->zslab[0], ctx->zslab[1]},
+                      r0[2] = {ctx->remap[0], ctx->remap[1]};
+            lbpf_status st = LBPF_OK;
+            for (int k = 0; k < 2 && !st; ++k)
+                st = lbpf_set_kernel_launch(ctx, k, l[k][0], l[k][1], l[k][2], l[k][3]);
+            if (st) {
+                for (int k = 0; k < 2; ++k) { ctx->shape[k] = s0[k]; ctx->zslab[k] = z0[k]; ctx->remap[k] = r0[k]; }
+                ctx->err.clear();
+                continue;
+            }
+            found = true;
+            if (hit) *hit = 1;
+            if (best_ms_per_step) *best_ms_per_step = ms;
+        }
+        const bool bad = std::ferror(in) != 0;
+        std::fclose(in);
+        if (found) return LBPF_OK;
+        if (bad) return fail(ctx, LBPF_EIO, std::string("cannot read ") + cache_path);
+    }
+    double best = 0.0;
+    const lbpf_status st = lbpf_autotune(ctx, steps_per_candidate, &best);
+    if (st) return st;
+    if (best_ms_per_step) *best_ms_per_step = best;
+    char line[1024];
+    int n = std::snprintf(line, sizeof(line), "%s", key);
+    for (int k = 0; k < 2; ++k) {
+        const Shape sh = kShapes[ctx->shape[k]];
+        n += std::snprintf(line + n, sizeof(line) - n, " %d %d %d %d", sh.tx, sh.ty, ctx->zslab[k], ctx->remap[k]);
+    }
+    std::snprintf(line + n, sizeof(line) - n, " %.6f\n", best);
+    FILE* out = std::fopen(cache_path, "a");
+    if (!out) return fail(ctx, LBPF_EIO, std::string("cannot append to ") + cache_path);
+    const bool ok = std::fputs(line, out) >= 0;
+    const bool closed = std::fclose(out) == 0;
+    if (!ok || !closed) return fail(ctx, LBPF_EIO, std::string("cannot append to ") + cache_path);
     return LBPF_OK;
 }
 
@@ -1346,6 +1429,7 @@ lbpf_status lbpf_batch_get_launch(lbpf_batch* b, int32_t kernel, int32_t* tile_x
 }
 
 lbpf_status lbpf_batch_autotune(lbpf_batch* b, int32_t steps_per_candidate, double* best_ms_per_step) {
+    const lbpf::Range range("lbpf_batch_autotune");
     if (!b) return LBPF_EINVAL;
     if (steps_per_candidate < 1) return bfail(b, LBPF_EINVAL, "steps_per_candidate < 1");
     const int cur0 = b->dom[0]->cur;
@@ -1439,6 +1523,7 @@ lbpf_status lbpf_batch_autotune(lbpf_batch* b, int32_t steps_per_candidate, doub
 }
 
 lbpf_status lbpf_batch_step(lbpf_batch* b, int64_t nsteps) {
+    const lbpf::Range range("lbpf_batch_step");
     if (!b) return LBPF_EINVAL;
     if (nsteps < 0) return bfail(b, LBPF_EINVAL, "nsteps < 0");
     const int cur = b->dom[0]->cur;

@@ -12,7 +12,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "liblbpf.so")
 
-LBPF_OK, LBPF_EINVAL, LBPF_ENOMEM, LBPF_EDEVICE, LBPF_EUNSTABLE, LBPF_ESTATE = 0, -1, -2, -3, -4, -5
+LBPF_OK, LBPF_EINVAL, LBPF_ENOMEM, LBPF_EDEVICE, LBPF_EUNSTABLE, LBPF_ESTATE, LBPF_EIO = 0, -1, -2, -3, -4, -5, -6
 LBPF_D3Q7, LBPF_D3Q15, LBPF_D3Q19 = 7, 15, 19
 LBPF_WALL_NOFLUX, LBPF_WALL_SYMMETRY = 0, 1
 LBPF_F32, LBPF_F16_DEV, LBPF_BF16_DEV, LBPF_F64 = 0, 1, 2, 3
@@ -65,7 +65,7 @@ SYMBOLS = ["lbpf_create", "lbpf_destroy", "lbpf_set_fields", "lbpf_step", "lbpf_
            "lbpf_debug_stream_only", "lbpf_set_velocity_field", "lbpf_set_timing",
            "lbpf_kernel_times",
            "lbpf_set_launch", "lbpf_get_launch", "lbpf_set_kernel_launch",
-           "lbpf_get_kernel_launch", "lbpf_autotune",
+           "lbpf_get_kernel_launch", "lbpf_autotune", "lbpf_autotune_cached",
            "lbpf_storage_bytes", "lbpf_bench_copy", "lbpf_bench_bandwidth", "lbpf_reduce_fields_noalloc",
            "lbpf_last_error", "lbpf_set_graph",
            "lbpf_batch_create", "lbpf_batch_domain", "lbpf_batch_set_graph", "lbpf_batch_step",
@@ -112,6 +112,7 @@ def load():
         "lbpf_get_kernel_launch": ([vp, ctypes.c_int32, P(ctypes.c_int32), P(ctypes.c_int32),
                                     P(ctypes.c_int32), P(ctypes.c_int32)], ctypes.c_int),
         "lbpf_autotune": ([vp, ctypes.c_int32, dp], ctypes.c_int),
+        "lbpf_autotune_cached": ([vp, ctypes.c_int32, ctypes.c_char_p, P(ctypes.c_int32), dp], ctypes.c_int),
         "lbpf_storage_bytes": ([ctypes.c_int32], ctypes.c_int32),
         "lbpf_bench_copy": ([vp, vp, ctypes.c_int64, vp], ctypes.c_int),
         "lbpf_reduce_fields_noalloc": ([vp, vp, vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
@@ -378,6 +379,14 @@ class Solver:
         best = ctypes.c_double()
         self._check(self._lib.lbpf_autotune(self._h, int(steps_per_candidate), ctypes.byref(best)))
         return self.launches(), best.value
+
+    def autotune_cached(self, cache_path, steps_per_candidate=10):
+        """lbpf_autotune_cached: returns (launches, best ms per step, hit)."""
+        best, hit = ctypes.c_double(), ctypes.c_int32()
+        self._check(self._lib.lbpf_autotune_cached(self._h, int(steps_per_candidate),
+                                                   os.fsencode(cache_path), ctypes.byref(hit),
+                                                   ctypes.byref(best)))
+        return self.launches(), best.value, bool(hit.value)
 
     def kernel_times(self):
         ms = (ctypes.c_double * 3)()

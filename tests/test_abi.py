@@ -34,8 +34,20 @@ def test_binding_covers_header():
     assert sorted(declared_symbols()) == sorted(lbpf.SYMBOLS)
 
 
+def test_status_codes_match_header():
+    text = open(os.path.join(ROOT, "include", "lbpf.h")).read()
+    codes = dict((k, int(v)) for k, v in re.findall(r"(LBPF_E[A-Z]+|LBPF_OK)\s*=\s*(-?\d+)", text))
+    assert codes == {"LBPF_OK": lbpf.LBPF_OK, "LBPF_EINVAL": lbpf.LBPF_EINVAL, "LBPF_ENOMEM": lbpf.LBPF_ENOMEM,
+                     "LBPF_EDEVICE": lbpf.LBPF_EDEVICE, "LBPF_EUNSTABLE": lbpf.LBPF_EUNSTABLE,
+                     "LBPF_ESTATE": lbpf.LBPF_ESTATE, "LBPF_EIO": lbpf.LBPF_EIO}
+
+
 def test_storage_bytes_and_invalid_arguments_without_gpu():
     L = lbpf.lib()
+    # the autotune cache refuses a missing context before any device call
+    hit, best = ctypes.c_int32(7), ctypes.c_double()
+    assert L.lbpf_autotune_cached(None, 2, b"/nonexistent/cache", ctypes.byref(hit),
+                                  ctypes.byref(best)) == lbpf.LBPF_EINVAL
     assert [L.lbpf_storage_bytes(s) for s in (0, 1, 2, 3, 9)] == [4, 2, 2, 8, 0]
     # argument validation happens before any device call
     g = lbpf.lbpf_grid()

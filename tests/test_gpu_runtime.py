@@ -386,6 +386,39 @@ def test_separate_lattices_runtime_paths():
         assert np.array_equal(x, y), "restored"
 
 
+@pytest.mark.gpu
+def test_autotune_cache(tmp_path):
+    """lbpf_autotune_cached: the first call tunes and appends one line, a
+    second context of the same configuration takes its launches from that
+    line without timing (and steps to the same fields as the tuned one), a
+    line that does not parse or names a refused launch is skipped, and
+    another domain size is a miss of its own."""
+    cache = str(tmp_path / "tune.txt")
+    pb = ragged()
+    a = make_gpu(pb, "f32")
+    la, best_a, hit = a.autotune_cached(cache, 1)
+    assert not hit and best_a > 0
+    lines = open(cache).read().splitlines()
+    assert len(lines) == 1 and lines[0].startswith("lbpf-autotune-1 ") and " q19 qut19 s0 45x23x21 pin0 " in lines[0]
+    key = lines[0].split(" pin0 ")[0] + " pin0"
+    # a garbled line and a refused launch (a 48x8 tile) ahead of the good one
+    with open(cache, "w") as fh:
+        fh.write(key + " 1 2 3\n")
+        fh.write(key + " 48 8 6 1 64 4 6 0 0.5\n")
+        fh.write(lines[0] + "\n")
+    b = make_gpu(pb, "f32")
+    lb, best_b, hit = b.autotune_cached(cache, 1)
+    assert hit and lb == la and abs(best_b - best_a) <= 1e-6 * best_a
+    a.step(10)
+    b.step(10)
+    for x, y in zip(fields(a), fields(b)):
+        assert np.array_equal(x, y)
+    c = make_gpu(ragged(n=(37, 21, 19)), "f32")
+    _, _, hit = c.autotune_cached(cache, 1)
+    assert not hit
+    assert len(open(cache).read().splitlines()) == 4
+
+
 def _mixed_lattice_batch():
     """(problem, lattice_ut) pairs: phi and U/theta lattices mixed within and
     across domains, at dt/tau0 = 0.11 (inside the D3Q7 and D3Q15 windows)."""

@@ -961,10 +961,17 @@ __global__ __launch_bounds__(TX * TY, (sizeof(T) == 4 ? 4 : 1)) void k_phi_batch
     const DomainDesc<T>* __restrict__ dd, const int2* __restrict__ work, int par) {
     const int2 wk = work[blockIdx.x];
     if (wk.x < 0) return;   // padding entry: the whole block leaves
-    const DomainDesc<T>& d = dd[wk.x];
+    // The descriptor is read once into registers, as the single-domain
+    // kernel receives it as arguments: read through a reference, its fields
+    // are re-loaded inside the march, and each scalar load's wait also
+    // drains the LDS operations in flight.
     const int a = par, b = 1 - par;
-    phi_body<L, T, S, TX, TY, true>(d.c[0], wk.y, (const S*)d.pop[0][a], (S*)d.pop[0][b], d.fld[0][a],
-                                    d.fld[1][a], d.fld[2][a], d.fld[0][b]);
+    const Coef<T> c = dd[wk.x].c[0];
+    const S* gin = (const S*)dd[wk.x].pop[0][a];
+    S* gout = (S*)dd[wk.x].pop[0][b];
+    const T *phin = dd[wk.x].fld[0][a], *Un = dd[wk.x].fld[1][a], *thn = dd[wk.x].fld[2][a];
+    T* phout = dd[wk.x].fld[0][b];
+    phi_body<L, T, S, TX, TY, true>(c, wk.y, gin, gout, phin, Un, thn, phout);
 }
 
 template <class L, class T, class S, int TX, int TY>
@@ -972,11 +979,16 @@ __global__ __launch_bounds__(TX * TY, (sizeof(T) == 4 ? 3 : 1)) void k_ut_batch(
     const DomainDesc<T>* __restrict__ dd, const int2* __restrict__ work, int par) {
     const int2 wk = work[blockIdx.x];
     if (wk.x < 0) return;   // padding entry: the whole block leaves
-    const DomainDesc<T>& d = dd[wk.x];
     const int a = par, b = 1 - par;
-    ut_body<L, T, S, TX, TY, true>(d.c[1], wk.y, (const S*)d.pop[1][a], (S*)d.pop[1][b],
-                                   (const S*)d.pop[2][a], (S*)d.pop[2][b], d.fld[0][a], d.fld[0][b],
-                                   d.fld[1][a], d.fld[2][a], d.fld[1][b], d.fld[2][b]);
+    const Coef<T> c = dd[wk.x].c[1];   // read once (see k_phi_batch)
+    const S* hin = (const S*)dd[wk.x].pop[1][a];
+    S* hout = (S*)dd[wk.x].pop[1][b];
+    const S* fin = (const S*)dd[wk.x].pop[2][a];
+    S* fout = (S*)dd[wk.x].pop[2][b];
+    const T *phio = dd[wk.x].fld[0][a], *phnew = dd[wk.x].fld[0][b];
+    const T *Un = dd[wk.x].fld[1][a], *thn = dd[wk.x].fld[2][a];
+    T *Uout = dd[wk.x].fld[1][b], *thout = dd[wk.x].fld[2][b];
+    ut_body<L, T, S, TX, TY, true>(c, wk.y, hin, hout, fin, fout, phio, phnew, Un, thn, Uout, thout);
 }
 
 // ==========================================================================

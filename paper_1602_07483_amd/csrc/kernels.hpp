@@ -137,6 +137,86 @@ template <> struct Raw<__hip_bfloat16> {
     }
 };
 
+// The populations h_i and f_i of one direction and node are pulled from the
+// same source, so k_ut stores them side by side: element e of the pair array
+// holds (h, f) at 2e and 2e + 1.  Pair<S> loads and stores both with one
+// instruction (4 bytes per lane for 16-bit storage, 8 for FP32, 16 for
+// FP64) and splits them where they are used.
+typedef unsigned u32x2_t __attribute__((ext_vector_type(2)));
+typedef unsigned u32x4_t __attribute__((ext_vector_type(4)));
+// The FP32 and FP64 pairs are float and double vectors: reinterpreting one
+// element of an integer vector as a float (bit_cast of x.y) is compiled, with
+// packed FP32 instructions off, into a read of element 0.
+typedef float f32x2_t __attribute__((ext_vector_type(2)));
+typedef double f64x2_t __attribute__((ext_vector_type(2)));
+template <class S> struct Pair;
+template <> struct Pair<float> {
+    using type = f32x2_t;
+    template <int CP = 0>
+    __device__ static type ld(__amdgpu_buffer_rsrc_t r, unsigned v, unsigned s) {
+        return __builtin_bit_cast(type, __builtin_amdgcn_raw_buffer_load_b64(r, (int)v, (int)s, CP));
+    }
+    __device__ static type ldg(const float* p) { return *reinterpret_cast<const type*>(p); }
+    __device__ static float h(type x) { return x.x; }
+    __device__ static float f(type x) { return x.y; }
+    __device__ static type pack(float h, float f) { return type{h, f}; }
+    __device__ static void st(type x, __amdgpu_buffer_rsrc_t r, unsigned v, unsigned s) {
+        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2_t, x), r, (int)v, (int)s, 2);
+    }
+    __device__ static void stg(type x, float* p) { __builtin_nontemporal_store(x, reinterpret_cast<type*>(p)); }
+};
+template <> struct Pair<double> {
+    using type = f64x2_t;
+    template <int CP = 0>
+    __device__ static type ld(__amdgpu_buffer_rsrc_t r, unsigned v, unsigned s) {
+        return __builtin_bit_cast(type, __builtin_amdgcn_raw_buffer_load_b128(r, (int)v, (int)s, CP));
+    }
+    __device__ static type ldg(const double* p) { return *reinterpret_cast<const type*>(p); }
+    __device__ static double h(type x) { return x.x; }
+    __device__ static double f(type x) { return x.y; }
+    __device__ static type pack(double h, double f) { return type{h, f}; }
+    __device__ static void st(type x, __amdgpu_buffer_rsrc_t r, unsigned v, unsigned s) {
+        __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4_t, x), r, (int)v, (int)s, 2);
+    }
+    __device__ static void stg(type x, double* p) { __builtin_nontemporal_store(x, reinterpret_cast<type*>(p)); }
+};
+template <> struct Pair<__half> {
+    using type = unsigned;
+    template <int CP = 0>
+    __device__ static type ld(__amdgpu_buffer_rsrc_t r, unsigned v, unsigned s) {
+        return (unsigned)__builtin_amdgcn_raw_buffer_load_b32(r, (int)v, (int)s, CP);
+    }
+    __device__ static type ldg(const __half* p) { return *reinterpret_cast<const unsigned*>(p); }
+    __device__ static float h(type x) { return __half2float(__ushort_as_half((unsigned short)(x & 0xffffu))); }
+    __device__ static float f(type x) { return __half2float(__ushort_as_half((unsigned short)(x >> 16))); }
+    __device__ static type pack(__half h, __half f) {
+        return (unsigned)__half_as_ushort(h) | ((unsigned)__half_as_ushort(f) << 16);
+    }
+    __device__ static void st(type x, __amdgpu_buffer_rsrc_t r, unsigned v, unsigned s) {
+        __builtin_amdgcn_raw_buffer_store_b32(x, r, (int)v, (int)s, 2);
+    }
+    __device__ static void stg(type x, __half* p) { __builtin_nontemporal_store(x, reinterpret_cast<unsigned*>(p)); }
+};
+template <> struct Pair<__hip_bfloat16> {
+    using type = unsigned;
+    template <int CP = 0>
+    __device__ static type ld(__amdgpu_buffer_rsrc_t r, unsigned v, unsigned s) {
+        return (unsigned)__builtin_amdgcn_raw_buffer_load_b32(r, (int)v, (int)s, CP);
+    }
+    __device__ static type ldg(const __hip_bfloat16* p) { return *reinterpret_cast<const unsigned*>(p); }
+    __device__ static float h(type x) { return __builtin_bit_cast(float, x << 16); }
+    __device__ static float f(type x) { return __builtin_bit_cast(float, x & 0xffff0000u); }
+    __device__ static type pack(__hip_bfloat16 h, __hip_bfloat16 f) {
+        return (unsigned)__builtin_bit_cast(unsigned short, h) | ((unsigned)__builtin_bit_cast(unsigned short, f) << 16);
+    }
+    __device__ static void st(type x, __amdgpu_buffer_rsrc_t r, unsigned v, unsigned s) {
+        __builtin_amdgcn_raw_buffer_store_b32(x, r, (int)v, (int)s, 2);
+    }
+    __device__ static void stg(type x, __hip_bfloat16* p) {
+        __builtin_nontemporal_store(x, reinterpret_cast<unsigned*>(p));
+    }
+};
+
 // Reciprocal and reciprocal square root: the hardware instructions (about
 // 1 ulp) in FP32, exact operations in the FP64 verification build.
 __device__ __forceinline__ float frcp(float x) { return __builtin_amdgcn_rcpf(x); }
@@ -630,7 +710,11 @@ __device__ __forceinline__ void ut_body(const Coef<T>& c, int block, const S* __
     const T k = c.k;
     const T zA = T(0.5) * (T(1) + k), zB = T(0.5) * (T(1) - k);
     const T omU1 = T(1) - c.omU, omT1 = T(1) - c.omT;
-    const unsigned pbytes = (unsigned)((size_t)L::Q * (size_t)c.np * sizeof(S));
+    // With both fields solved, h and f sit side by side in one pair array
+    // (Pair<S>), addressed through hin/hout.
+    constexpr bool PAIR = SU && ST;
+    constexpr unsigned PS = PAIR ? 2u * (unsigned)sizeof(S) : (unsigned)sizeof(S);   // bytes per element
+    const unsigned pbytes = (unsigned)((size_t)L::Q * (size_t)c.np * PS);
     const __amdgpu_buffer_rsrc_t rhin = make_rsrc(hin, BUF ? pbytes : 0u);
     const __amdgpu_buffer_rsrc_t rfin = make_rsrc(fin, BUF ? pbytes : 0u);
     const __amdgpu_buffer_rsrc_t rhout = make_rsrc(hout, BUF ? pbytes : 0u);
@@ -640,7 +724,9 @@ __device__ __forceinline__ void ut_body(const Coef<T>& c, int block, const S* __
     T po_[M::NB], pu[M::NB], pt[M::NB];   // phi^n, U^n, theta^n at the term nodes
     T pv[ADV ? 3 : 1][ADV ? M::NB : 1];   // advective velocity at the term nodes (field)
     [[maybe_unused]] const size_t nodes = (size_t)plane * (size_t)nz;
-    typename Raw<S>::type ph_[L::Q], pf_[L::Q];   // dh_j, df_j of the pulled plane's sources, raw
+    // dh_j, df_j of the pulled plane's sources, raw: as pairs, or one array each
+    typename Pair<S>::type pp_[PAIR ? L::Q : 1];
+    typename Raw<S>::type ph_[PAIR ? 1 : L::Q], pf_[PAIR ? 1 : L::Q];
     T pUx = T(0), pthx = T(0);            // U^n, theta^n of the pulled node
     auto prefetch = [&](int zz) {
         {
@@ -695,18 +781,26 @@ __device__ __forceinline__ void ut_body(const Coef<T>& c, int block, const S* __
                     constexpr int ex = L::ex(I), ey = L::ey(I), ez = L::ez(I);
                     const int off = ex + ey * px + ez * (int)plane;
                     if constexpr (BUF) {
-                        const unsigned vx = xi * (unsigned)sizeof(S);
-                        const unsigned sj = (unsigned)(I * np) * (unsigned)sizeof(S) - (unsigned)off * (unsigned)sizeof(S);
+                        const unsigned vx = xi * PS;
+                        const unsigned sj = (unsigned)(I * np) * PS - (unsigned)off * PS;
                         // The pull is a bijection: with e_x = 0 and rows of whole
                         // 128-byte lines, every line of a source row is read by
                         // this block alone, once.
-                        constexpr int CP = ex == 0 && (TX * sizeof(S)) % 128 == 0 ? 2 : 0;
-                        if constexpr (SU) ph_[I] = Raw<S>::template ld<CP>(rhin, vx, sj);
-                        if constexpr (ST) pf_[I] = Raw<S>::template ld<CP>(rfin, vx, sj);
+                        constexpr int CP = ex == 0 && (TX * PS) % 128 == 0 ? 2 : 0;
+                        if constexpr (PAIR) {
+                            pp_[I] = Pair<S>::template ld<CP>(rhin, vx, sj);
+                        } else {
+                            if constexpr (SU) ph_[I] = Raw<S>::template ld<CP>(rhin, vx, sj);
+                            if constexpr (ST) pf_[I] = Raw<S>::template ld<CP>(rfin, vx, sj);
+                        }
                     } else {
-                        const unsigned so = xi - (unsigned)off;
-                        if constexpr (SU) ph_[I] = Raw<S>::ldg(hin + (size_t)I * np + so);
-                        if constexpr (ST) pf_[I] = Raw<S>::ldg(fin + (size_t)I * np + so);
+                        const size_t so = (size_t)I * np + (xi - (unsigned)off);
+                        if constexpr (PAIR) {
+                            pp_[I] = Pair<S>::ldg(hin + 2 * so);
+                        } else {
+                            if constexpr (SU) ph_[I] = Raw<S>::ldg(hin + so);
+                            if constexpr (ST) pf_[I] = Raw<S>::ldg(fin + so);
+                        }
                     }
                 });
             } else {
@@ -720,12 +814,20 @@ __device__ __forceinline__ void ut_body(const Coef<T>& c, int block, const S* __
                         src = (size_t)w.j * np + ((size_t)w.sz * ny + w.sy) * px + w.sx;
                     }
                     if constexpr (BUF) {
-                        const unsigned ve = (unsigned)src * (unsigned)sizeof(S);
-                        if constexpr (SU) ph_[I] = Raw<S>::template ld<>(rhin, ve, 0u);
-                        if constexpr (ST) pf_[I] = Raw<S>::template ld<>(rfin, ve, 0u);
+                        const unsigned ve = (unsigned)src * PS;
+                        if constexpr (PAIR) {
+                            pp_[I] = Pair<S>::template ld<>(rhin, ve, 0u);
+                        } else {
+                            if constexpr (SU) ph_[I] = Raw<S>::template ld<>(rhin, ve, 0u);
+                            if constexpr (ST) pf_[I] = Raw<S>::template ld<>(rfin, ve, 0u);
+                        }
                     } else {
-                        if constexpr (SU) ph_[I] = Raw<S>::ldg(hin + src);
-                        if constexpr (ST) pf_[I] = Raw<S>::ldg(fin + src);
+                        if constexpr (PAIR) {
+                            pp_[I] = Pair<S>::ldg(hin + 2 * src);
+                        } else {
+                            if constexpr (SU) ph_[I] = Raw<S>::ldg(hin + src);
+                            if constexpr (ST) pf_[I] = Raw<S>::ldg(fin + src);
+                        }
                     }
                     __builtin_amdgcn_sched_barrier(0);   // one direction's sources at a time
                 });
@@ -844,13 +946,25 @@ __device__ __forceinline__ void ut_body(const Coef<T>& c, int block, const S* __
             const size_t np = (size_t)opaque(c.np);
             T iu[L::Q], it[L::Q];
             T du = T(0), dth = T(0);
+            // the prefetched dh_j, df_j of link I, decoded
+            auto dh_of = [&](auto ic) -> T {
+                constexpr int I = decltype(ic)::value;
+                if constexpr (PAIR) return (T)Pair<S>::h(pp_[I]);
+                else if constexpr (SU) return (T)Raw<S>::dec(ph_[I]);
+                else return T(0);
+            };
+            auto df_of = [&](auto ic) -> T {
+                constexpr int I = decltype(ic)::value;
+                if constexpr (PAIR) return (T)Pair<S>::f(pp_[I]);
+                else if constexpr (ST) return (T)Raw<S>::dec(pf_[I]);
+                else return T(0);
+            };
             // A link that crosses a wall: source after bounce-back or reflection.
             auto wall_link = [&](auto ic, T& vu, T& vt) {
                 constexpr int I = decltype(ic)::value;
                 const Src s = source<L, I>(opaque_v(tile.x), opaque_v(tile.y), z, nx, ny, nz, c.symm);
                 // loaded with the others from the wall rule's source
-                const T dh = SU ? (T)Raw<S>::dec(ph_[I]) : T(0);
-                const T df = ST ? (T)Raw<S>::dec(pf_[I]) : T(0);
+                const T dh = dh_of(ic), df = df_of(ic);
                 const int tsl = (s.sz + 3) % 3, tl = (s.sy - tile.y0 + 1) * G::HX + (s.sx - tile.x0 + 1);
                 const V4<T> ta = sta[tsl][tl];
                 constexpr T wi = T(L::w(I));
@@ -878,7 +992,7 @@ __device__ __forceinline__ void ut_body(const Coef<T>& c, int block, const S* __
                 T vu = T(0), vt = T(0);
                 T eA = T(0);
                 if constexpr (I == 0) {
-                    if constexpr (SU) vu = (wi - T(1)) * Cx + wi * Sx + omU1 * (T)Raw<S>::dec(ph_[I]);
+                    if constexpr (SU) vu = (wi - T(1)) * Cx + wi * Sx + omU1 * dh_of(ic);
                 } else {
                     T eK = T(ex) * ta.z + T(ey) * ta.w;
                     if constexpr (ADV) {
@@ -888,9 +1002,9 @@ __device__ __forceinline__ void ut_body(const Coef<T>& c, int block, const S* __
                     } else {
                         if constexpr (ez != 0) eK += T(ez) * stk[sl[1 - ez]][tl];
                     }
-                    if constexpr (SU) vu = wi * (ta.x - Px + eK) + omU1 * (T)Raw<S>::dec(ph_[I]);
+                    if constexpr (SU) vu = wi * (ta.x - Px + eK) + omU1 * dh_of(ic);
                 }
-                if constexpr (ST) vt = wi * (ta.y - thx + eA) + omT1 * (T)Raw<S>::dec(pf_[I]);
+                if constexpr (ST) vt = wi * (ta.y - thx + eA) + omT1 * df_of(ic);
                 if constexpr (EDGE && I != 0) {
                     if (crosses<L, I>(f)) wall_link(ic, vu, vt);
                     __builtin_amdgcn_sched_barrier(0);   // one wall link at a time
@@ -913,12 +1027,20 @@ __device__ __forceinline__ void ut_body(const Coef<T>& c, int block, const S* __
                 const T dhv = (I == 0) ? iu[I] - du + Bi * hb : iu[I] + Bi * hb;
                 const S hv = Codec<S>::enc(dhv), fv = Codec<S>::enc(it[I] - wi * dth);
                 if constexpr (BUF) {
-                    const unsigned vx = xi * (unsigned)sizeof(S), sI = (unsigned)(I * np) * (unsigned)sizeof(S);
-                    if constexpr (SU) buf_st(hv, rhout, vx, sI);
-                    if constexpr (ST) buf_st(fv, rfout, vx, sI);
+                    const unsigned vx = xi * PS, sI = (unsigned)(I * np) * PS;
+                    if constexpr (PAIR) {
+                        Pair<S>::st(Pair<S>::pack(hv, fv), rhout, vx, sI);
+                    } else {
+                        if constexpr (SU) buf_st(hv, rhout, vx, sI);
+                        if constexpr (ST) buf_st(fv, rfout, vx, sI);
+                    }
                 } else {
-                    if constexpr (SU) st_nt(&hout[(size_t)I * np + xi], hv);
-                    if constexpr (ST) st_nt(&fout[(size_t)I * np + xi], fv);
+                    if constexpr (PAIR) {
+                        Pair<S>::stg(Pair<S>::pack(hv, fv), hout + 2 * ((size_t)I * np + xi));
+                    } else {
+                        if constexpr (SU) st_nt(&hout[(size_t)I * np + xi], hv);
+                        if constexpr (ST) st_nt(&fout[(size_t)I * np + xi], fv);
+                    }
                 }
             });
         }
@@ -1001,7 +1123,8 @@ __global__ __launch_bounds__(TX * TY, (sizeof(T) == 4 ? 3 : 1)) void k_ut_batch(
 // ==========================================================================
 template <class L, class T, class S>
 __global__ __launch_bounds__(256) void k_init(const Coef<T> c, S* __restrict__ g, S* __restrict__ h,
-                                              S* __restrict__ f, const T* __restrict__ phi,
+                                              S* __restrict__ f, int hs,   // element stride of h and f
+                                              const T* __restrict__ phi,
                                               const T* __restrict__ U, const T* __restrict__ th,
                                               int parts) {   // bit 0: g, bit 1: h and f (on lattice L)
     const int nx = c.nx, ny = c.ny, nz = c.nz, px = c.px;
@@ -1041,16 +1164,16 @@ __global__ __launch_bounds__(256) void k_init(const Coef<T> c, S* __restrict__ g
         const T eJ = T(L::ex(I)) * Jx + T(L::ey(I)) * Jy + T(L::ez(I)) * Jz;
         const size_t o = (size_t)I * c.np + s;
         if (parts & 1) g[o] = Codec<S>::enc(-wi * eN * c.cphi_e2);
-        if (parts & 2) h[o] = Codec<S>::enc((I == 0) ? T(0) : wi * eJ * c.jt);
+        if (parts & 2) h[o * hs] = Codec<S>::enc((I == 0) ? T(0) : wi * eJ * c.jt);
         // f = w_i theta [1 + e_i . v dt / (e^2 dx)]: deviation w_i theta e_i . v'
         const T ev = T(L::ex(I)) * ax + T(L::ey(I)) * ay + T(L::ez(I)) * az;
-        if (parts & 2) f[o] = Codec<S>::enc(c.has_adv ? wi * th[s] * ev : T(0));
+        if (parts & 2) f[o * hs] = Codec<S>::enc(c.has_adv ? wi * th[s] * ev : T(0));
     });
 }
 
 // Full populations in FP64 (deviation + rest equilibrium) for inspection.
 template <class L, class T, class S>
-__global__ __launch_bounds__(256) void k_decode(const Coef<T> c, const S* __restrict__ pop, int field,
+__global__ __launch_bounds__(256) void k_decode(const Coef<T> c, const S* __restrict__ pop, int es, int field,
                                                 const T* __restrict__ phi, const T* __restrict__ U,
                                                 const T* __restrict__ th, double* __restrict__ out) {
     const size_t n = (size_t)c.nx * c.ny * c.nz;
@@ -1061,7 +1184,7 @@ __global__ __launch_bounds__(256) void k_decode(const Coef<T> c, const S* __rest
     Unroll<0, L::Q>::run([&](auto ic) {
         constexpr int I = decltype(ic)::value;
         constexpr double wi = L::w(I);
-        const double d = (double)(T)Codec<S>::dec(pop[(size_t)I * c.np + s]);
+        const double d = (double)(T)Codec<S>::dec(pop[((size_t)I * c.np + s) * es]);
         double ref;
         if (field == 0) {
             ref = wi * (double)phi[s];
@@ -1081,6 +1204,7 @@ __global__ __launch_bounds__(256) void k_decode(const Coef<T> c, const S* __rest
 // ==========================================================================
 template <class L, class B>
 __global__ __launch_bounds__(256) void k_stream_only(int nx, int ny, int nz, int px, int symm, long long np,
+                                                     int es,   // element stride
                                                      const B* __restrict__ in, B* __restrict__ out) {
     const size_t n = (size_t)nx * ny * nz;
     const size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -1091,7 +1215,7 @@ __global__ __launch_bounds__(256) void k_stream_only(int nx, int ny, int nz, int
         constexpr int I = decltype(ic)::value;
         const Src src = source<L, I>(x, y, z, nx, ny, nz, symm);
         const size_t si = ((size_t)src.sz * ny + src.sy) * px + src.sx;
-        out[(size_t)I * np + s] = in[(size_t)src.j * np + si];
+        out[((size_t)I * np + s) * es] = in[((size_t)src.j * np + si) * es];
     });
 }
 

@@ -252,7 +252,7 @@ lbpf_status launch_init_t(lbpf_ctx* ctx) {
     const int a = ctx->cur;
     const int parts = (ctx->q == L::Q ? 1 : 0) | (ctx->q_ut == L::Q ? 2 : 0);
     hipLaunchKernelGGL((k_init<L, T, S>), dim3(nb), dim3(256), 0, ctx->stream, c, (S*)ctx->pop[0][a],
-                       (S*)ctx->pop[1][a], (S*)ctx->pop[2][a], (const T*)ctx->fld[0][a],
+                       (S*)ctx->pop[1][a], (S*)ctx->pop[2][a], ctx->hs, (const T*)ctx->fld[0][a],
                        (const T*)ctx->fld[1][a], (const T*)ctx->fld[2][a], parts);
     CHK(hipGetLastError());
     return LBPF_OK;
@@ -264,7 +264,7 @@ lbpf_status launch_decode_t(lbpf_ctx* ctx, int field, double* dout) {
     const int nb = (int)((ctx->n + 255) / 256);
     const int a = ctx->cur;
     hipLaunchKernelGGL((k_decode<L, T, S>), dim3(nb), dim3(256), 0, ctx->stream, c,
-                       (const S*)ctx->pop[field][a], field, (const T*)ctx->fld[0][a],
+                       (const S*)ctx->pop[field][a], pop_stride(ctx, field), field, (const T*)ctx->fld[0][a],
                        (const T*)ctx->fld[1][a], (const T*)ctx->fld[2][a], dout);
     CHK(hipGetLastError());
     return LBPF_OK;
@@ -314,7 +314,7 @@ lbpf_status stream_only_t(lbpf_ctx* ctx, int f0, int f1) {
     for (int f = f0; f < f1; ++f)
         hipLaunchKernelGGL((k_stream_only<L, B>), dim3(nb), dim3(256), 0, ctx->stream, ctx->grid.nx,
                            ctx->grid.ny, ctx->grid.nz, ctx->px, symm, (long long)ctx->np,
-                           (const B*)ctx->pop[f][a], (B*)ctx->pop[f][b]);
+                           pop_stride(ctx, f), (const B*)ctx->pop[f][a], (B*)ctx->pop[f][b]);
     CHK(hipGetLastError());
     return LBPF_OK;
 }
@@ -432,10 +432,11 @@ void free_all(lbpf_ctx* ctx) {
     ctx->gexec = nullptr;
     for (int f = 0; f < 3; ++f)
         for (int p = 0; p < 2; ++p) {
-            if (ctx->pop[f][p]) (void)hipFree(ctx->pop[f][p]);
+            if (ctx->pop[f][p] && pop_alloc_bytes(ctx, f)) (void)hipFree(ctx->pop[f][p]);
             if (ctx->fld[f][p]) (void)hipFree(ctx->fld[f][p]);
-            ctx->pop[f][p] = ctx->fld[f][p] = nullptr;
         }
+    for (int f = 0; f < 3; ++f)
+        for (int p = 0; p < 2; ++p) ctx->pop[f][p] = ctx->fld[f][p] = nullptr;
     if (ctx->part) (void)hipFree(ctx->part);
     if (ctx->hist) (void)hipFree(ctx->hist);
     if (ctx->fresh) (void)hipFree(ctx->fresh);
@@ -540,10 +541,17 @@ lbpf_status lbpf_create(const lbpf_grid* grid, const lbpf_params* params, void* 
     // sit a power of two apart (at 256^3 that power of two is 64 MiB, and
     // k_phi FP32 runs 3.5 % slower on it).
     ctx->np = (ctx->na + 63) / 64 * 64 + kStridePadBytes / ctx->sbytes;
+    // h and f of a node and direction are pulled from the same source: with
+    // both fields solved they share one pair array, loaded and stored by k_ut
+    // with one instruction per direction
+    ctx->hs = (p.skip_U == 0 && p.skip_theta == 0) ? 2 : 1;
     hipError_t e = hipSuccess;
     for (int f = 0; f < 3 && e == hipSuccess; ++f)
         for (int par = 0; par < 2 && e == hipSuccess; ++par) {
-            e = hipMalloc(&ctx->pop[f][par], ctx->np * lattice_of(ctx, f) * ctx->sbytes);
+            if (pop_alloc_bytes(ctx, f))
+                e = hipMalloc(&ctx->pop[f][par], pop_alloc_bytes(ctx, f));
+            else
+                ctx->pop[f][par] = (char*)ctx->pop[1][par] + ctx->sbytes;   // f: the odd elements
             if (e == hipSuccess) e = hipMalloc(&ctx->fld[f][par], ctx->na * ctx->tbytes);
         }
     if (e == hipSuccess) e = hipMalloc((void**)&ctx->part, RED_BLOCKS * RED_STRIDE * sizeof(double));
@@ -773,10 +781,17 @@ lbpf_status lbpf_read_populations(lbpf_ctx* ctx, int32_t field, void* dst) {
     CHK(hipStreamSynchronize(ctx->stream));
     const size_t arr = ctx->n * ctx->sbytes, w = ctx->grid.nx * ctx->sbytes, pw = ctx->px * ctx->sbytes;
     const size_t rows = (size_t)ctx->grid.ny * ctx->grid.nz;
-    std::vector<char> tmp(ctx->na * ctx->sbytes);
+    const int es = pop_stride(ctx, field), lane = pop_lane(ctx, field);
+    const char* base = (const char*)pop_alloc(ctx, field, ctx->cur);
+    std::vector<char> tmp(ctx->na * ctx->sbytes), pairs(es > 1 ? ctx->na * ctx->sbytes * es : 0);
     for (int i = 0; i < lattice_of(ctx, field); ++i) {
-        CHK(hipMemcpy(tmp.data(), (const char*)ctx->pop[field][ctx->cur] + i * ctx->np * ctx->sbytes, tmp.size(),
-                      hipMemcpyDeviceToHost));
+        if (es == 1) {
+            CHK(hipMemcpy(tmp.data(), base + i * ctx->np * ctx->sbytes, tmp.size(), hipMemcpyDeviceToHost));
+        } else {   // this field's elements of the pair array
+            CHK(hipMemcpy(pairs.data(), base + i * ctx->np * es * ctx->sbytes, pairs.size(), hipMemcpyDeviceToHost));
+            for (size_t k = 0; k < ctx->na; ++k)
+                std::memcpy(tmp.data() + k * ctx->sbytes, pairs.data() + (k * es + lane) * ctx->sbytes, ctx->sbytes);
+        }
         unpack_rows((char*)dst + i * arr, tmp.data(), w, pw, rows);
     }
     return LBPF_OK;
@@ -789,11 +804,20 @@ lbpf_status lbpf_write_populations(lbpf_ctx* ctx, int32_t field, const void* src
     CHK(hipStreamSynchronize(ctx->stream));
     const size_t arr = ctx->n * ctx->sbytes, w = ctx->grid.nx * ctx->sbytes, pw = ctx->px * ctx->sbytes;
     const size_t rows = (size_t)ctx->grid.ny * ctx->grid.nz;
-    std::vector<char> tmp(ctx->na * ctx->sbytes, 0);
+    const int es = pop_stride(ctx, field), lane = pop_lane(ctx, field);
+    char* base = (char*)pop_alloc(ctx, field, ctx->cur);
+    std::vector<char> tmp(ctx->na * ctx->sbytes, 0), pairs(es > 1 ? ctx->na * ctx->sbytes * es : 0);
     for (int i = 0; i < lattice_of(ctx, field); ++i) {
         pack_rows(tmp.data(), (const char*)src + i * arr, w, pw, rows);
-        CHK(hipMemcpy((char*)ctx->pop[field][ctx->cur] + i * ctx->np * ctx->sbytes, tmp.data(), tmp.size(),
-                      hipMemcpyHostToDevice));
+        if (es == 1) {
+            CHK(hipMemcpy(base + i * ctx->np * ctx->sbytes, tmp.data(), tmp.size(), hipMemcpyHostToDevice));
+        } else {   // replace this field's elements of the pair array, keep the other's
+            char* dev = base + i * ctx->np * es * ctx->sbytes;
+            CHK(hipMemcpy(pairs.data(), dev, pairs.size(), hipMemcpyDeviceToHost));
+            for (size_t k = 0; k < ctx->na; ++k)
+                std::memcpy(pairs.data() + (k * es + lane) * ctx->sbytes, tmp.data() + k * ctx->sbytes, ctx->sbytes);
+            CHK(hipMemcpy(dev, pairs.data(), pairs.size(), hipMemcpyHostToDevice));
+        }
     }
     return LBPF_OK;
 }
@@ -902,18 +926,23 @@ lbpf_status lbpf_autotune(lbpf_ctx* ctx, int32_t steps_per_candidate, double* be
     if (steps_per_candidate < 1) return fail(ctx, LBPF_EINVAL, "steps_per_candidate < 1");
     if (!ctx->have_fields) return fail(ctx, LBPF_ESTATE, "lbpf_set_fields has not been called");
     CHK(hipStreamSynchronize(ctx->stream));
-    // snapshot of the current state (populations and fields of parity cur)
-    // (one slot per population set, sized for the larger lattice)
-    const size_t pbytes = ctx->np * std::max(ctx->q, ctx->q_ut) * ctx->sbytes, fbytes = ctx->na * ctx->tbytes;
-    size_t pset[3];
-    for (int f = 0; f < 3; ++f) pset[f] = ctx->np * lattice_of(ctx, f) * ctx->sbytes;
+    // snapshot of the current state (populations and fields of parity cur):
+    // the population allocations one after another, then the three fields
+    const size_t fbytes = ctx->na * ctx->tbytes;
+    size_t pset[3], poff[3], ptot = 0;
+    for (int f = 0; f < 3; ++f) {
+        pset[f] = pop_alloc_bytes(ctx, f);
+        poff[f] = ptot;
+        ptot += pset[f];
+    }
     void* snap = nullptr;
-    CHK(hipMalloc(&snap, 3 * (pbytes + fbytes)));
+    CHK(hipMalloc(&snap, ptot + 3 * fbytes));
     const int cur0 = ctx->cur;
     for (int f = 0; f < 3; ++f) {
-        CHK(hipMemcpyAsync((char*)snap + f * pbytes, ctx->pop[f][cur0], pset[f], hipMemcpyDeviceToDevice,
-                           ctx->stream));
-        CHK(hipMemcpyAsync((char*)snap + 3 * pbytes + f * fbytes, ctx->fld[f][cur0], fbytes,
+        if (pset[f])
+            CHK(hipMemcpyAsync((char*)snap + poff[f], ctx->pop[f][cur0], pset[f], hipMemcpyDeviceToDevice,
+                               ctx->stream));
+        CHK(hipMemcpyAsync((char*)snap + ptot + f * fbytes, ctx->fld[f][cur0], fbytes,
                            hipMemcpyDeviceToDevice, ctx->stream));
     }
     // launches timed so far count for the caller; the tuner's own stay apart
@@ -961,9 +990,10 @@ lbpf_status lbpf_autotune(lbpf_ctx* ctx, int32_t steps_per_candidate, double* be
     // restore the state and keep the best launch of each kernel
     ctx->cur = cur0;
     for (int f = 0; f < 3; ++f) {
-        (void)hipMemcpyAsync(ctx->pop[f][cur0], (char*)snap + f * pbytes, pset[f], hipMemcpyDeviceToDevice,
-                             ctx->stream);
-        (void)hipMemcpyAsync(ctx->fld[f][cur0], (char*)snap + 3 * pbytes + f * fbytes, fbytes,
+        if (pset[f])
+            (void)hipMemcpyAsync(ctx->pop[f][cur0], (char*)snap + poff[f], pset[f], hipMemcpyDeviceToDevice,
+                                 ctx->stream);
+        (void)hipMemcpyAsync(ctx->fld[f][cur0], (char*)snap + ptot + f * fbytes, fbytes,
                              hipMemcpyDeviceToDevice, ctx->stream);
     }
     (void)drain_launches(ctx, nullptr, nullptr);
@@ -1374,7 +1404,7 @@ lbpf_status lbpf_batch_create(int32_t n, const lbpf_grid* grids, const lbpf_para
         }
         c->in_batch = true;
         b->dom.push_back(c);
-        if ((size_t)std::max(c->q, c->q_ut) * c->np * c->sbytes >= ((size_t)1 << 32) - 256) {
+        if (std::max(pop_alloc_bytes(c, 0), pop_alloc_bytes(c, 1)) >= ((size_t)1 << 32) - 256) {
             for (lbpf_ctx* d : b->dom) { d->in_batch = false; lbpf_destroy(d); }
             if (b->own_stream) (void)hipStreamDestroy(b->stream);
             delete b;
@@ -1443,7 +1473,7 @@ lbpf_status lbpf_batch_autotune(lbpf_batch* b, int32_t steps_per_candidate, doub
     size_t total = 0;
     for (lbpf_ctx* c : b->dom) {
         off.push_back(total);
-        for (int f = 0; f < 3; ++f) total += c->np * lattice_of(c, f) * c->sbytes + c->na * c->tbytes;
+        for (int f = 0; f < 3; ++f) total += pop_alloc_bytes(c, f) + c->na * c->tbytes;
     }
     char* snap = nullptr;
     BCHK(hipMalloc((void**)&snap, total));
@@ -1452,9 +1482,11 @@ lbpf_status lbpf_batch_autotune(lbpf_batch* b, int32_t steps_per_candidate, doub
             lbpf_ctx* c = b->dom[d];
             size_t o = off[d];
             for (int f = 0; f < 3; ++f) {
-                const size_t pb = c->np * lattice_of(c, f) * c->sbytes, fb = c->na * c->tbytes;
-                hipError_t e = save ? hipMemcpyAsync(snap + o, c->pop[f][cur0], pb, hipMemcpyDeviceToDevice, b->stream)
-                                    : hipMemcpyAsync(c->pop[f][cur0], snap + o, pb, hipMemcpyDeviceToDevice, b->stream);
+                const size_t pb = pop_alloc_bytes(c, f), fb = c->na * c->tbytes;
+                hipError_t e = hipSuccess;
+                if (pb)
+                    e = save ? hipMemcpyAsync(snap + o, c->pop[f][cur0], pb, hipMemcpyDeviceToDevice, b->stream)
+                             : hipMemcpyAsync(c->pop[f][cur0], snap + o, pb, hipMemcpyDeviceToDevice, b->stream);
                 if (e != hipSuccess) return e;
                 o += pb;
                 e = save ? hipMemcpyAsync(snap + o, c->fld[f][cur0], fb, hipMemcpyDeviceToDevice, b->stream)

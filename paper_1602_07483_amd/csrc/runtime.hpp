@@ -88,6 +88,10 @@ struct lbpf_ctx {
     size_t na = 0;           // elements of one device field array, px * ny * nz
     size_t np = 0;           // population stride in elements (na rounded up to 64)
     void* pop[3][2] = {};    // [field][parity]
+    // Element stride of h and f: 2 when both fields are solved and their
+    // populations share one pair array (h at even, f at odd elements;
+    // pop[2] is then pop[1] plus one element and owns no memory), else 1.
+    int hs = 1;
     void* fld[3][2] = {};    // phi, U, theta [parity]
     int cur = 0;
     bool have_fields = false;
@@ -186,6 +190,21 @@ inline bool has_advection(const lbpf_ctx* ctx) {
 inline int lattice_of(const lbpf_ctx* ctx, int f) { return f == 0 ? ctx->q : ctx->q_ut; }
 
 inline int default_shape(const lbpf_ctx* ctx, int k) { return kDefaultShape[k][ctx->storage]; }
+
+// Element stride of field f's populations (1, or 2 for paired h and f).
+inline int pop_stride(const lbpf_ctx* ctx, int f) { return f == 0 ? 1 : ctx->hs; }
+// Bytes of the allocation that holds field f's populations, 0 where another
+// field's allocation holds them (f of a pair).
+inline size_t pop_alloc_bytes(const lbpf_ctx* ctx, int f) {
+    if (f == 2 && ctx->hs == 2) return 0;
+    return ctx->np * (size_t)lattice_of(ctx, f) * ctx->sbytes * (size_t)pop_stride(ctx, f);
+}
+// The allocation holding field f's populations at parity par, and the
+// element offset of field f within each of its elements' strides.
+inline void* pop_alloc(const lbpf_ctx* ctx, int f, int par) {
+    return (f == 2 && ctx->hs == 2) ? ctx->pop[1][par] : ctx->pop[f][par];
+}
+inline int pop_lane(const lbpf_ctx* ctx, int f) { return (f == 2 && ctx->hs == 2) ? 1 : 0; }
 
 inline int adv_shape(const lbpf_ctx* ctx) { return kAdvShape[ctx->storage]; }
 

@@ -50,10 +50,11 @@ lbpf_status launch_ut(lbpf_ctx* ctx) {
     });
 }
 
-// One buffer resource per field when its Q population arrays total < 4 GiB.
+// One buffer resource per population array when it holds < 4 GiB (for k_ut
+// the pair array of h and f when they share one).
 template <class L, class T, class S, int K, int TX, int TY>
 lbpf_status launch_t(lbpf_ctx* ctx) {
-    const size_t pbytes = (size_t)L::Q * ctx->np * sizeof(S);
+    const size_t pbytes = (size_t)L::Q * ctx->np * sizeof(S) * (size_t)(K == K_UT ? ctx->hs : 1);
     const bool buf = pbytes < ((size_t)1 << 32) - 256;
     if constexpr (sizeof(T) == 8) {
         if (!buf) return fail(ctx, LBPF_EINVAL, "FP64 verification build limited to < 4 GiB per field");

@@ -259,6 +259,9 @@ lbpf_status lbpf_read_fields_device(lbpf_ctx* ctx, void* phi, void* U, void* the
  * the three writes.  Q is the field's lattice (lbpf_grid.lattice for phi,
  * lattice_ut, when set, for U and theta); the size of dst/src is
  * Q*nx*ny*nz*lbpf_storage_bytes.
+ * The device layout is the library's own (h and f share one array when
+ * both fields are solved); a write of one field leaves the others' stored
+ * bits unchanged.
  * Both synchronise; the fields are not changed by a write.
  * Errors: EINVAL (bad field, NULL), ESTATE (write before set_fields). */
 lbpf_status lbpf_read_populations(lbpf_ctx* ctx, int32_t field, void* dst);

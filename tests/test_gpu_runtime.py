@@ -387,6 +387,34 @@ def test_separate_lattices_runtime_paths():
 
 
 @pytest.mark.gpu
+@pytest.mark.parametrize("storage,over", [("f32", {}), ("f16", {}), ("bf16", {}), ("f64", {}),
+                                          ("f32", {"skip_theta": 1}), ("f16", {"skip_U": 1})])
+def test_population_writes_leave_other_fields_intact(storage, over):
+    """With both transport fields solved, h and f share one device array
+    (side by side per direction and node); in the single-field modes each has
+    its own.  Writing one field's populations must leave the others' bit for
+    bit, and each field must read back exactly what was written, on both
+    layouts and every storage type."""
+    pb = dataclasses.replace(ragged(), Mcinf=0.0) if over.get("skip_U") else ragged()
+    s = lbpf.solver_for(pb, storage=storage, **over)
+    s.set_fields(*pb.initial_fields())
+    s.step(3)
+    rng = np.random.default_rng(11)
+
+    def bits(a):
+        return a.view(np.uint8)
+
+    have = [s.read_populations(f) for f in range(3)]
+    for f in (1, 2, 0, 1):
+        new = rng.integers(0, 256, size=bits(have[f]).shape, dtype=np.uint8).view(have[f].dtype)
+        new = new.reshape(have[f].shape)
+        s.write_populations(f, new)
+        have[f] = new
+        for g in range(3):
+            assert np.array_equal(bits(s.read_populations(g)), bits(have[g])), (f, g)
+
+
+@pytest.mark.gpu
 def test_autotune_cache(tmp_path):
     """lbpf_autotune_cached: the first call tunes and appends one line, a
     second context of the same configuration takes its launches from that

@@ -367,7 +367,7 @@ def cpu_baseline(n=256):
     from paper_1602_07483_amd.inputs import workload_centred, workload_octant
     threads = oracle.num_threads()
     v, steps = _oracle_rate(workload_centred(n=n), 12.0, 12)
-    v128, s128 = _oracle_rate(workload_octant(128), 6.0, 40)
+    v128, s128 = _oracle_rate(workload_octant(128), 12.0, 100)   # the 128^3 run of 100 steps
     one = None
     try:
         gomp = ctypes.CDLL("libgomp.so.1")

@@ -163,6 +163,43 @@ def test_thermal2d_steady_velocity_does_not_depend_on_the_initial_width():
     assert max(v.values()) < 1.003 * v[1.0]
 
 
+def test_thermal2d_tip_velocity_does_not_depend_on_the_tip_estimator():
+    """Reading R16 places the tip at the linearly interpolated phi = 0
+    crossing.  A quadratic crossing through three nodes around it moves each
+    position by a near-constant amount while the tip advances steadily, so
+    the velocity between T = 296 and T = 300 (dx/W0 = 0.4) must agree within
+    0.2 % whichever is used, and the linear one equals the library's reduced
+    tip velocity."""
+    pb = workload_thermal2d()
+    s = lbpf.solver_for(pb, storage="f32", skip_U=1)
+    s.set_fields(*pb.initial_fields())
+    every = pb.reduce_every
+    s.step(pb.steps - every)
+    rows = [s.read()[0][0, 0, :]]
+    s.step(every)
+    phi, _, _, red = s.read()
+    rows.append(phi[0, 0, :])
+    hist = s.history()
+    s.close()
+
+    def tips(row):
+        i = int(np.nonzero((row[:-1] > 0) & (row[1:] <= 0))[0].max())
+        lin = i + row[i] / (row[i] - row[i + 1])
+        a, b, c = row[i - 1], row[i], row[i + 1]   # parabola through i-1, i, i+1 (t = x - i)
+        qa, qb, qc = 0.5 * (a + c) - b, 0.5 * (c - a), b
+        r = np.roots([qa, qb, qc])
+        quad = i + float(np.real(r[(np.isreal(r)) & (np.real(r) >= 0) & (np.real(r) <= 1)][0]))
+        return lin, quad
+
+    (l0, q0), (l1, q1) = tips(rows[0]), tips(rows[1])
+    scale = pb.dx / pb.dt * (0.8839 / pb.lam) / pb.kappa / every
+    v_lin, v_quad = (l1 - l0) * scale, (q1 - q0) * scale
+    v_red = (hist[-1]["tip"][0] - hist[-2]["tip"][0]) * scale
+    print("V_p(T=300): linear %.5f, quadratic %.5f, reduction %.5f" % (v_lin, v_quad, v_red))
+    assert abs(v_quad - v_lin) / v_lin < 2e-3
+    assert abs(v_red - v_lin) / v_lin < 1e-6
+
+
 def test_thermal2d_tip_velocity_paper_lattices():
     """Sec. 4.1's own lattice pair: the phase field on D2Q9 and theta on
     D2Q5, here a one-node slab with phi on D3Q19 (D2Q9 after the mirror

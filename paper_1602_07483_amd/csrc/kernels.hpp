@@ -351,6 +351,14 @@ __device__ __forceinline__ V opaque_v(V v) {
     return v;
 }
 
+// Marks a loaded value as used on a path that has no use for it, so that its
+// load is waited for there and not, later, by a write of the same register
+// that would then also wait for every store issued since.
+template <class V>
+__device__ __forceinline__ void consume(const V& v) {
+    asm volatile("" ::"v"(v));
+}
+
 // Compile-time loop over the directions.
 template <int I, int Q>
 struct Unroll {
@@ -435,10 +443,13 @@ struct Tile {
         y0 = by * TY;
         zs = bz * c.zslab;
         ze = min(zs + c.zslab, c.nz);
-        x = x0 + (int)threadIdx.x % TX;
-        y = y0 + (int)threadIdx.x / TX;
-        lt = (y - y0 + 1) * HX + (x - x0 + 1);
-        active = x < c.nx && y < c.ny;
+        const int ux = x0 + (int)threadIdx.x % TX, uy = y0 + (int)threadIdx.x / TX;
+        lt = (uy - y0 + 1) * HX + (ux - x0 + 1);
+        active = ux < c.nx && uy < c.ny;
+        // a lane past the domain's last column or row works on the nearest
+        // node of the tile and stores nothing
+        x = min(ux, c.nx - 1);
+        y = min(uy, c.ny - 1);
         // no node of the tile lies on an x or y face
         xy_inner = x0 > 0 && x0 + TX < c.nx && y0 > 0 && y0 + TY < c.ny;
         f.xl = x == 0; f.xh = x == c.nx - 1;
@@ -450,8 +461,10 @@ struct Tile {
 // The march.  Iteration zz of a block stages the stencil-field plane zz (A),
 // computes the node terms of plane zz-1 (B) and pulls plane zz-2 (C).  All
 // global loads an iteration needs (the field plane, the fields at the term
-// nodes and the populations of the pulled plane) are issued together at the
-// end of the previous iteration, so each iteration waits for memory once.
+// nodes and the populations of the pulled plane) are issued together, before
+// stage A: K_ut issues them at the end of the previous iteration and waits
+// for them once; K_phi issues them at the top of the iteration and waits for
+// each group where it is used.
 // ==========================================================================
 template <int TX, int TY>
 struct March {
@@ -492,6 +505,33 @@ __device__ __forceinline__ void phi_body(const Coef<T>& c, int block, const S* _
     const unsigned pbytes = (unsigned)((size_t)L::Q * (size_t)c.np * sizeof(S));
     const __amdgpu_buffer_rsrc_t rin = make_rsrc(gin, BUF ? pbytes : 0u);
     const __amdgpu_buffer_rsrc_t rout = make_rsrc(gout, BUF ? pbytes : 0u);
+    // The fields through buffer resources too: a lane's offset within a
+    // plane is fixed for the whole march, the plane is a scalar offset.
+    const unsigned fbytes = BUF ? (unsigned)((size_t)nz * plane * sizeof(T)) : 0u;
+    const __amdgpu_buffer_rsrc_t rphi = make_rsrc(phin, fbytes), rU = make_rsrc(Un, fbytes),
+                                 rth = make_rsrc(thn, fbytes);
+    unsigned oa[M::NA], ob[M::NB];     // in-plane offsets of the staged and term nodes
+#pragma unroll
+    for (int k = 0; k < M::NA; ++k) {
+        const int t = min((int)threadIdx.x + k * G::NT, G::PN - 1);
+        oa[k] = (unsigned)(clampi(tile.y0 - 2 + t / G::PX, ny) * px + clampi(tile.x0 - 2 + t % G::PX, nx));
+    }
+#pragma unroll
+    for (int k = 0; k < M::NB; ++k) {
+        const int t = min((int)threadIdx.x + k * G::NT, G::HN - 1);
+        ob[k] = (unsigned)(clampi(tile.y0 - 1 + t / G::HX, ny) * px + clampi(tile.x0 - 1 + t % G::HX, nx));
+    }
+    // In-plane byte offsets of the lane's node and its eight in-plane
+    // neighbours, clamped to the domain.  The source of link i lies in plane
+    // z - e_z at neighbour (-e_x, -e_y); clamping every coordinate gives a
+    // link that crosses a wall an in-bounds stand-in, which stage C replaces.
+    unsigned nbo[3][3];
+#pragma unroll
+    for (int dy = 0; dy < 3; ++dy)
+#pragma unroll
+        for (int dx = 0; dx < 3; ++dx)
+            nbo[dy][dx] = (unsigned)(clampi(tile.y + dy - 1, ny) * px + clampi(tile.x + dx - 1, nx)) *
+                          (unsigned)sizeof(S);
 
     // registers filled one iteration ahead
     T pa[M::NA];                       // phi^n of the staged plane
@@ -499,50 +539,56 @@ __device__ __forceinline__ void phi_body(const Coef<T>& c, int block, const S* _
     // d_j(source) and d_i(x) of the pulled plane, kept in the storage format
     // and decoded where used, so no conversion sits between the loads.
     typename Raw<S>::type pj[L::Q], pnl[L::Q];
-    auto prefetch = [&](int zz) {
+    // The first four iterations of a slab fill the staged planes (stages A
+    // and B only); every later one runs all three stages on the same loads
+    // in the same order (lanes outside the domain read an in-bounds
+    // stand-in).  With no path that skips a use, each group of loads is
+    // waited for where it is used: the populations of stage C stay in flight
+    // through stages A and B.
+    auto prefetch = [&](int zz, auto full_c) {
         {   // A of iteration zz
             const size_t base = (size_t)clampi(zz, nz) * plane;
 #pragma unroll
             for (int k = 0; k < M::NA; ++k) {
-                const int t = (int)threadIdx.x + k * G::NT;
-                if (t < G::PN) {
-                    const int gx = clampi(tile.x0 - 2 + t % G::PX, nx), gy = clampi(tile.y0 - 2 + t / G::PX, ny);
-                    pa[k] = phin[base + (size_t)gy * px + gx];
-                }
+                if constexpr (BUF)
+                    pa[k] = buf_ld<T>(rphi, oa[k] * (unsigned)sizeof(T), (unsigned)base * (unsigned)sizeof(T));
+                else
+                    pa[k] = phin[base + oa[k]];
             }
         }
-        if (zz >= tile.zs) {   // B of iteration zz: terms of plane zz-1
+        {   // B of iteration zz: terms of plane zz-1
             const size_t base = (size_t)clampi(zz - 1, nz) * plane;
 #pragma unroll
             for (int k = 0; k < M::NB; ++k) {
-                const int t = (int)threadIdx.x + k * G::NT;
-                if (t < G::HN) {
-                    const int gx = clampi(tile.x0 - 1 + t % G::HX, nx), gy = clampi(tile.y0 - 1 + t / G::HX, ny);
-                    const size_t gi = base + (size_t)gy * px + gx;
-                    pu[k] = Un[gi];
-                    pt[k] = thn[gi];
+                if constexpr (BUF) {
+                    pu[k] = buf_ld<T>(rU, ob[k] * (unsigned)sizeof(T), (unsigned)base * (unsigned)sizeof(T));
+                    pt[k] = buf_ld<T>(rth, ob[k] * (unsigned)sizeof(T), (unsigned)base * (unsigned)sizeof(T));
+                } else {
+                    pu[k] = Un[base + ob[k]];
+                    pt[k] = thn[base + ob[k]];
                 }
             }
         }
-        if (zz >= tile.zs + 2 && tile.active) {   // C of iteration zz: plane zz-2
+        if constexpr (decltype(full_c)::value) {   // C of iteration zz: plane zz-2
             const int z = zz - 2;
             const unsigned xi = (unsigned)z * plane + (unsigned)tile.y * px + tile.x;
             Faces f = tile.f;
             f.zl = z == 0;
             f.zh = z == nz - 1;
             const size_t np = (size_t)opaque(c.np);
+            // planes z + 1, z, z - 1 (clamped), the source planes of e_z = -1, 0, 1
+            const unsigned zo[3] = {(unsigned)clampi(z + 1, nz) * plane, (unsigned)z * plane,
+                                    (unsigned)clampi(z - 1, nz) * plane};
             Unroll<0, L::Q>::run([&](auto ic) {
                 constexpr int I = decltype(ic)::value;
                 constexpr int ex = L::ex(I), ey = L::ey(I), ez = L::ez(I);
                 const int off = ex + ey * px + ez * (int)plane;
-                const bool cr = crosses<L, I>(f);    // wall links: read any in-bounds value
                 if constexpr (BUF) {
-                    const unsigned vx = xi * (unsigned)sizeof(S);
-                    const unsigned sI = (unsigned)(I * np) * (unsigned)sizeof(S);
-                    const unsigned vj = cr ? vx + (unsigned)off * (unsigned)sizeof(S) : vx;
-                    pnl[I] = Raw<S>::template ld<>(rin, vx, sI);
-                    pj[I] = Raw<S>::template ld<>(rin, vj, sI - (unsigned)off * (unsigned)sizeof(S));
+                    pnl[I] = Raw<S>::template ld<>(rin, nbo[1][1], (unsigned)(I * np + zo[1]) * (unsigned)sizeof(S));
+                    pj[I] = Raw<S>::template ld<>(rin, nbo[1 - ey][1 - ex],
+                                                  (unsigned)(I * np + zo[1 + ez]) * (unsigned)sizeof(S));
                 } else {
+                    const bool cr = crosses<L, I>(f);    // wall links: read any in-bounds value
                     const S* gI = gin + (size_t)I * np;
                     const unsigned so = cr ? xi : xi - (unsigned)off;
                     pnl[I] = Raw<S>::ldg(gI + xi);
@@ -552,20 +598,24 @@ __device__ __forceinline__ void phi_body(const Coef<T>& c, int block, const S* _
         }
     };
 
-    prefetch(tile.zs - 2);
-    for (int zz = tile.zs - 2; zz <= tile.ze + 1; ++zz) {
+    auto iteration = [&](int zz, auto full_c) {
+        constexpr bool FULL = decltype(full_c)::value;
+        prefetch(zz, full_c);
         // A: stage phi^n plane zz
         {
             T* dst = sphi[(zz + 3) % 3];
 #pragma unroll
             for (int k = 0; k < M::NA; ++k) {
                 const int t = (int)threadIdx.x + k * G::NT;
+                consume(pa[k]);
                 if (t < G::PN) dst[t] = pa[k];
             }
         }
         __syncthreads();
         // B: node terms of plane zz-1 (needs phi^n planes zz-2 .. zz)
-        if (zz >= tile.zs) {
+#pragma unroll
+        for (int k = 0; k < M::NB; ++k) { consume(pu[k]); consume(pt[k]); }
+        if (FULL || zz >= tile.zs) {
             const int pz = zz - 1;
             const T* fm = sphi[(pz + 2) % 3];
             const T* f0 = sphi[(pz + 3) % 3];
@@ -597,8 +647,9 @@ __device__ __forceinline__ void phi_body(const Coef<T>& c, int block, const S* _
             }
         }
         __syncthreads();
-        // C: pull plane zz-2 (terms of planes zz-3 .. zz-1 are ready)
-        if (zz >= tile.zs + 2 && tile.active) {
+        // C: pull plane zz-2 (terms of planes zz-3 .. zz-1 are ready).  Lanes
+        // outside the domain compute a stand-in and store nothing.
+        if constexpr (FULL) {
             const int z = zz - 2;
             const unsigned xi = (unsigned)z * plane + (unsigned)tile.y * px + tile.x;
             const int sl[3] = {(z + 2) % 3, (z + 3) % 3, (z + 4) % 3};   // planes z-1, z, z+1
@@ -637,6 +688,8 @@ __device__ __forceinline__ void phi_body(const Coef<T>& c, int block, const S* _
                 T v = wi * (ta.x * (ta.w - phx) + ta.z - eAV) + ta.y * (T)Raw<S>::dec(pj[I]) -
                          (ta.x - T(1)) * (T)Raw<S>::dec(pnl[I]);
                 if constexpr (EDGE && I != 0) {
+                    consume(pj[I]);
+                    consume(pnl[I]);
                     if (crosses<L, I>(f)) v = wall_link(ic);
                     __builtin_amdgcn_sched_barrier(0);   // one wall link at a time
                 }
@@ -647,19 +700,30 @@ __device__ __forceinline__ void phi_body(const Coef<T>& c, int block, const S* _
                 Unroll<0, L::Q>::run([&](auto ic) { fast(ic, std::false_type{}); });
             else
                 Unroll<0, L::Q>::run([&](auto ic) { fast(ic, std::true_type{}); });
-            phout[xi] = phx + dsum;
+            // Both arms used every population; said once more where they
+            // join, so that no load is taken as still in flight past it.
             Unroll<0, L::Q>::run([&](auto ic) {
                 constexpr int I = decltype(ic)::value;
-                constexpr T wi = T(L::w(I));
-                const S v = Codec<S>::enc(inc[I] - wi * dsum);
-                if constexpr (BUF)
-                    buf_st(v, rout, xi * (unsigned)sizeof(S), (unsigned)(I * np) * (unsigned)sizeof(S));
-                else
-                    st_nt(&gout[(size_t)I * np + xi], v);
+                consume(pj[I]);
+                consume(pnl[I]);
             });
+            if (tile.active) {
+                phout[xi] = phx + dsum;
+                Unroll<0, L::Q>::run([&](auto ic) {
+                    constexpr int I = decltype(ic)::value;
+                    constexpr T wi = T(L::w(I));
+                    const S v = Codec<S>::enc(inc[I] - wi * dsum);
+                    if constexpr (BUF)
+                        buf_st(v, rout, xi * (unsigned)sizeof(S), (unsigned)(I * np) * (unsigned)sizeof(S));
+                    else
+                        st_nt(&gout[(size_t)I * np + xi], v);
+                });
+            }
         }
-        if (zz + 1 <= tile.ze + 1) prefetch(zz + 1);
-    }
+    };
+    int zz = tile.zs - 2;
+    for (; zz < tile.zs + 2 && zz <= tile.ze + 1; ++zz) iteration(zz, std::false_type{});
+    for (; zz <= tile.ze + 1; ++zz) iteration(zz, std::true_type{});
 }
 
 // ==========================================================================

@@ -159,7 +159,7 @@ template <> struct Pair<float> {
     __device__ static type ldg(const float* p) { return *reinterpret_cast<const type*>(p); }
     __device__ static float h(type x) { return x.x; }
     __device__ static float f(type x) { return x.y; }
-    __device__ static type pack(float h, float f) { return type{h, f}; }
+    __device__ static type enc2(float h, float f) { return type{h, f}; }
     __device__ static void st(type x, __amdgpu_buffer_rsrc_t r, unsigned v, unsigned s) {
         __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2_t, x), r, (int)v, (int)s, 2);
     }
@@ -174,7 +174,7 @@ template <> struct Pair<double> {
     __device__ static type ldg(const double* p) { return *reinterpret_cast<const type*>(p); }
     __device__ static double h(type x) { return x.x; }
     __device__ static double f(type x) { return x.y; }
-    __device__ static type pack(double h, double f) { return type{h, f}; }
+    __device__ static type enc2(double h, double f) { return type{h, f}; }
     __device__ static void st(type x, __amdgpu_buffer_rsrc_t r, unsigned v, unsigned s) {
         __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4_t, x), r, (int)v, (int)s, 2);
     }
@@ -189,8 +189,13 @@ template <> struct Pair<__half> {
     __device__ static type ldg(const __half* p) { return *reinterpret_cast<const unsigned*>(p); }
     __device__ static float h(type x) { return __half2float(__ushort_as_half((unsigned short)(x & 0xffffu))); }
     __device__ static float f(type x) { return __half2float(__ushort_as_half((unsigned short)(x >> 16))); }
-    __device__ static type pack(__half h, __half f) {
-        return (unsigned)__half_as_ushort(h) | ((unsigned)__half_as_ushort(f) << 16);
+    // encoded and packed as a two-half vector: each conversion is fused with
+    // the FMA before it, the second writing the upper half of the first
+    // one's register (no shift and merge)
+    __device__ static type enc2(float h, float f) {
+        typedef _Float16 h16x2_t __attribute__((ext_vector_type(2)));
+        return __builtin_bit_cast(type, h16x2_t{__builtin_bit_cast(_Float16, Codec<__half>::enc(h)),
+                                                __builtin_bit_cast(_Float16, Codec<__half>::enc(f))});
     }
     __device__ static void st(type x, __amdgpu_buffer_rsrc_t r, unsigned v, unsigned s) {
         __builtin_amdgcn_raw_buffer_store_b32(x, r, (int)v, (int)s, 2);
@@ -206,8 +211,10 @@ template <> struct Pair<__hip_bfloat16> {
     __device__ static type ldg(const __hip_bfloat16* p) { return *reinterpret_cast<const unsigned*>(p); }
     __device__ static float h(type x) { return __builtin_bit_cast(float, x << 16); }
     __device__ static float f(type x) { return __builtin_bit_cast(float, x & 0xffff0000u); }
-    __device__ static type pack(__hip_bfloat16 h, __hip_bfloat16 f) {
-        return (unsigned)__builtin_bit_cast(unsigned short, h) | ((unsigned)__builtin_bit_cast(unsigned short, f) << 16);
+    // both rounded (to nearest even) and packed by one conversion of a pair
+    __device__ static type enc2(float h, float f) {
+        typedef __bf16 b16x2_t __attribute__((ext_vector_type(2)));
+        return __builtin_bit_cast(type, __builtin_convertvector(f32x2_t{h, f}, b16x2_t));
     }
     __device__ static void st(type x, __amdgpu_buffer_rsrc_t r, unsigned v, unsigned s) {
         __builtin_amdgcn_raw_buffer_store_b32(x, r, (int)v, (int)s, 2);
@@ -1089,18 +1096,19 @@ __device__ __forceinline__ void ut_body(const Coef<T>& c, int block, const S* __
                 constexpr T wi = T(L::w(I));
                 constexpr T Bi = (I == 0) ? T(L::w(0)) - T(1) : wi;
                 const T dhv = (I == 0) ? iu[I] - du + Bi * hb : iu[I] + Bi * hb;
-                const S hv = Codec<S>::enc(dhv), fv = Codec<S>::enc(it[I] - wi * dth);
+                const T dfv = it[I] - wi * dth;
+                const S hv = Codec<S>::enc(dhv), fv = Codec<S>::enc(dfv);
                 if constexpr (BUF) {
                     const unsigned vx = xi * PS, sI = (unsigned)(I * np) * PS;
                     if constexpr (PAIR) {
-                        Pair<S>::st(Pair<S>::pack(hv, fv), rhout, vx, sI);
+                        Pair<S>::st(Pair<S>::enc2(dhv, dfv), rhout, vx, sI);
                     } else {
                         if constexpr (SU) buf_st(hv, rhout, vx, sI);
                         if constexpr (ST) buf_st(fv, rfout, vx, sI);
                     }
                 } else {
                     if constexpr (PAIR) {
-                        Pair<S>::stg(Pair<S>::pack(hv, fv), hout + 2 * ((size_t)I * np + xi));
+                        Pair<S>::stg(Pair<S>::enc2(dhv, dfv), hout + 2 * ((size_t)I * np + xi));
                     } else {
                         if constexpr (SU) st_nt(&hout[(size_t)I * np + xi], hv);
                         if constexpr (ST) st_nt(&fout[(size_t)I * np + xi], fv);

@@ -540,7 +540,7 @@ __device__ __forceinline__ void phi_body(const Coef<T>& c, int block, const S* _
             nbo[dy][dx] = (unsigned)(clampi(tile.y + dy - 1, ny) * px + clampi(tile.x + dx - 1, nx)) *
                           (unsigned)sizeof(S);
 
-    // registers filled one iteration ahead
+    // registers filled at the top of each iteration
     T pa[M::NA];                       // phi^n of the staged plane
     T pu[M::NB], pt[M::NB];            // U^n, theta^n at the term nodes
     // d_j(source) and d_i(x) of the pulled plane, kept in the storage format

@@ -324,6 +324,14 @@ __device__ __forceinline__ Src source(int x, int y, int z, int nx, int ny, int n
     return s;
 }
 
+// Index of the direction opposite to I.
+template <class L, int I>
+constexpr int opposite_dir() {
+    for (int i = 0; i < L::Q; ++i)
+        if (L::ex(i) == -L::ex(I) && L::ey(i) == -L::ey(I) && L::ez(i) == -L::ez(I)) return i;
+    return -1;
+}
+
 // Does the incoming link I of a node with the given face flags cross a wall?
 struct Faces {
     bool xl, xh, yl, yh, zl, zh;   // node lies on the -x, +x, -y, +y, -z, +z face
@@ -671,11 +679,21 @@ __device__ __forceinline__ void phi_body(const Coef<T>& c, int block, const S* _
             // Every link as if its source x - e_i were inside the domain; on
             // edge tiles, a link that crosses a wall takes its source after
             // bounce-back or reflection instead (only the lanes it concerns).
+            // When that source is the node itself (bounce-back, or reflection
+            // across every face the link crosses), d_j(source) is the node's
+            // own population of the opposite direction, already loaded as
+            // d_i(x) of that direction; only other reflections load.
             auto wall_link = [&](auto ic) -> T {
                 constexpr int I = decltype(ic)::value;
+                constexpr int J = opposite_dir<L, I>();
                 const Src s = source<L, I>(opaque_v(tile.x), opaque_v(tile.y), z, nx, ny, nz, c.symm);
-                const size_t si = ((size_t)s.sz * ny + s.sy) * px + s.sx;
-                const T dj = (T)Codec<S>::dec(gin[(size_t)s.j * np + si]);
+                T dj;
+                if (s.sx == tile.x && s.sy == tile.y && s.sz == z) {
+                    dj = (T)Raw<S>::dec(pnl[J]);
+                } else {
+                    const size_t si = ((size_t)s.sz * ny + s.sy) * px + s.sx;
+                    dj = (T)Codec<S>::dec(gin[(size_t)s.j * np + si]);
+                }
                 const T dnl = (T)Raw<S>::dec(pnl[I]);
                 const int tsl = (s.sz + 3) % 3, tl = (s.sy - tile.y0 + 1) * G::HX + (s.sx - tile.x0 + 1);
                 const V4<T> ta = sta[tsl][tl], tb = stb[tsl][tl];

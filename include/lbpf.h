@@ -342,12 +342,15 @@ lbpf_status lbpf_autotune(lbpf_ctx* ctx, int32_t steps_per_candidate, double* be
 /* The autotuner with a persisted result, so that a configuration is timed
  * once per machine type.  cache_path names a text file with one line per
  * tuned configuration:
- *   lbpf-autotune-1 <gcnArchName> cu<CUs> q<lattice> qut<lattice_ut>
- *     s<storage> <nx>x<ny>x<nz> pin<0|1>  <k_phi: tx ty zslab remap>
- *     <k_ut: tx ty zslab remap> <ms per step>
- * where pin = 1 when k_ut runs one of its variants (advection, skip_U or
- * skip_theta).  If a line's key matches this context (device architecture
- * and CU count, lattices, storage, domain size, pin), its launches are set
+ *   lbpf-autotune-2 k<kernel build> <gcnArchName> cu<CUs> q<lattice>
+ *     qut<lattice_ut> s<storage> <nx>x<ny>x<nz> pin<0|1>
+ *     <k_phi: tx ty zslab remap> <k_ut: tx ty zslab remap> <ms per step>
+ * where the kernel build is a digest of the kernel sources the library was
+ * compiled from (so launches tuned for other kernels are not reused) and
+ * pin = 1 when k_ut runs one of its variants (advection, skip_U or
+ * skip_theta).  If a line's key matches this context (kernel build, device
+ * architecture and CU count, lattices, storage, domain size, pin), its
+ * launches are set
  * without any timing and *hit = 1; *best_ms_per_step receives the stored
  * time.  Otherwise lbpf_autotune runs, its result is appended to the file
  * (created if missing) and *hit = 0.  Lines that do not parse or name a

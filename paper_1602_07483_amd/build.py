@@ -8,6 +8,7 @@ objects are linked into one library.
 Usage: python -m paper_1602_07483_amd.build
 """
 import concurrent.futures
+import hashlib
 import os
 import subprocess
 import sys
@@ -32,9 +33,21 @@ LATTICES = (7, 15, 19)
 STORAGES = (0, 1, 2, 3)      # lbpf_storage: F32, F16_DEV, BF16_DEV, F64
 
 
+def kernel_build_id() -> str:
+    """Digest of the kernel sources (every file under csrc/), 16 hex digits:
+    persisted autotuner results are keyed by it."""
+    h = hashlib.sha256()
+    for name in sorted(os.listdir(CSRC)):
+        if name.endswith((".hpp", ".hip")):
+            h.update(name.encode())
+            with open(os.path.join(CSRC, name), "rb") as f:
+                h.update(f.read())
+    return h.hexdigest()[:16]
+
+
 def units():
     """(object name, source, extra flags) of every translation unit."""
-    out = [("lbpf.o", os.path.join(CSRC, "lbpf.hip"), [])]
+    out = [("lbpf.o", os.path.join(CSRC, "lbpf.hip"), ['-DLBPF_KERNEL_BUILD="%s"' % kernel_build_id()])]
     for q in LATTICES:
         for st in STORAGES:
             out.append(("step_q%d_s%d.o" % (q, st), os.path.join(CSRC, "step.hip"),

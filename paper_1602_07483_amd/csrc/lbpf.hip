@@ -11,6 +11,12 @@
 
 #include <mutex>
 
+// Digest of the kernel sources this library was compiled from (set by the
+// build); part of the key of persisted autotuner results.
+#ifndef LBPF_KERNEL_BUILD
+#define LBPF_KERNEL_BUILD "unknown"
+#endif
+
 // The library's two non-template kernels, defined in this translation unit
 // only (the step translation units include kernels.hpp too).
 namespace lbpf {
@@ -1027,8 +1033,8 @@ lbpf_status lbpf_autotune_cached(lbpf_ctx* ctx, int32_t steps_per_candidate, con
     for (char* a = arch; *a; ++a)
         if (*a == ' ' || *a == '\t') *a = '_';
     char key[512];
-    std::snprintf(key, sizeof(key), "lbpf-autotune-1 %s cu%d q%d qut%d s%d %dx%dx%d pin%d", arch,
-                  prop.multiProcessorCount, ctx->q, ctx->q_ut, ctx->storage, ctx->grid.nx, ctx->grid.ny,
+    std::snprintf(key, sizeof(key), "lbpf-autotune-2 k%s %s cu%d q%d qut%d s%d %dx%dx%d pin%d", LBPF_KERNEL_BUILD,
+                  arch, prop.multiProcessorCount, ctx->q, ctx->q_ut, ctx->storage, ctx->grid.nx, ctx->grid.ny,
                   ctx->grid.nz, ut_pinned(ctx) ? 1 : 0);
     const size_t klen = std::strlen(key);
     if (FILE* in = std::fopen(cache_path, "r")) {

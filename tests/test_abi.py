@@ -159,3 +159,15 @@ def test_struct_layout_matches_header(struct, tmp_path):
     assert int(got["size"]) == ctypes.sizeof(struct)
     for fname, _ in struct._fields_:
         assert int(got[fname]) == getattr(struct, fname).offset, fname
+
+
+def test_kernel_build_id_is_a_stable_digest_of_the_kernel_sources():
+    """The build passes a digest of the kernel sources to the host runtime,
+    which keys persisted autotuner results by it: 16 hex digits, the same
+    on every call for the same sources."""
+    from paper_1602_07483_amd.build import kernel_build_id, units
+    k = kernel_build_id()
+    assert len(k) == 16 and all(ch in "0123456789abcdef" for ch in k)
+    assert kernel_build_id() == k
+    lbpf_unit = [u for u in units() if u[0] == "lbpf.o"][0]
+    assert '-DLBPF_KERNEL_BUILD="%s"' % k in lbpf_unit[2]

@@ -8,6 +8,7 @@ import pytest
 
 from oracle import Oracle, R_SOLID, R_MASS, R_ENTHALPY, R_TIPX, R_TIPY, R_TIPZ
 from paper_1602_07483_amd import lbpf
+from paper_1602_07483_amd.build import kernel_build_id
 from paper_1602_07483_amd.inputs import workload_interior, Problem, workload_small, workload_octant, NOFLUX, SYMMETRY, DT
 from tests.pairs import make_oracle, make_gpu, maxabs
 
@@ -419,20 +420,26 @@ def test_autotune_cache(tmp_path):
     """lbpf_autotune_cached: the first call tunes and appends one line, a
     second context of the same configuration takes its launches from that
     line without timing (and steps to the same fields as the tuned one), a
-    line that does not parse or names a refused launch is skipped, and
-    another domain size is a miss of its own."""
+    line that does not parse, names a refused launch or was tuned for other
+    kernel sources is skipped, and another domain size is a miss of its
+    own."""
     cache = str(tmp_path / "tune.txt")
     pb = ragged()
     a = make_gpu(pb, "f32")
     la, best_a, hit = a.autotune_cached(cache, 1)
     assert not hit and best_a > 0
     lines = open(cache).read().splitlines()
-    assert len(lines) == 1 and lines[0].startswith("lbpf-autotune-1 ") and " q19 qut19 s0 45x23x21 pin0 " in lines[0]
+    prefix = "lbpf-autotune-2 k%s " % kernel_build_id()
+    assert len(lines) == 1 and lines[0].startswith(prefix) and " q19 qut19 s0 45x23x21 pin0 " in lines[0]
     key = lines[0].split(" pin0 ")[0] + " pin0"
-    # a garbled line and a refused launch (a 48x8 tile) ahead of the good one
+    # a launch the library accepts, but keyed by another kernel build
+    other = (32, 16, 8, 0) if tuple(la["k_phi"]) != (32, 16, 8, 0) else (64, 2, 4, 0)
+    stale = key.replace(prefix, "lbpf-autotune-2 k0123456789abcdef ") + " %d %d %d %d %d %d %d %d 0.5" % (other + other)
+    # a garbled line, a refused launch (a 48x8 tile) and the stale line ahead of the good one
     with open(cache, "w") as fh:
         fh.write(key + " 1 2 3\n")
         fh.write(key + " 48 8 6 1 64 4 6 0 0.5\n")
+        fh.write(stale + "\n")
         fh.write(lines[0] + "\n")
     b = make_gpu(pb, "f32")
     lb, best_b, hit = b.autotune_cached(cache, 1)
@@ -444,7 +451,7 @@ def test_autotune_cache(tmp_path):
     c = make_gpu(ragged(n=(37, 21, 19)), "f32")
     _, _, hit = c.autotune_cached(cache, 1)
     assert not hit
-    assert len(open(cache).read().splitlines()) == 4
+    assert len(open(cache).read().splitlines()) == 5
 
 
 def _mixed_lattice_batch():
